@@ -1,0 +1,312 @@
+"""CPU oracle for the event-driven / JIT-connectivity synaptic propagation path.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke()``
+and by the CPU-baseline leg of ``bench.py``; never by the GPU library or its
+Python binding.  All arithmetic lives in ``oracle.c`` / ``snn.c`` (plain C
+loops, FP64 unless stated); this module only marshals numpy arrays.
+
+parity unpinned: the exact output bits of the Philox-4x32-10 generator (no
+published known-answer vector is reproduced; the pins are statistical).
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+STREAM_CONN, STREAM_W, STREAM_V0 = 1, 2, 3
+W_HOMO, W_NORMAL, W_UNIFORM = 0, 1, 2
+COBA, CUBA = 0, 1
+CONN_CSR, CONN_JIT = 0, 1
+
+_i32p = np.ctypeslib.ndpointer(np.int32, flags="C")
+_u32p = np.ctypeslib.ndpointer(np.uint32, flags="C")
+_u8p = np.ctypeslib.ndpointer(np.uint8, flags="C")
+_f32p = np.ctypeslib.ndpointer(np.float32, flags="C")
+_f64p = np.ctypeslib.ndpointer(np.float64, flags="C")
+_i64p = np.ctypeslib.ndpointer(np.int64, flags="C")
+
+
+class NetParams(C.Structure):
+    _fields_ = [("model", C.c_int32), ("n", C.c_int32), ("n_exc", C.c_int32),
+                ("conn", C.c_int32), ("max_gap", C.c_int32), ("block", C.c_int32),
+                ("seed", C.c_uint64),
+                ("w_exc", C.c_float), ("w_inh", C.c_float),
+                ("tau_m", C.c_float), ("tau_e", C.c_float), ("tau_i", C.c_float), ("tau_ref", C.c_float),
+                ("v_rest", C.c_float), ("v_th", C.c_float), ("v_reset", C.c_float),
+                ("e_exc", C.c_float), ("e_inh", C.c_float), ("r", C.c_float), ("i_ext", C.c_float),
+                ("dt", C.c_float), ("v0_lo", C.c_float), ("v0_hi", C.c_float)]
+
+
+class SnnParams(C.Structure):
+    _fields_ = [("B", C.c_int32), ("C", C.c_int32), ("N", C.c_int32), ("O", C.c_int32), ("T", C.c_int32),
+                ("surrogate", C.c_int32), ("smooth", C.c_int32), ("detach_reset", C.c_int32),
+                ("alpha", C.c_double), ("beta", C.c_double), ("theta", C.c_double),
+                ("slope", C.c_double), ("relu_a", C.c_double), ("relu_width", C.c_double)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        if not os.path.exists(path):
+            _build.build()
+        L = C.CDLL(path)
+        L.or_hash.restype = C.c_uint32
+        L.or_hash.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]
+        L.or_hash_many.argtypes = [C.c_uint64, C.c_uint32, _u32p, _u32p, _u32p, _u32p, C.c_int64]
+        L.or_philox.argtypes = [_u32p, C.c_uint32, C.c_uint32, _u32p]
+        L.or_philox_many.argtypes = [_u32p, _u32p, _u32p, C.c_int64]
+        L.or_max_gap.restype = C.c_int32
+        L.or_max_gap.argtypes = [C.c_double]
+        L.or_row_block.restype = C.c_int64
+        L.or_row_block.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p]
+        L.or_row.restype = C.c_int64
+        L.or_row.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p]
+        L.or_csr_count.restype = C.c_int64
+        L.or_csr_count.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p]
+        L.or_csr_build.restype = C.c_int64
+        L.or_csr_build.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _i32p, _i32p, C.c_int64]
+        L.or_compact.restype = C.c_int32
+        L.or_compact.argtypes = [_u8p, C.c_int32, _i32p]
+        L.or_event_csr_matvec.argtypes = [_i32p, _i32p, C.c_void_p, C.c_double, C.c_int32, C.c_int32, _u8p, _f64p]
+        L.or_event_csr_counts.argtypes = [_i32p, _i32p, C.c_int32, C.c_int32, _u8p, _i64p]
+        L.or_event_csr_vjp.argtypes = [_i32p, _i32p, C.c_void_p, C.c_double, C.c_int32, C.c_int32, _u8p, _f64p,
+                                       C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_jit_weight.restype = C.c_double
+        L.or_jit_weight.argtypes = [C.c_uint64, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_int32,
+                                    C.c_int64, C.c_void_p]
+        L.or_jit_matvec.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                    C.c_int32, C.c_int32, _u8p, _f64p]
+        L.or_jit_counts.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _u8p, _i64p]
+        L.or_jit_vjp.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                 C.c_int32, C.c_int32, _u8p, _f64p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_net_v0.argtypes = [C.POINTER(NetParams), _f32p]
+        L.or_net_ref_steps.restype = C.c_int32
+        L.or_net_ref_steps.argtypes = [C.POINTER(NetParams)]
+        L.or_net_run_f32.argtypes = [C.POINTER(NetParams), C.c_void_p, C.c_void_p, C.c_int32,
+                                     _f32p, _f32p, _f32p, _i32p, _u8p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]
+        L.or_net_run_f64.argtypes = [C.POINTER(NetParams), C.c_void_p, C.c_void_p, C.c_int32,
+                                     _f64p, _f64p, _f64p, _i32p, _u8p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]
+        L.or_snn_grad.restype = C.c_int
+        L.or_snn_grad.argtypes = [C.POINTER(SnnParams), _u8p, _i32p, _f64p, _i32p, _i32p, _f64p, _f64p, _f64p,
+                                  C.c_void_p, C.POINTER(C.c_double), _f64p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+# ---------------------------------------------------------------- hash / K
+def hash_word(seed, stream, a, b, k):
+    return int(lib().or_hash(seed, stream, a, b, k))
+
+
+def hash_many(seed, stream, a, b, k):
+    a = np.ascontiguousarray(a, np.uint32)
+    b = np.ascontiguousarray(b, np.uint32)
+    k = np.ascontiguousarray(k, np.uint32)
+    out = np.empty(a.shape[0], np.uint32)
+    lib().or_hash_many(seed, stream, a, b, k, out, a.shape[0])
+    return out
+
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, np.uint32)
+    out = np.empty(4, np.uint32)
+    lib().or_philox(c, int(key[0]), int(key[1]), out)
+    return out
+
+
+def philox_many(ctr, key):
+    c = np.ascontiguousarray(ctr, np.uint32).reshape(-1, 4)
+    k = np.ascontiguousarray(key, np.uint32).reshape(-1, 2)
+    out = np.empty_like(c)
+    lib().or_philox_many(c, k, out, c.shape[0])
+    return out
+
+
+def max_gap(p):
+    return int(lib().or_max_gap(float(p)))
+
+
+# ---------------------------------------------------------------- rows / CSR
+def row_block(seed, K, n_post, B, j, b):
+    n = lib().or_row_block(seed, K, n_post, B, j, b, None)
+    out = np.empty(max(n, 1), np.int32)
+    lib().or_row_block(seed, K, n_post, B, j, b, _ptr(out))
+    return out[:n]
+
+
+def row(seed, K, n_post, B, j):
+    n = lib().or_row(seed, K, n_post, B, j, None)
+    out = np.empty(max(n, 1), np.int32)
+    lib().or_row(seed, K, n_post, B, j, _ptr(out))
+    return out[:n]
+
+
+def csr_build(seed, K, n_pre, n_post, B):
+    rowlen = np.empty(max(n_pre, 1), np.int32)
+    nnz = lib().or_csr_count(seed, K, n_pre, n_post, B, _ptr(rowlen))
+    indptr = np.empty(n_pre + 1, np.int32)
+    indices = np.empty(max(nnz, 1), np.int32)
+    got = lib().or_csr_build(seed, K, n_pre, n_post, B, indptr, indices, nnz)
+    assert got == nnz
+    return indptr, indices[:nnz]
+
+
+def compact(s):
+    s = np.ascontiguousarray(s, np.uint8)
+    ids = np.empty(max(s.shape[0], 1), np.int32)
+    c = lib().or_compact(s, s.shape[0], ids)
+    return ids[:c]
+
+
+# ---------------------------------------------------------------- matvecs
+def event_csr_matvec(indptr, indices, data, w, n_post, events):
+    ev = np.ascontiguousarray(events, np.uint8)
+    y = np.empty(n_post, np.float64)
+    d = None if data is None else np.ascontiguousarray(data, np.float32)
+    lib().or_event_csr_matvec(np.ascontiguousarray(indptr, np.int32), np.ascontiguousarray(indices, np.int32),
+                              _ptr(d), float(w), ev.shape[0], n_post, ev, y)
+    return y
+
+
+def event_csr_counts(indptr, indices, n_post, events):
+    ev = np.ascontiguousarray(events, np.uint8)
+    cnt = np.empty(n_post, np.int64)
+    lib().or_event_csr_counts(np.ascontiguousarray(indptr, np.int32), np.ascontiguousarray(indices, np.int32),
+                              ev.shape[0], n_post, ev, cnt)
+    return cnt
+
+
+def event_csr_vjp(indptr, indices, data, w, n_post, events, dy):
+    ev = np.ascontiguousarray(events, np.uint8)
+    n_pre = ev.shape[0]
+    nnz = int(indptr[-1])
+    d = None if data is None else np.ascontiguousarray(data, np.float32)
+    d_ev = np.empty(n_pre, np.float64)
+    d_data = np.empty(max(nnz, 1), np.float64)
+    d_w = np.zeros(1, np.float64)
+    lib().or_event_csr_vjp(np.ascontiguousarray(indptr, np.int32), np.ascontiguousarray(indices, np.int32),
+                           _ptr(d), float(w), n_pre, n_post, ev, np.ascontiguousarray(dy, np.float64),
+                           _ptr(d_ev), _ptr(d_data), _ptr(d_w))
+    return d_ev, d_data[:nnz], float(d_w[0])
+
+
+def jit_weight(seed, wkind, w0, w1, j, b, m):
+    u = C.c_double(0.0)
+    w = lib().or_jit_weight(seed, wkind, w0, w1, j, b, m, C.byref(u))
+    return w, u.value
+
+
+def jit_matvec(seed, K, B, wkind, w0, w1, n_post, events):
+    ev = np.ascontiguousarray(events, np.uint8)
+    y = np.empty(n_post, np.float64)
+    lib().or_jit_matvec(seed, K, B, wkind, float(w0), float(w1), ev.shape[0], n_post, ev, y)
+    return y
+
+
+def jit_counts(seed, K, B, n_post, events):
+    ev = np.ascontiguousarray(events, np.uint8)
+    cnt = np.empty(n_post, np.int64)
+    lib().or_jit_counts(seed, K, B, ev.shape[0], n_post, ev, cnt)
+    return cnt
+
+
+def jit_vjp(seed, K, B, wkind, w0, w1, n_post, events, dy):
+    ev = np.ascontiguousarray(events, np.uint8)
+    d_ev = np.empty(ev.shape[0], np.float64)
+    g0 = np.zeros(1, np.float64)
+    g1 = np.zeros(1, np.float64)
+    lib().or_jit_vjp(seed, K, B, wkind, float(w0), float(w1), ev.shape[0], n_post, ev,
+                     np.ascontiguousarray(dy, np.float64), _ptr(d_ev), _ptr(g0), _ptr(g1))
+    return d_ev, float(g0[0]), float(g1[0])
+
+
+# ---------------------------------------------------------------- network
+def net_params(**kw):
+    """NetParams from keyword arguments (names as in the struct)."""
+    p = NetParams()
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def net_v0(P):
+    V = np.empty(P.n, np.float32)
+    lib().or_net_v0(C.byref(P), V)
+    return V
+
+
+def net_ref_steps(P):
+    return int(lib().or_net_ref_steps(C.byref(P)))
+
+
+class NetState:
+    """FP32 (default) or FP64 network state in host arrays."""
+
+    def __init__(self, P, precision=32):
+        self.precision = precision
+        dt = np.float32 if precision == 32 else np.float64
+        self.V = net_v0(P).astype(dt)
+        self.ge = np.zeros(P.n, dt)
+        self.gi = np.zeros(P.n, dt)
+        self.ref = np.zeros(P.n, np.int32)
+        self.s_prev = np.zeros(P.n, np.uint8)
+        self.t = 0
+
+
+def net_run(P, state, T, indptr=None, indices=None, iext_vec=None, want_raster=True):
+    raster = np.empty((T, P.n), np.uint8) if want_raster else None
+    counts = np.empty(T, np.int32)
+    events = np.zeros(1, np.int64)
+    ip = None if indptr is None else np.ascontiguousarray(indptr, np.int32)
+    ix = None if indices is None else np.ascontiguousarray(indices, np.int32)
+    if state.precision == 32:
+        iv = None if iext_vec is None else np.ascontiguousarray(iext_vec, np.float32)
+        fn = lib().or_net_run_f32
+    else:
+        iv = None if iext_vec is None else np.ascontiguousarray(iext_vec, np.float64)
+        fn = lib().or_net_run_f64
+    fn(C.byref(P), _ptr(ip), _ptr(ix), T, state.V, state.ge, state.gi, state.ref, state.s_prev,
+       _ptr(iv), _ptr(raster), _ptr(counts), _ptr(events))
+    state.t += T
+    return raster, counts, int(events[0])
+
+
+# ---------------------------------------------------------------- SNN
+def snn_params(B, C_, N, O, T, alpha, beta, theta=1.0, slope=4.0, surrogate=0, smooth=0, detach_reset=1,
+               relu_a=0.3, relu_width=1.0):
+    return SnnParams(B, C_, N, O, T, surrogate, smooth, detach_reset, alpha, beta, theta, slope, relu_a,
+                     relu_width)
+
+
+def snn_grad(P, x, labels, W_in, indptr, indices, w_rec, W_out, b_out, z_force=None, want_z=False):
+    B, N, O, T, Cc = P.B, P.N, P.O, P.T, P.C
+    loss = C.c_double(0.0)
+    logits = np.empty((B, O), np.float64)
+    z_out = np.empty((T, B, N), np.uint8) if want_z else None
+    dW_in = np.empty((Cc, N), np.float64)
+    nnz = int(indptr[-1])
+    dw_rec = np.empty(max(nnz, 1), np.float64)
+    dW_out = np.empty((N, O), np.float64)
+    db_out = np.empty(O, np.float64)
+    zf = None if z_force is None else np.ascontiguousarray(z_force, np.uint8)
+    rc = lib().or_snn_grad(C.byref(P), np.ascontiguousarray(x, np.uint8), np.ascontiguousarray(labels, np.int32),
+                           np.ascontiguousarray(W_in, np.float64), np.ascontiguousarray(indptr, np.int32),
+                           np.ascontiguousarray(indices, np.int32), np.ascontiguousarray(w_rec, np.float64),
+                           np.ascontiguousarray(W_out, np.float64), np.ascontiguousarray(b_out, np.float64),
+                           _ptr(zf), C.byref(loss), logits, _ptr(z_out), _ptr(dW_in), _ptr(dw_rec),
+                           _ptr(dW_out), _ptr(db_out))
+    assert rc == 0
+    return dict(loss=loss.value, logits=logits, z=z_out, dW_in=dW_in, dw_rec=dw_rec[:nnz], dW_out=dW_out,
+                db_out=db_out)

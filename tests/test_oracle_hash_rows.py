@@ -1,0 +1,237 @@
+"""Pins for the oracle's random source, maximum gap, row generator and CSR
+build (CPU only).  Each test checks the oracle against something other than
+itself: the paper's stated values and expectations, closed forms, exact
+probabilities, library statistics, or invariants."""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle as O
+
+
+# ----------------------------------------------------------------- Philox
+def test_philox_is_a_bijection_on_distinct_counters():
+    # For a fixed key every Philox round is invertible, so distinct counters
+    # never collide.  A dropped or mis-mixed word typically breaks this.
+    n = 1 << 17
+    rng = np.random.default_rng(1)
+    ctr = np.zeros((n, 4), np.uint32)
+    ctr[:, 0] = np.arange(n)  # distinct in word 0, the rest small / random
+    ctr[:, 1] = rng.integers(0, 4, n)
+    ctr[:, 3] = 1
+    key = np.tile(np.array([12345, 678], np.uint32), (n, 1))
+    out = O.philox_many(ctr, key)
+    as_bytes = out.view(np.dtype((np.void, 16)))
+    assert np.unique(as_bytes).size == n
+
+
+def _popcount32(x):
+    x = x.astype(np.uint64)
+    c = np.zeros_like(x)
+    for _ in range(32):
+        c += x & 1
+        x >>= 1
+    return c
+
+
+def test_philox_avalanche():
+    # Flipping any single input bit (128 counter bits, 64 key bits) flips each
+    # of the 128 output bits with probability 1/2: the mean number of flipped
+    # output bits is 64 with sd 5.66/sqrt(n) per input bit.  Too few rounds,
+    # a missing key bump or a wrong multiplier shows up as a biased mean.
+    n = 2048
+    rng = np.random.default_rng(2)
+    ctr = rng.integers(0, 2**32, (n, 4), dtype=np.uint64).astype(np.uint32)
+    key = rng.integers(0, 2**32, (n, 2), dtype=np.uint64).astype(np.uint32)
+    base = O.philox_many(ctr, key)
+    for word in range(6):
+        for bit in range(32):
+            c2, k2 = ctr.copy(), key.copy()
+            if word < 4:
+                c2[:, word] ^= np.uint32(1 << bit)
+            else:
+                k2[:, word - 4] ^= np.uint32(1 << bit)
+            out = O.philox_many(c2, k2)
+            flips = sum(_popcount32(out[:, w] ^ base[:, w]) for w in range(4))
+            m = flips.mean()
+            assert abs(m - 64.0) < 0.8, (word, bit, m)
+
+
+def test_hash_words_uniform_chi2():
+    n = 1 << 20
+    a = np.arange(n, dtype=np.uint32) // 64
+    b = np.zeros(n, np.uint32)
+    k = np.arange(n, dtype=np.uint32) % 64
+    w = O.hash_many(7, O.STREAM_CONN, a, b, k)
+    for shift in (24, 0, 12):
+        h = np.bincount(((w >> shift) & 255).astype(np.int64), minlength=256)
+        chi2, p = stats.chisquare(h)
+        assert p > 1e-4, (shift, p)
+
+
+def test_hash_consecutive_words_uncorrelated():
+    n = 1 << 18
+    a = np.full(n, 3, np.uint32)
+    b = np.zeros(n, np.uint32)
+    k = np.arange(n, dtype=np.uint32)
+    u = O.hash_many(11, O.STREAM_CONN, a, b, k).astype(np.float64) / 2**32
+    r = np.corrcoef(u[:-1], u[1:])[0, 1]
+    assert abs(r) < 5 / math.sqrt(n)
+    # the mean of U[0,1) is 1/2 with sd 1/sqrt(12 n)
+    assert abs(u.mean() - 0.5) < 5 / math.sqrt(12 * n)
+
+
+def test_hash_interface_selects_philox_words():
+    # H(seed, stream, a, b, k) is word k mod 4 of Philox(counter=(a, b, k//4, stream),
+    # key=(seed lo, seed hi)).
+    seed = (0xDEADBEEF << 32) | 0x01234567
+    for (a, b, k, s) in [(0, 0, 0, 1), (5, 7, 9, 2), (2**31, 3, 123457, 3)]:
+        words = O.philox([a, b, k >> 2, s], [seed & 0xFFFFFFFF, seed >> 32])
+        assert O.hash_word(seed, s, a, b, k) == int(words[k & 3])
+
+
+def test_streams_and_seeds_differ():
+    w1 = O.hash_word(0, 1, 0, 0, 0)
+    assert w1 != O.hash_word(0, 2, 0, 0, 0)
+    assert w1 != O.hash_word(1, 1, 0, 0, 0)
+    assert w1 != O.hash_word(1 << 32, 1, 0, 0, 0)
+
+
+# ----------------------------------------------------------------- K
+@pytest.mark.parametrize("p,K", [(0.02, 99), (0.01, 199), (2e-4, 9999), (0.1, 19), (1.0, 1),
+                                 (80 / 4000, 99), (80 / 400000, 9999), (0.5, 3), (0.9, 1)])
+def test_max_gap_values(p, K):
+    # Appendix C: K = floor(2/p - 1); uniform gaps on [1, K] have mean 1/p
+    # exactly when 2/p - 1 is an integer.
+    assert O.max_gap(p) == K
+
+
+def test_max_gap_mean_gap_is_inverse_p():
+    for p in (0.02, 0.01, 2e-4, 0.1):
+        K = O.max_gap(p)
+        assert (K + 1) / 2 == pytest.approx(1 / p, rel=1e-12)
+
+
+def test_max_gap_rejects_bad_p():
+    assert O.max_gap(0.0) == -1 and O.max_gap(-0.1) == -1 and O.max_gap(1.5) == -1
+
+
+def test_max_gap_floor_when_not_integer():
+    # 2/p - 1 = 307.625 for p = 80/12345: the text's floor gives 307
+    assert O.max_gap(80 / 12345) == 307
+
+
+# ----------------------------------------------------------------- rows
+def test_row_paper_mode_gaps_uniform_on_1_K():
+    K, n_post = 19, 2_000_000
+    rows = [O.row(3, K, n_post, 0, j) for j in range(20)]
+    gaps = np.concatenate([np.diff(r) for r in rows])
+    assert gaps.min() >= 1 and gaps.max() <= K
+    h = np.bincount(gaps, minlength=K + 1)[1:]
+    _, p = stats.chisquare(h)
+    assert p > 1e-4
+    # first position: one gap minus one, uniform on {0..K-1}
+    firsts = np.array([O.row(3, K, 1000, 0, j)[0] for j in range(20000)])
+    h0 = np.bincount(firsts, minlength=K)
+    assert h0.size == K
+    _, p0 = stats.chisquare(h0)
+    assert p0 > 1e-4
+
+
+def test_row_paper_mode_follows_listing():
+    # Appendix C listing (0-based first target, one counter stream per row):
+    # pos = gap - 1; while pos < n: emit; pos += gap.  Draw i is H(seed, CONN, j, 0, i).
+    seed, K, n_post = 99, 49, 3000
+    for j in (0, 1, 17, 2999):
+        out, i = [], 0
+        pos = 1 + (O.hash_word(seed, O.STREAM_CONN, j, 0, i) * K >> 32) - 1
+        while pos < n_post:
+            out.append(pos)
+            i += 1
+            pos += 1 + (O.hash_word(seed, O.STREAM_CONN, j, 0, i) * K >> 32)
+        assert np.array_equal(O.row(seed, K, n_post, 0, j), np.array(out, np.int32))
+
+
+def test_row_density_equals_p():
+    # mean row length = n_post * 2/(K+1) = p n_post (paper: the sampler has
+    # connection probability p); checked for p = 0.02 (configs' E/I net).
+    K, n_post, n = 99, 4000, 4000
+    lens = np.array([len(O.row(0, K, n_post, 0, j)) for j in range(n)])
+    mu = n_post * 2 / (K + 1)
+    # row length variance of a renewal count ~ n_post var(G)/E[G]^3
+    varg = (K * K - 1) / 12
+    sd = math.sqrt(n_post * varg / ((K + 1) / 2) ** 3)
+    assert abs(lens.mean() - mu) < 5 * sd / math.sqrt(n) + 0.6  # +0.6: start effect of paper mode
+
+
+@pytest.mark.parametrize("K,B", [(99, 40), (99, 256), (9999, 1024), (19, 7)])
+def test_block_mode_is_stationary(K, B):
+    # With a stationary first point every block has exactly B*2/(K+1) expected
+    # targets, and each offset inside a block is a target with probability 2/(K+1).
+    n_post = B * 8
+    rng_rows = range(60000 if K > 1000 else 6000)
+    cnt = np.zeros(B, np.int64)
+    total = 0
+    nblk = 0
+    for j in rng_rows:
+        r = O.row(5, K, n_post, B, j)
+        np.add.at(cnt, r % B, 1)
+        total += r.size
+        nblk += 8
+    p = 2 / (K + 1)
+    mean_per_block = total / nblk
+    # counts per block have variance <= B p (Bernoulli bound for a renewal with gaps >= 1)
+    assert abs(mean_per_block - B * p) < 5 * math.sqrt(B * p / nblk) + 1e-9
+    _, pv = stats.chisquare(cnt)
+    assert pv > 1e-4
+
+
+def test_block_first_point_distribution():
+    # P(R >= r) = (K-r)(K-r+1)/(K(K+1)): the forward recurrence time of a
+    # stationary renewal process with gaps uniform on [1, K].
+    K, B = 9, 1000
+    firsts = []
+    for j in range(40000):
+        r = O.row_block(1, K, 1000, B, j, 0)
+        firsts.append(r[0])
+    h = np.bincount(np.array(firsts), minlength=K)[:K]
+    r = np.arange(K)
+    pr = ((K - r) * (K - r + 1) - (K - r - 1) * (K - r)) / (K * (K + 1))
+    assert pr.sum() == pytest.approx(1.0)
+    _, pv = stats.chisquare(h, pr * h.sum())
+    assert pv > 1e-4
+
+
+def test_rows_sorted_in_range_and_order_independent():
+    K, n_post = 7, 5000
+    for B in (0, 64, 333):
+        first = {j: O.row(42, K, n_post, B, j) for j in range(50)}
+        for j in reversed(range(50)):
+            r = O.row(42, K, n_post, B, j)
+            assert np.array_equal(r, first[j])
+            assert np.all(np.diff(r) > 0) and r.min() >= 0 and r.max() < n_post
+
+
+def test_dense_limit_k1():
+    # p = 1 gives K = 1: every position is a target (block mode too).
+    for B in (0, 16):
+        assert np.array_equal(O.row(0, 1, 100, B, 3), np.arange(100, dtype=np.int32))
+
+
+def test_csr_build_matches_rows():
+    seed, K, n_pre, n_post = 8, 49, 300, 700
+    for B in (0, 128):
+        ip, ix = O.csr_build(seed, K, n_pre, n_post, B)
+        assert ip[0] == 0 and ip.size == n_pre + 1
+        for j in range(n_pre):
+            assert np.array_equal(ix[ip[j]:ip[j + 1]], O.row(seed, K, n_post, B, j))
+
+
+def test_compaction_is_ascending_nonzero_set():
+    rng = np.random.default_rng(0)
+    for frac in (0.0, 0.01, 0.5, 1.0):
+        s = (rng.random(10007) < frac).astype(np.uint8)
+        assert np.array_equal(O.compact(s), np.flatnonzero(s).astype(np.int32))
+    assert O.compact(np.zeros(0, np.uint8)).size == 0

@@ -1,0 +1,166 @@
+"""Pins for the oracle's event-driven CSR matvec, JIT matvec and their
+reverse modes (CPU only): dense brute force over every event vector of tiny
+matrices, a library sparse product, exact special cases, exact finite
+differences of the (linear) operators, and distribution tests of the JIT
+weights."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy import stats
+
+import oracle as O
+import synthetic as S
+
+
+def _random_csr(rng, n_pre, n_post, dens, dup=True):
+    indptr = [0]
+    idx = []
+    for _ in range(n_pre):
+        m = rng.binomial(n_post, dens)
+        cols = list(rng.integers(0, n_post, m)) if dup else sorted(rng.choice(n_post, m, replace=False))
+        idx += cols
+        indptr.append(len(idx))
+    return np.array(indptr, np.int32), np.array(idx, np.int32)
+
+
+def _dense(indptr, indices, data, w, n_pre, n_post):
+    D = np.zeros((n_pre, n_post))
+    for j in range(n_pre):
+        for idx in range(indptr[j], indptr[j + 1]):
+            D[j, indices[idx]] += data[idx] if data is not None else w
+    return D
+
+
+@pytest.mark.parametrize("hetero", [False, True])
+def test_event_csr_bruteforce_all_event_vectors(hetero):
+    # Appendix B defines y = M^T e over rows that fire; with duplicated and
+    # unsorted columns each entry adds.  All 2^8 event vectors.
+    rng = np.random.default_rng(3)
+    n_pre, n_post = 8, 13
+    ip, ix = _random_csr(rng, n_pre, n_post, 0.4, dup=True)
+    data = rng.standard_normal(ix.size).astype(np.float32) if hetero else None
+    w = 0.6
+    D = _dense(ip, ix, data, w, n_pre, n_post)
+    for bits in itertools.product([0, 1], repeat=n_pre):
+        e = np.array(bits, np.uint8)
+        y = O.event_csr_matvec(ip, ix, data, w, n_post, e)
+        np.testing.assert_allclose(y, D.T @ e, rtol=0, atol=1e-12)
+
+
+def test_event_csr_vs_scipy():
+    rng = np.random.default_rng(4)
+    n_pre, n_post = 3000, 2000
+    ip, ix = _random_csr(rng, n_pre, n_post, 0.01)
+    data = S.hetero_data(ix.size, 1)
+    e = S.events(n_pre, 0.1, 2)
+    M = sp.csr_matrix((data.astype(np.float64), ix, ip), shape=(n_pre, n_post))
+    y = O.event_csr_matvec(ip, ix, data, 0.0, n_post, e)
+    np.testing.assert_allclose(y, M.T @ (e != 0).astype(np.float64), rtol=1e-12, atol=1e-12)
+
+
+def test_event_csr_special_cases():
+    ip, ix = O.csr_build(1, 19, 500, 400, 0)
+    z = O.event_csr_matvec(ip, ix, None, 0.6, 400, np.zeros(500, np.uint8))
+    assert np.all(z == 0.0)
+    ones = O.event_csr_matvec(ip, ix, None, 0.6, 400, np.ones(500, np.uint8))
+    indeg = np.bincount(ix, minlength=400)
+    np.testing.assert_allclose(ones, 0.6 * indeg, rtol=1e-13)
+    e = S.events(500, 0.3, 5)
+    cnt = O.event_csr_counts(ip, ix, 400, e)
+    np.testing.assert_allclose(O.event_csr_matvec(ip, ix, None, 0.6, 400, e), 0.6 * cnt, rtol=1e-13)
+    # event values are truthiness: any non-zero byte is one event
+    e2 = e * np.uint8(7)
+    np.testing.assert_array_equal(O.event_csr_counts(ip, ix, 400, e2), cnt)
+
+
+@pytest.mark.parametrize("B", [0, 64])
+def test_jit_equals_csr_of_same_seed(B):
+    seed, K, n_pre, n_post = 77, 49, 700, 900
+    ip, ix = O.csr_build(seed, K, n_pre, n_post, B)
+    for frac in (0.0, 0.05, 1.0):
+        e = S.events(n_pre, frac, 9)
+        np.testing.assert_array_equal(O.jit_counts(seed, K, B, n_post, e), O.event_csr_counts(ip, ix, n_post, e))
+        y = O.jit_matvec(seed, K, B, O.W_HOMO, 6.7, 0.0, n_post, e)
+        np.testing.assert_allclose(y, 6.7 * O.event_csr_counts(ip, ix, n_post, e), rtol=1e-13)
+
+
+@pytest.mark.parametrize("wkind", [O.W_NORMAL, O.W_UNIFORM])
+def test_jit_weighted_bruteforce(wkind):
+    seed, K, n_pre, n_post, B = 5, 9, 40, 60, 16
+    w0, w1 = (0.5, 0.1) if wkind == O.W_NORMAL else (-1.0, 2.0)
+    D = np.zeros((n_pre, n_post))
+    nb = -(-n_post // B)
+    for j in range(n_pre):
+        for b in range(nb):
+            r = O.row_block(seed, K, n_post, B, j, b)
+            for m, k in enumerate(r):
+                D[j, k] += O.jit_weight(seed, wkind, w0, w1, j, b, m)[0]
+    e = S.events(n_pre, 0.5, 1)
+    y = O.jit_matvec(seed, K, B, wkind, w0, w1, n_post, e)
+    np.testing.assert_allclose(y, D.T @ e, rtol=1e-12, atol=1e-12)
+
+
+def test_jit_normal_weights_are_normal():
+    z = np.array([O.jit_weight(3, O.W_NORMAL, 0.0, 1.0, j, 0, m)[1] for j in range(400) for m in range(50)])
+    assert abs(z.mean()) < 5 / math.sqrt(z.size)
+    assert abs(z.var() - 1.0) < 5 * math.sqrt(2 / z.size)
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    w = np.array([O.jit_weight(3, O.W_NORMAL, 0.5, 0.1, j, 0, 7)[0] for j in range(2000)])
+    assert abs(w.mean() - 0.5) < 5 * 0.1 / math.sqrt(w.size)
+
+
+def test_jit_uniform_weights_are_uniform():
+    u = np.array([O.jit_weight(4, O.W_UNIFORM, 0.0, 1.0, j, 1, m)[0] for j in range(400) for m in range(50)])
+    assert stats.kstest(u, "uniform").pvalue > 1e-3
+    assert u.min() >= 0.0 and u.max() < 1.0
+
+
+# ----------------------------------------------------------------- reverse mode
+def test_event_csr_vjp_exact_differences():
+    # The operator is linear, so switching one row on changes L = dy . y by
+    # exactly d_ev[j]; moving one weight by h changes L by h e_j dy_k; moving
+    # w by h changes L by h d_w.
+    rng = np.random.default_rng(12)
+    n_pre, n_post = 60, 45
+    ip, ix = _random_csr(rng, n_pre, n_post, 0.2)
+    data = (rng.integers(-8, 8, ix.size) / 4).astype(np.float32)  # dyadic: exact sums
+    dy = (rng.integers(-8, 8, n_post) / 8).astype(np.float64)
+    e = S.events(n_pre, 0.4, 3)
+    d_ev, d_data, _ = O.event_csr_vjp(ip, ix, data, 0.0, n_post, e, dy)
+
+    def L(ev, dat, w=0.0):
+        return float(dy @ O.event_csr_matvec(ip, ix, dat, w, n_post, ev))
+
+    for j in range(n_pre):
+        on, off = e.copy(), e.copy()
+        on[j], off[j] = 1, 0
+        assert L(on, data) - L(off, data) == d_ev[j]
+    for idx in rng.choice(ix.size, 40, replace=False):
+        d2 = data.copy()
+        d2[idx] += np.float32(0.5)
+        assert (L(e, d2) - L(e, data)) / 0.5 == d_data[idx]
+    _, _, d_w = O.event_csr_vjp(ip, ix, None, 0.25, n_post, e, dy)
+    assert (L(e, None, 0.75) - L(e, None, 0.25)) / 0.5 == pytest.approx(d_w, abs=1e-12)
+
+
+@pytest.mark.parametrize("wkind,w0,w1", [(O.W_HOMO, 0.6, 0.0), (O.W_NORMAL, 0.5, 0.1), (O.W_UNIFORM, -0.5, 1.5)])
+def test_jit_vjp_differences(wkind, w0, w1):
+    seed, K, B, n_pre, n_post = 21, 9, 32, 50, 70
+    e = S.events(n_pre, 0.4, 2)
+    dy = S.cotangent(n_post, 1)
+    d_ev, g0, g1 = O.jit_vjp(seed, K, B, wkind, w0, w1, n_post, e, dy)
+
+    def L(ev, a, b):
+        return float(dy @ O.jit_matvec(seed, K, B, wkind, a, b, n_post, ev))
+
+    for j in range(n_pre):
+        on, off = e.copy(), e.copy()
+        on[j], off[j] = 1, 0
+        assert L(on, w0, w1) - L(off, w0, w1) == pytest.approx(d_ev[j], abs=1e-10)
+    h = 1e-3
+    assert (L(e, w0 + h, w1) - L(e, w0 - h, w1)) / (2 * h) == pytest.approx(g0, rel=1e-7, abs=1e-9)
+    if wkind != O.W_HOMO:
+        assert (L(e, w0, w1 + h) - L(e, w0, w1 - h)) / (2 * h) == pytest.approx(g1, rel=1e-7, abs=1e-9)
