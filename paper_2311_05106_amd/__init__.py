@@ -1,0 +1,261 @@
+"""MI355X (gfx950) event-driven spiking-network path: Python binding.
+
+Thin marshalling over the C ABI of ``libbpmi.so`` (include/bp.h).  Every
+step of the path runs in the HIP kernels; PyTorch only provides device
+memory and the current stream.  Importing this module does not touch the
+GPU; the first call loads the library and fails loudly if it is missing.
+"""
+import ctypes as C
+import math
+
+import torch
+
+from . import _abi
+from ._abi import (COBA, CONN_CSR, CONN_JIT, CUBA, STREAM_CONN, STREAM_V0, STREAM_W, W_HOMO, W_NORMAL,
+                   W_UNIFORM, BpError, check, lib)
+
+__all__ = [
+    "lib", "BpError", "max_gap", "hash_words", "csr_build", "csr_tile_index", "compact", "event_csr_matvec",
+    "jit_conn_matvec", "event_csr_backward", "jit_conn_backward", "Net", "run_batch", "JitConn",
+    "COBA", "CUBA", "CONN_CSR", "CONN_JIT", "W_HOMO", "W_NORMAL", "W_UNIFORM",
+]
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _p(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    return t.contiguous()
+
+
+def max_gap(p):
+    """K of the connectivity sampler (Appendix C), -1 for p outside (0, 1]."""
+    return int(lib().bp_max_gap(float(p)))
+
+
+def hash_words(seed, rng_stream, a, b, k):
+    a = _dev(a, torch.int32, "a")
+    b = _dev(b, torch.int32, "b")
+    k = _dev(k, torch.int32, "k")
+    out = torch.empty_like(a)
+    check(lib().bp_hash(seed, rng_stream, _p(a), _p(b), _p(k), _p(out), a.numel(), _stream()))
+    return out
+
+
+class JitConn:
+    """Fixed-probability connectivity regenerated from a seed."""
+
+    def __init__(self, n_pre, n_post, p=None, K=None, block=0, seed=0, wkind=W_HOMO, w0=1.0, w1=0.0):
+        if K is None:
+            K = max_gap(p)
+        if K < 1:
+            raise ValueError(f"invalid connection probability {p}")
+        self.c = _abi.JitConn(n_pre, n_post, K, block, seed, wkind, w0, w1)
+
+    def __getattr__(self, name):
+        return getattr(self.__dict__["c"], name)
+
+
+def csr_build(conn: JitConn, device="cuda"):
+    """(indptr, indices) int32 device tensors of the seeded matrix."""
+    c = conn.c
+    indptr = torch.empty(c.n_pre + 1, dtype=torch.int32, device=device)
+    check(lib().bp_csr_count(C.byref(c), _p(indptr), _stream()))
+    nnz = int(indptr[-1].item())
+    if nnz < 0:
+        raise BpError(_abi.BP_EUNSUPPORTED, "more than 2^31-1 synapses")
+    indices = torch.empty(max(nnz, 1), dtype=torch.int32, device=device)
+    check(lib().bp_csr_fill(C.byref(c), _p(indptr), _p(indices), _stream()))
+    return indptr, indices[:nnz]
+
+
+def csr_tile_index(indptr, indices, n_post, tile_width):
+    n_pre = indptr.numel() - 1
+    n_tiles = max(1, -(-n_post // tile_width))
+    tp = torch.empty(max(n_pre, 1) * (n_tiles + 1), dtype=torch.int32, device=indptr.device)
+    check(lib().bp_csr_tile_index(_p(indptr), _p(indices), n_pre, n_post, tile_width, _p(tp), _stream()))
+    return tp
+
+
+def compact(s):
+    s = _dev(s, torch.uint8, "s")
+    n = s.numel()
+    ids = torch.empty(max(n, 1), dtype=torch.int32, device=s.device)
+    count = torch.empty(1, dtype=torch.int32, device=s.device)
+    wsb = int(lib().bp_compact_ws_bytes(n))
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=s.device)
+    check(lib().bp_compact(_p(s), n, _p(ids), _p(count), _p(ws), wsb, _stream()))
+    return ids, count
+
+
+def _csr_struct(indptr, indices, data, w, n_post, tile_ptr=None, tile_width=0, sorted_rows=True):
+    n_pre = indptr.numel() - 1
+    return _abi.Csr(indptr.data_ptr(), indices.data_ptr() if indices.numel() else None,
+                    None if data is None else data.data_ptr(), float(w), n_pre, n_post, int(bool(sorted_rows)),
+                    None if tile_ptr is None else tile_ptr.data_ptr(), int(tile_width))
+
+
+def event_csr_matvec(indptr, indices, data, w, n_post, events, tile_ptr=None, tile_width=0, sorted_rows=True,
+                     out=None, ws=None):
+    """y = M^T e over the firing rows (Appendix B).  data None: homogeneous w."""
+    m = _csr_struct(indptr, indices, data, w, n_post, tile_ptr, tile_width, sorted_rows)
+    y = out if out is not None else torch.empty(n_post, dtype=torch.float32, device=events.device)
+    wsb = int(lib().bp_event_csr_ws_bytes(C.byref(m)))
+    if ws is None or ws.numel() < wsb:
+        ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=events.device)
+    check(lib().bp_event_csr_matvec(C.byref(m), _p(events), _p(y), _p(ws), wsb, _stream()))
+    return y
+
+
+def event_csr_ws(indptr, indices, data, w, n_post, tile_ptr=None, tile_width=0, sorted_rows=True):
+    m = _csr_struct(indptr, indices, data, w, n_post, tile_ptr, tile_width, sorted_rows)
+    return int(lib().bp_event_csr_ws_bytes(C.byref(m)))
+
+
+def jit_conn_matvec(conn: JitConn, events, out=None, ws=None):
+    """y = M^T e with M regenerated from the seed (Appendix C)."""
+    c = conn.c
+    y = out if out is not None else torch.empty(c.n_post, dtype=torch.float32, device=events.device)
+    wsb = int(lib().bp_jit_ws_bytes(C.byref(c)))
+    if ws is None or ws.numel() < wsb:
+        ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=events.device)
+    check(lib().bp_jit_conn_matvec(C.byref(c), _p(events), _p(y), _p(ws), wsb, _stream()))
+    return y
+
+
+def jit_ws(conn: JitConn):
+    return int(lib().bp_jit_ws_bytes(C.byref(conn.c)))
+
+
+def event_csr_backward(indptr, indices, data, w, n_post, events, dy, want_events=True, want_data=True,
+                       want_w=True):
+    m = _csr_struct(indptr, indices, data, w, n_post)
+    dev = events.device
+    d_ev = torch.empty(indptr.numel() - 1, dtype=torch.float32, device=dev) if want_events else None
+    d_data = torch.empty(max(indices.numel(), 1), dtype=torch.float32, device=dev) if want_data else None
+    d_w = torch.empty(1, dtype=torch.float32, device=dev) if want_w else None
+    check(lib().bp_event_csr_backward(C.byref(m), _p(events), _p(dy), _p(d_ev), _p(d_data), _p(d_w), _stream()))
+    if d_data is not None:
+        d_data = d_data[:indices.numel()]
+    return d_ev, d_data, d_w
+
+
+def jit_conn_backward(conn: JitConn, events, dy, want_events=True, want_w=True):
+    c = conn.c
+    dev = events.device
+    d_ev = torch.empty(c.n_pre, dtype=torch.float32, device=dev) if want_events else None
+    d_w = torch.empty(2, dtype=torch.float32, device=dev) if want_w else None
+    check(lib().bp_jit_conn_backward(C.byref(c), _p(events), _p(dy), _p(d_ev), _p(d_w), _stream()))
+    return d_ev, d_w
+
+
+# ------------------------------------------------------------------ network
+COBA_DEFAULTS = dict(w_exc=0.6, w_inh=6.7, tau_m=20.0, tau_e=5.0, tau_i=10.0, tau_ref=5.0, v_rest=-60.0,
+                     v_th=-50.0, v_reset=-60.0, e_exc=0.0, e_inh=-80.0, r=1.0, i_ext=20.0, dt=0.1,
+                     v0_lo=-60.0, v0_hi=-50.0)
+
+
+def net_desc(n, n_exc=None, p=None, K=None, conn=CONN_JIT, block=0, seed=0, model=COBA, max_wgs=0, **params):
+    kw = dict(COBA_DEFAULTS)
+    kw.update(params)
+    if n_exc is None:
+        n_exc = int(math.floor(0.8 * n))
+    if K is None:
+        K = max_gap(p if p is not None else 80.0 / n)
+    return _abi.NetDesc(model=model, n=n, n_exc=n_exc, conn=conn, max_gap=K, block=block, seed=seed,
+                        max_wgs=max_wgs, **kw)
+
+
+def net_bytes(desc):
+    b = C.c_size_t(0)
+    check(lib().bp_net_bytes(C.byref(desc), C.byref(b)))
+    return int(b.value)
+
+
+class Net:
+    """An E/I LIF network resident in a caller-owned device workspace."""
+
+    def __init__(self, desc, device="cuda", workspace=None):
+        self.desc = desc
+        nbytes = net_bytes(desc)
+        self.ws = workspace if workspace is not None else torch.empty(nbytes, dtype=torch.uint8, device=device)
+        if self.ws.numel() < nbytes:
+            raise BpError(_abi.BP_ENOMEM, f"workspace {self.ws.numel()} < {nbytes} bytes")
+        h = C.c_void_p()
+        check(lib().bp_create_net(C.byref(desc), _p(self.ws), self.ws.numel(), _stream(), C.byref(h)))
+        self.h = h
+        self.device = self.ws.device
+
+    @property
+    def n(self):
+        return self.desc.n
+
+    def info(self):
+        i = _abi.NetInfo()
+        check(lib().bp_net_get_info(self.h, C.byref(i)))
+        return i
+
+    def run(self, n_steps, raster=False, counts=True, i_ext=None):
+        r = torch.empty((n_steps, self.n), dtype=torch.uint8, device=self.device) if raster else None
+        c = torch.empty(max(n_steps, 1), dtype=torch.int32, device=self.device) if counts else None
+        check(lib().bp_run(self.h, n_steps, _p(i_ext), _p(r), _p(c), _stream()))
+        return r, (c[:n_steps] if c is not None else None)
+
+    def step(self, i_ext=None):
+        s = torch.empty(self.n, dtype=torch.uint8, device=self.device)
+        check(lib().bp_step(self.h, _p(i_ext), _p(s), _stream()))
+        return s
+
+    def events(self):
+        out = torch.empty(1, dtype=torch.int64, device=self.device)
+        check(lib().bp_net_events(self.h, _p(out), _stream()))
+        return out
+
+    def error_flag(self):
+        """Device error word of the net (non-zero: a run gave up waiting)."""
+        off = self.info().error_dev - self.ws.data_ptr()
+        return int(self.ws[off:off + 4].view(torch.int32).item())
+
+    def get_state(self):
+        nb = int(lib().bp_state_bytes(self.h))
+        buf = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        check(lib().bp_get_state(self.h, _p(buf), nb, _stream()))
+        n = self.n
+        return dict(V=buf[0:4 * n].view(torch.float32), ge=buf[4 * n:8 * n].view(torch.float32),
+                    gi=buf[8 * n:12 * n].view(torch.float32), ref=buf[12 * n:16 * n].view(torch.int32),
+                    s_prev=buf[16 * n:17 * n], raw=buf, step=self.info().step)
+
+    def set_state(self, raw, step):
+        check(lib().bp_set_state(self.h, _p(raw), raw.numel(), int(step), _stream()))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().bp_destroy_net(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run_batch(nets, n_steps, counts=None):
+    """Advance several nets concurrently in one launch (continuous batching)."""
+    k = len(nets)
+    arr = (C.c_void_p * k)(*[n.h.value for n in nets])
+    st = (C.c_int64 * k)(*[int(s) for s in n_steps])
+    cp = None
+    if counts is not None:
+        cp = (C.c_void_p * k)(*[None if c is None else c.data_ptr() for c in counts])
+    check(lib().bp_run_batch(arr, k, st, cp, _stream()))

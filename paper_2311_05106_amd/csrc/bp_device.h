@@ -1,0 +1,223 @@
+// Device-side building blocks shared by the kernels: the Philox-4x32-10
+// counter-based generator, the seeded row/block generator of the
+// fixed-probability connectivity, wave64 primitives and device-coherent
+// accesses used for cross-workgroup exchange.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bp {
+
+constexpr int kWave = 64;
+constexpr uint32_t kStreamConn = 1, kStreamW = 2, kStreamV0 = 3;
+constexpr int kWHomo = 0, kWNormal = 1, kWUniform = 2;
+
+// ---------------------------------------------------------------------------
+// Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64-bit products mixed into the other two counter words and the round
+// key; the key advances by the golden-ratio Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+struct Words4 {
+  uint32_t w[4];
+};
+
+__device__ __forceinline__ Words4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                           uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return Words4{{c0, c1, c2, c3}};
+}
+
+__device__ __forceinline__ uint32_t pick(const Words4& q, uint32_t i) {
+  const uint32_t s = i & 3u;
+  uint32_t v = q.w[0];
+  v = (s == 1u) ? q.w[1] : v;
+  v = (s == 2u) ? q.w[2] : v;
+  v = (s == 3u) ? q.w[3] : v;
+  return v;
+}
+
+// hash(seed, stream, a, b, k): word k mod 4 of Philox(counter (a, b, k/4, stream)).
+__device__ __forceinline__ uint32_t hash_word(uint64_t seed, uint32_t stream, uint32_t a, uint32_t b, uint32_t k) {
+  return pick(philox10(a, b, k >> 2, stream, (uint32_t)seed, (uint32_t)(seed >> 32)), k);
+}
+
+// Sequential reader of the draws of one (a, b) sub-stream: one Philox call
+// per four draws.
+struct DrawSeq {
+  uint32_t k0, k1, a, b, stream;
+  uint32_t blk;
+  Words4 cur;
+  __device__ __forceinline__ DrawSeq(uint64_t seed, uint32_t stream_, uint32_t a_, uint32_t b_)
+      : k0((uint32_t)seed), k1((uint32_t)(seed >> 32)), a(a_), b(b_), stream(stream_), blk(0xFFFFFFFFu) {}
+  __device__ __forceinline__ uint32_t operator()(uint32_t i) {
+    const uint32_t want = i >> 2;
+    if (want != blk) {
+      blk = want;
+      cur = philox10(a, b, want, stream, k0, k1);
+    }
+    return pick(cur, i);
+  }
+};
+
+// Uniform integer on {0..m-1} from one word (multiply-shift).
+__device__ __forceinline__ uint32_t below(uint32_t word, uint32_t m) { return __umulhi(word, m); }
+
+// u in (0, 1] and [0, 1) from the top 24 bits (exact in FP32).
+__device__ __forceinline__ float u_open0(uint32_t w) { return (float)((w >> 8) + 1u) * (1.0f / 16777216.0f); }
+__device__ __forceinline__ float u_open1(uint32_t w) { return (float)(w >> 8) * (1.0f / 16777216.0f); }
+
+// ---------------------------------------------------------------------------
+// Positions of row j inside post block b of the fixed-probability matrix
+// (gaps uniform on [1, K]; block == 0: one block, first target = gap - 1;
+// block > 0: stationary start block_start + min(ra, rb)), restricted to the
+// window [lo, hi).  emit(pos, m) receives every target in the window, m being
+// its index among all targets of (j, b) in generation order.  Returns the
+// number of targets generated before the walk left the window or block.
+// ---------------------------------------------------------------------------
+template <class Emit>
+__device__ __forceinline__ void gen_block(uint64_t seed, uint32_t K, int32_t n_post, int32_t B, uint32_t j,
+                                          uint32_t b, int64_t lo, int64_t hi, Emit&& emit) {
+  DrawSeq d(seed, kStreamConn, j, b);
+  int64_t start, end, pos;
+  uint32_t i;
+  if (B > 0) {
+    start = (int64_t)b * B;
+    end = start + B;
+    if (end > n_post) end = n_post;
+    const uint32_t ra = below(d(0), K);
+    const uint32_t rb = below(d(1), K + 1u);
+    pos = start + (int64_t)(ra < rb ? ra : rb);
+    i = 2;
+  } else {
+    start = 0;
+    end = n_post;
+    pos = (int64_t)below(d(0), K);
+    i = 1;
+  }
+  if (hi < end) end = hi;
+  uint32_t m = 0;
+  while (pos < end) {
+    if (pos >= lo) emit((int32_t)pos, m);
+    ++m;
+    pos += 1 + (int64_t)below(d(i), K);
+    ++i;
+  }
+}
+
+// Weight of connection m of (j, b) for the JIT weight kinds; *unit receives
+// the unit draw (z or u) for the reverse mode.
+__device__ __forceinline__ float jit_weight(uint64_t seed, int wkind, float w0, float w1, uint32_t j, uint32_t b,
+                                            uint32_t m, float* unit) {
+  if (wkind == kWNormal) {
+    const Words4 q = philox10(j, b, m >> 1, kStreamW, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const uint32_t wa = pick(q, 2u * m), wb = pick(q, 2u * m + 1u);
+    const float u1 = u_open0(wa), u2 = u_open1(wb);
+    const float z = sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
+    *unit = z;
+    return w0 + w1 * z;
+  }
+  if (wkind == kWUniform) {
+    const float u = u_open1(hash_word(seed, kStreamW, j, b, m));
+    *unit = u;
+    return w0 + (w1 - w0) * u;
+  }
+  *unit = 1.0f;
+  return w0;
+}
+
+// ---------------------------------------------------------------------------
+// wave64 / workgroup primitives
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Number of set bits of `mask` below this lane.
+__device__ __forceinline__ int mask_rank(uint64_t mask) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Inclusive prefix sum across the wave.
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int t = __shfl_up(v, o, kWave);
+    if (l >= o) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Exclusive prefix sum over the workgroup; *total receives the sum.
+// `scratch` holds at least blockDim.x / 64 + 1 ints of LDS.
+__device__ __forceinline__ int block_excl_scan(int v, int* scratch, int* total) {
+  const int l = lane_id(), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  const int inc = wave_incl_scan(v);
+  if (l == kWave - 1) scratch[w] = inc;
+  __syncthreads();
+  if (w == 0) {
+    const int s = (l < nw) ? scratch[l] : 0;
+    const int si = wave_incl_scan(s);
+    if (l < nw) scratch[l] = si - s;
+    if (l == nw - 1) scratch[nw] = si;
+  }
+  __syncthreads();
+  const int r = scratch[w] + inc - v;
+  *total = scratch[nw];
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Device-coherent accesses for data exchanged between workgroups of one
+// launch (possibly on different XCDs, whose L2 caches are not coherent with
+// each other).  These compile to sc1 loads/stores that bypass the
+// non-coherent L2 state, without the L2 writeback/invalidate that an
+// agent-scope fence performs.  A writer makes its coherent stores complete
+// (vm_drain) before the workgroup barrier that precedes its flag store; a
+// reader issues its coherent data loads only after it has observed the flag.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int ld_coh(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_coh(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coh(int* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coh(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until every vector memory operation this wave issued has completed
+// (s_waitcnt vmcnt(0); stores are counted by vmcnt on gfx9-family targets).
+__device__ __forceinline__ void vm_drain() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+}  // namespace bp

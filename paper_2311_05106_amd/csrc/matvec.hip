@@ -1,0 +1,500 @@
+// Event-driven CSR matvec (Appendix B), JIT-connectivity matvec (Appendix C,
+// Section 5.2) and their reverse modes (Section 4.1).
+//
+// Forward layout: the postsynaptic range is cut into tiles of P columns that
+// fit in LDS, the presynaptic range into C chunks of rows.  Workgroup
+// (tile, chunk) compacts the spikes of its rows into LDS (ballot + prefix
+// sum, ascending), then streams the part of every firing row that falls in
+// its tile and accumulates into its LDS tile (integer counts for homogeneous
+// weights, FP32 otherwise).  With one chunk the tile is written to y
+// directly; with several, each chunk stores its tile to a partial buffer and
+// a second kernel sums the partials in chunk order (no global atomics: device
+// atomics run far below HBM rate on this chip).
+//   CSR rows are streamed coalesced; a wave walks a contiguous slice of the
+//   flattened (row, offset) space of the firing rows (merge-path split).
+//   JIT rows are regenerated per (row, block) by one lane each.
+#include "bp_device.h"
+#include "bp_host.h"
+
+namespace bp {
+
+constexpr int kMvThreads = 512;
+constexpr int kMvWaves = kMvThreads / kWave;
+constexpr int kMvPiece = kMvThreads * 4;  // rows compacted per piece
+constexpr int kTileMax = 16384;           // LDS tile columns (64 KB)
+
+enum MvMode { kCsrHomo = 0, kCsrData = 1, kJitHomo = 2, kJitWeighted = 3 };
+
+struct MvArgs {
+  const int32_t* indptr;
+  const int32_t* indices;
+  const float* data;
+  const int32_t* tile_ptr;  // [n_pre][n_tiles + 1] or null (single tile)
+  const uint8_t* events;
+  void* out;                // y (chunks == 1) or partials [chunks][n_post]
+  bp_jit_conn jit;
+  float w;
+  int32_t n_pre, n_post;
+  int32_t tile, n_tiles;    // tile width P, number of tiles
+  int32_t chunks, chunk_rows;
+};
+
+struct MvShared {
+  int ids[kMvPiece];
+  int pref[kMvPiece + 1];
+  int start[kMvPiece];
+  int scan[kMvWaves + 1];
+};
+
+// Compacts events[r0, r1) (r1 - r0 <= kMvPiece) into sh.ids, ascending.
+__device__ __forceinline__ int compact_piece(const uint8_t* __restrict__ ev, int32_t r0, int32_t r1, MvShared& sh) {
+  const int base = threadIdx.x * 4;
+  uint32_t bits = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int32_t r = r0 + base + q;
+    if (r < r1 && ev[r]) bits |= 1u << q;
+  }
+  int tot;
+  int off = block_excl_scan(__popc(bits), sh.scan, &tot);
+  while (bits) {
+    const int q = __ffs(bits) - 1;
+    bits &= bits - 1;
+    sh.ids[off++] = r0 + base + q;
+  }
+  __syncthreads();
+  return tot;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
+  using Acc = typename std::conditional<(MODE == kCsrHomo || MODE == kJitHomo), uint32_t, float>::type;
+  __shared__ Acc acc[kTileMax];
+  __shared__ MvShared sh;
+  const int t = blockIdx.x % a.n_tiles;
+  const int c = blockIdx.x / a.n_tiles;
+  const int32_t lo = t * a.tile;
+  const int32_t hi = min(lo + a.tile, a.n_post);
+  const int32_t width = hi - lo;
+  const int32_t r_begin = c * a.chunk_rows;
+  const int32_t r_end = min(r_begin + a.chunk_rows, a.n_pre);
+  for (int i = threadIdx.x; i < width; i += kMvThreads) acc[i] = (Acc)0;
+  __syncthreads();
+
+  for (int32_t r0 = r_begin; r0 < r_end; r0 += kMvPiece) {
+    const int n_act = compact_piece(a.events, r0, min(r0 + kMvPiece, r_end), sh);
+    if (n_act == 0) continue;
+    if constexpr (MODE == kCsrHomo || MODE == kCsrData) {
+      // segment of each firing row inside this tile
+      int total = 0;
+      for (int base = 0; base < n_act; base += kMvThreads) {
+        const int i = base + threadIdx.x;
+        int st = 0, len = 0;
+        if (i < n_act) {
+          const int32_t j = sh.ids[i];
+          if (a.tile_ptr) {
+            const int32_t* tp = a.tile_ptr + (size_t)j * (a.n_tiles + 1) + t;
+            st = tp[0];
+            len = tp[1] - st;
+          } else {
+            st = a.indptr[j];
+            len = a.indptr[j + 1] - st;
+          }
+        }
+        int tot;
+        const int ex = block_excl_scan(len, sh.scan, &tot);
+        if (i < n_act) {
+          sh.pref[i] = total + ex;
+          sh.start[i] = st;
+        }
+        total += tot;
+      }
+      if (threadIdx.x == 0) sh.pref[n_act] = total;
+      __syncthreads();
+      // merge-path: wave w walks [e0, e1) of the flattened firing entries
+      const int wv = threadIdx.x / kWave, ln = lane_id();
+      const int per = (total + kMvWaves - 1) / kMvWaves;
+      const int e0 = wv * per, e1 = min(e0 + per, total);
+      if (e0 < e1) {
+        int lo_r = 0, hi_r = n_act;  // largest r with pref[r] <= e0
+        while (hi_r - lo_r > 1) {
+          const int mid = (lo_r + hi_r) >> 1;
+          if (sh.pref[mid] <= e0) lo_r = mid; else hi_r = mid;
+        }
+        int r = lo_r;
+        for (int e = e0 + ln; e < e1 + ln; e += 2 * kWave) {
+          const int ea = e, eb = e + kWave;
+          int ra = r;
+          while (ra + 1 < n_act && sh.pref[ra + 1] <= ea) ++ra;
+          int rb = ra;
+          while (rb + 1 < n_act && sh.pref[rb + 1] <= eb) ++rb;
+          const bool va = ea < e1, vb = eb < e1;
+          const int ia = va ? sh.start[ra] + (ea - sh.pref[ra]) : 0;
+          const int ib = vb ? sh.start[rb] + (eb - sh.pref[rb]) : 0;
+          const int ca = va ? a.indices[ia] : 0;
+          const int cb = vb ? a.indices[ib] : 0;
+          if constexpr (MODE == kCsrHomo) {
+            if (va) atomicAdd(&acc[ca - lo], 1u);
+            if (vb) atomicAdd(&acc[cb - lo], 1u);
+          } else {
+            const float da = va ? a.data[ia] : 0.f;
+            const float db = vb ? a.data[ib] : 0.f;
+            if (va) atomicAdd(&acc[ca - lo], da);
+            if (vb) atomicAdd(&acc[cb - lo], db);
+          }
+          r = rb;
+        }
+      }
+      __syncthreads();
+    } else {
+      // JIT: one lane per (firing row, block overlapping the tile)
+      const int32_t B = a.jit.block;
+      const int32_t b_lo = B > 0 ? lo / B : 0;
+      const int32_t b_hi = B > 0 ? (hi - 1) / B : 0;
+      const int32_t nbt = b_hi - b_lo + 1;
+      const int items = n_act * nbt;
+      for (int it = threadIdx.x; it < items; it += kMvThreads) {
+        const int ai = it / nbt;
+        const uint32_t b = (uint32_t)(b_lo + it % nbt);
+        const uint32_t j = (uint32_t)sh.ids[ai];
+        gen_block(a.jit.seed, (uint32_t)a.jit.max_gap, a.n_post, B, j, b, lo, hi, [&](int32_t pos, uint32_t m) {
+          if constexpr (MODE == kJitHomo) {
+            atomicAdd(&acc[pos - lo], 1u);
+          } else {
+            float unit;
+            atomicAdd(&acc[pos - lo], jit_weight(a.jit.seed, a.jit.wkind, a.jit.w0, a.jit.w1, j, b, m, &unit));
+          }
+        });
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  if (a.chunks == 1) {
+    float* y = reinterpret_cast<float*>(a.out);
+    for (int i = threadIdx.x; i < width; i += kMvThreads) {
+      if constexpr (MODE == kCsrHomo || MODE == kJitHomo) y[lo + i] = (float)acc[i] * a.w;
+      else y[lo + i] = acc[i];
+    }
+  } else {
+    Acc* part = reinterpret_cast<Acc*>(a.out) + (size_t)c * a.n_post;
+    for (int i = threadIdx.x; i < width; i += kMvThreads) part[lo + i] = acc[i];
+  }
+}
+
+// y[k] = w * sum_c counts[c][k]  (integer sum, one FP32 rounding)
+__global__ void mv_reduce_counts_k(const uint32_t* __restrict__ part, int32_t chunks, int32_t n_post, float w,
+                                   float* __restrict__ y) {
+  const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_post) return;
+  uint32_t s = 0;
+  for (int c = 0; c < chunks; ++c) s += part[(size_t)c * n_post + k];
+  y[k] = (float)s * w;
+}
+// y[k] = sum_c part[c][k] in chunk order
+__global__ void mv_reduce_f32_k(const float* __restrict__ part, int32_t chunks, int32_t n_post, float* __restrict__ y) {
+  const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_post) return;
+  float s = 0.f;
+  for (int c = 0; c < chunks; ++c) s += part[(size_t)c * n_post + k];
+  y[k] = s;
+}
+
+// Unsorted CSR wider than one tile: counts / sums with device atomics.
+__global__ void mv_zero_k(uint32_t* p, int32_t n) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+template <bool HOMO>
+__global__ void mv_atomic_k(MvArgs a, uint32_t* acc) {
+  const int wv = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int nw = gridDim.x * blockDim.x / kWave;
+  for (int32_t j = wv; j < a.n_pre; j += nw) {
+    if (!a.events[j]) continue;
+    for (int32_t idx = a.indptr[j] + lane_id(); idx < a.indptr[j + 1]; idx += kWave) {
+      if (HOMO) atomicAdd(&acc[a.indices[idx]], 1u);
+      else atomicAdd(reinterpret_cast<float*>(acc) + a.indices[idx], a.data[idx]);
+    }
+  }
+}
+__global__ void mv_counts_to_y_k(const uint32_t* acc, int32_t n, float w, float* y) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (float)acc[i] * w;
+}
+
+// ---------------------------------------------------------------- reverse mode
+__global__ void zero_f32_k(float* p, int32_t n) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.f;
+}
+
+// One wave per row.
+__global__ void csr_backward_k(bp_csr m, const uint8_t* __restrict__ ev, const float* __restrict__ dy,
+                               float* __restrict__ d_ev, float* __restrict__ d_data, float* __restrict__ d_w) {
+  const int wv = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int nw = gridDim.x * blockDim.x / kWave;
+  float gw = 0.f;
+  for (int32_t j = wv; j < m.n_pre; j += nw) {
+    const bool on = ev[j] != 0;
+    float acc = 0.f, accw = 0.f;
+    for (int32_t idx = m.indptr[j] + lane_id(); idx < m.indptr[j + 1]; idx += kWave) {
+      const float g = dy[m.indices[idx]];
+      acc += (m.data ? m.data[idx] : m.w) * g;
+      accw += g;
+      if (d_data) d_data[idx] = on ? g : 0.f;
+    }
+    acc = wave_sum_f(acc);
+    if (d_ev && lane_id() == 0) d_ev[j] = acc;
+    if (on) gw += accw;
+  }
+  if (d_w) {
+    gw = wave_sum_f(gw);
+    if (lane_id() == 0 && gw != 0.f) atomicAdd(d_w, gw);
+  }
+}
+
+// One thread per row (all blocks of the row in order).
+__global__ void jit_backward_k(bp_jit_conn c, const uint8_t* __restrict__ ev, const float* __restrict__ dy,
+                               float* __restrict__ d_ev, float* __restrict__ d_w) {
+  const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  float g0 = 0.f, g1 = 0.f;
+  if (j < c.n_pre) {
+    const int32_t nb = c.block > 0 ? (int32_t)(((int64_t)c.n_post + c.block - 1) / c.block) : 1;
+    const bool on = ev[j] != 0;
+    float acc = 0.f;
+    for (int32_t b = 0; b < nb; ++b) {
+      gen_block(c.seed, (uint32_t)c.max_gap, c.n_post, c.block, (uint32_t)j, (uint32_t)b, 0, c.n_post,
+                [&](int32_t pos, uint32_t m) {
+                  float unit;
+                  const float wjk = jit_weight(c.seed, c.wkind, c.w0, c.w1, (uint32_t)j, (uint32_t)b, m, &unit);
+                  const float g = dy[pos];
+                  acc += wjk * g;
+                  if (on) {
+                    if (c.wkind == kWNormal) { g0 += g; g1 += unit * g; }
+                    else if (c.wkind == kWUniform) { g0 += (1.f - unit) * g; g1 += unit * g; }
+                    else g0 += g;
+                  }
+                });
+    }
+    if (d_ev) d_ev[j] = acc;
+  }
+  if (d_w) {
+    g0 = wave_sum_f(g0);
+    g1 = wave_sum_f(g1);
+    if (lane_id() == 0) {
+      if (g0 != 0.f) atomicAdd(&d_w[0], g0);
+      if (g1 != 0.f) atomicAdd(&d_w[1], g1);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- planning
+struct MvPlan {
+  int32_t tile, n_tiles, chunks, chunk_rows;
+  bool atomic_path;
+  size_t ws;
+};
+
+static int32_t target_wgs() { return 2 * device_cu_count(); }
+
+static MvPlan plan_csr(const bp_csr* m) {
+  MvPlan p{};
+  if (m->n_post <= kTileMax) {
+    p.tile = m->n_post > 0 ? m->n_post : 1;
+    p.n_tiles = 1;
+  } else if (m->sorted && m->tile_ptr && m->tile_width > 0 && m->tile_width <= kTileMax) {
+    p.tile = m->tile_width;
+    p.n_tiles = (int32_t)(((int64_t)m->n_post + p.tile - 1) / p.tile);
+  } else {
+    p.atomic_path = true;
+    p.ws = (size_t)(m->n_post > 0 ? m->n_post : 1) * sizeof(uint32_t);
+    return p;
+  }
+  int32_t want = (target_wgs() + p.n_tiles - 1) / p.n_tiles;
+  const int32_t by_rows = (m->n_pre + kMvPiece - 1) / kMvPiece;  // at least one piece per chunk
+  p.chunks = max(1, min(want, max(by_rows, 1)));
+  p.chunk_rows = (m->n_pre + p.chunks - 1) / max(p.chunks, 1);
+  p.chunk_rows = max(1, p.chunk_rows);
+  p.chunks = max(1, (m->n_pre + p.chunk_rows - 1) / p.chunk_rows);
+  p.ws = p.chunks > 1 ? (size_t)p.chunks * m->n_post * sizeof(uint32_t) : 0;
+  return p;
+}
+
+static MvPlan plan_jit(const bp_jit_conn* c) {
+  MvPlan p{};
+  if (c->n_post <= kTileMax) {
+    p.tile = c->n_post > 0 ? c->n_post : 1;
+  } else if (c->block > 0 && c->block <= kTileMax) {
+    p.tile = (kTileMax / c->block) * c->block;
+  } else {
+    p.tile = kTileMax;  // whole-row sequences regenerated up to each tile
+  }
+  p.n_tiles = (int32_t)(((int64_t)c->n_post + p.tile - 1) / p.tile);
+  if (p.n_tiles < 1) p.n_tiles = 1;
+  int32_t want = (target_wgs() + p.n_tiles - 1) / p.n_tiles;
+  const int32_t by_rows = (c->n_pre + 255) / 256;
+  p.chunks = max(1, min(want, max(by_rows, 1)));
+  p.chunk_rows = max(1, (c->n_pre + p.chunks - 1) / p.chunks);
+  p.chunks = max(1, (c->n_pre + p.chunk_rows - 1) / p.chunk_rows);
+  p.ws = p.chunks > 1 ? (size_t)p.chunks * c->n_post * sizeof(uint32_t) : 0;
+  return p;
+}
+
+static bp_status check_csr(const bp_csr* m) {
+  BP_REQUIRE(m != nullptr, "null CSR descriptor");
+  BP_REQUIRE(m->n_pre >= 0 && m->n_post >= 0, "negative size");
+  BP_REQUIRE(m->indptr != nullptr, "null indptr");
+  return BP_OK;
+}
+
+template <int MODE>
+static bp_status launch_scatter(const MvArgs& a, const MvPlan& p, hipStream_t st) {
+  mv_scatter_k<MODE><<<p.n_tiles * p.chunks, kMvThreads, 0, st>>>(a);
+  BP_LAUNCHED("mv_scatter_k");
+  return BP_OK;
+}
+
+static bp_status finish_partials(const MvPlan& p, bool homo, void* ws, int32_t n_post, float w, float* y,
+                                 hipStream_t st) {
+  if (p.chunks <= 1 || n_post == 0) return BP_OK;
+  const int g = (n_post + 255) / 256;
+  if (homo) mv_reduce_counts_k<<<g, 256, 0, st>>>((const uint32_t*)ws, p.chunks, n_post, w, y);
+  else mv_reduce_f32_k<<<g, 256, 0, st>>>((const float*)ws, p.chunks, n_post, y);
+  BP_LAUNCHED("mv_reduce_k");
+  return BP_OK;
+}
+
+}  // namespace bp
+
+using namespace bp;
+
+extern "C" {
+
+size_t bp_event_csr_ws_bytes(const bp_csr* m) {
+  if (!m) return 0;
+  return plan_csr(m).ws;
+}
+
+bp_status bp_csr_tile_index(const int32_t* indptr, const int32_t* indices, int32_t n_pre, int32_t n_post,
+                            int32_t tile_width, int32_t* tile_ptr, bp_stream stream) {
+  BP_REQUIRE(indptr && tile_ptr, "null pointer");
+  BP_REQUIRE(n_pre >= 0 && n_post >= 0, "negative size");
+  BP_REQUIRE(tile_width > 0 && tile_width <= kTileMax, "tile_width must be in [1, %d]", kTileMax);
+  if (n_pre == 0) return BP_OK;
+  const int32_t n_tiles = (int32_t)(((int64_t)n_post + tile_width - 1) / tile_width);
+  return launch_tile_index(indptr, indices, n_pre, tile_width, n_tiles > 0 ? n_tiles : 1, tile_ptr,
+                           as_stream(stream));
+}
+
+bp_status bp_event_csr_matvec(const bp_csr* m, const uint8_t* events, float* y, void* ws, size_t ws_bytes,
+                              bp_stream stream) {
+  bp_status s = check_csr(m);
+  if (s) return s;
+  if (m->n_post == 0) return BP_OK;
+  BP_REQUIRE(y != nullptr, "null y");
+  BP_REQUIRE(m->n_pre == 0 || events != nullptr, "null events");
+  hipStream_t st = as_stream(stream);
+  const MvPlan p = plan_csr(m);
+  BP_REQUIRE(ws_bytes >= p.ws && (p.ws == 0 || ws != nullptr), "workspace too small (%zu < %zu)", ws_bytes, p.ws);
+  const bool homo = m->data == nullptr;
+  if (p.atomic_path) {
+    uint32_t* acc = (uint32_t*)ws;
+    const int g = (m->n_post + 255) / 256;
+    mv_zero_k<<<g, 256, 0, st>>>(acc, m->n_post);
+    BP_LAUNCHED("mv_zero_k");
+    MvArgs a{};
+    a.indptr = m->indptr; a.indices = m->indices; a.data = m->data; a.events = events; a.n_pre = m->n_pre;
+    a.n_post = m->n_post;
+    if (m->n_pre > 0) {
+      if (homo) mv_atomic_k<true><<<1024, 256, 0, st>>>(a, acc);
+      else mv_atomic_k<false><<<1024, 256, 0, st>>>(a, acc);
+      BP_LAUNCHED("mv_atomic_k");
+    }
+    if (homo) {
+      mv_counts_to_y_k<<<g, 256, 0, st>>>(acc, m->n_post, m->w, y);
+      BP_LAUNCHED("mv_counts_to_y_k");
+    } else {
+      BP_HIP(hipMemcpyAsync(y, acc, (size_t)m->n_post * 4, hipMemcpyDeviceToDevice, st));
+    }
+    return BP_OK;
+  }
+  MvArgs a{};
+  a.indptr = m->indptr; a.indices = m->indices; a.data = m->data;
+  a.tile_ptr = p.n_tiles > 1 ? m->tile_ptr : nullptr;
+  a.events = events; a.out = p.chunks > 1 ? ws : (void*)y; a.w = m->w;
+  a.n_pre = m->n_pre; a.n_post = m->n_post; a.tile = p.tile; a.n_tiles = p.n_tiles;
+  a.chunks = p.chunks; a.chunk_rows = p.chunk_rows;
+  s = homo ? launch_scatter<kCsrHomo>(a, p, st) : launch_scatter<kCsrData>(a, p, st);
+  if (s) return s;
+  return finish_partials(p, homo, ws, m->n_post, m->w, y, st);
+}
+
+size_t bp_jit_ws_bytes(const bp_jit_conn* c) {
+  if (!c) return 0;
+  return plan_jit(c).ws;
+}
+
+bp_status bp_jit_conn_matvec(const bp_jit_conn* c, const uint8_t* events, float* y, void* ws, size_t ws_bytes,
+                             bp_stream stream) {
+  bp_status s = check_conn(c, true);
+  if (s) return s;
+  if (c->n_post == 0) return BP_OK;
+  BP_REQUIRE(y != nullptr, "null y");
+  BP_REQUIRE(c->n_pre == 0 || events != nullptr, "null events");
+  hipStream_t st = as_stream(stream);
+  const MvPlan p = plan_jit(c);
+  BP_REQUIRE(ws_bytes >= p.ws && (p.ws == 0 || ws != nullptr), "workspace too small (%zu < %zu)", ws_bytes, p.ws);
+  const bool homo = c->wkind == kWHomo;
+  MvArgs a{};
+  a.jit = *c; a.events = events; a.out = p.chunks > 1 ? ws : (void*)y; a.w = c->w0;
+  a.n_pre = c->n_pre; a.n_post = c->n_post; a.tile = p.tile; a.n_tiles = p.n_tiles;
+  a.chunks = p.chunks; a.chunk_rows = p.chunk_rows;
+  s = homo ? launch_scatter<kJitHomo>(a, p, st) : launch_scatter<kJitWeighted>(a, p, st);
+  if (s) return s;
+  return finish_partials(p, homo, ws, c->n_post, c->w0, y, st);
+}
+
+bp_status bp_event_csr_backward(const bp_csr* m, const uint8_t* events, const float* dy, float* d_events,
+                                float* d_data, float* d_w, bp_stream stream) {
+  bp_status s = check_csr(m);
+  if (s) return s;
+  hipStream_t st = as_stream(stream);
+  if (d_w) {
+    zero_f32_k<<<1, 64, 0, st>>>(d_w, 1);
+    BP_LAUNCHED("zero_f32_k");
+  }
+  if (m->n_pre == 0) return BP_OK;
+  BP_REQUIRE(events && dy, "null events or dy");
+  const int64_t waves = m->n_pre;
+  const int64_t want = (waves + 3) / 4;
+  const int blocks = (int)(want < 4096 ? want : 4096);
+  csr_backward_k<<<blocks, 256, 0, st>>>(*m, events, dy, d_events, d_data, d_w);
+  BP_LAUNCHED("csr_backward_k");
+  return BP_OK;
+}
+
+bp_status bp_jit_conn_backward(const bp_jit_conn* c, const uint8_t* events, const float* dy, float* d_events,
+                               float* d_w, bp_stream stream) {
+  bp_status s = check_conn(c, true);
+  if (s) return s;
+  hipStream_t st = as_stream(stream);
+  if (d_w) {
+    zero_f32_k<<<1, 64, 0, st>>>(d_w, 2);
+    BP_LAUNCHED("zero_f32_k");
+  }
+  if (c->n_pre == 0) return BP_OK;
+  BP_REQUIRE(events && dy, "null events or dy");
+  jit_backward_k<<<(c->n_pre + 255) / 256, 256, 0, st>>>(*c, events, dy, d_events, d_w);
+  BP_LAUNCHED("jit_backward_k");
+  return BP_OK;
+}
+
+bp_status bp_backward(int32_t op, const void* args, const uint8_t* events, const float* dy, float* d_events,
+                      float* d_data, float* d_w, bp_stream stream) {
+  BP_REQUIRE(args != nullptr, "null args");
+  if (op == 0) return bp_event_csr_backward((const bp_csr*)args, events, dy, d_events, d_data, d_w, stream);
+  if (op == 1) return bp_jit_conn_backward((const bp_jit_conn*)args, events, dy, d_events, d_w, stream);
+  return set_error(BP_EINVAL, "unknown op %d", op);
+}
+
+}  // extern "C"

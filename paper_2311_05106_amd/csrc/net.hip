@@ -1,0 +1,766 @@
+// The E/I LIF network of Appendix N (LIF and conductance equations of
+// Appendix F, exact exponential synapses of Appendix E merged per
+// postsynaptic neuron as in the AlignPost projection of Section 4.3) with a
+// one-step spike delay, run as one persistent kernel per call.
+//
+// Each workgroup owns a contiguous range of neurons: their V, ge, gi and
+// refractory counters stay in registers for the whole launch.  One step:
+//   1. wait until every workgroup of the net has published the spikes of the
+//      previous step (per-workgroup step flags, device-coherent loads);
+//   2. gather the compacted spike lists of all workgroups;
+//   3. for every firing presynaptic row, accumulate the targets that fall in
+//      the own range into LDS integer counters (excitatory and inhibitory
+//      separately): stored CSR segments are streamed, JIT rows are
+//      regenerated per post block from the seed;
+//   4. update the own neurons (synaptic decay + input, COBA/CUBA current,
+//      forward Euler, refractoriness, threshold, reset);
+//   5. compact the own spikes (wave ballots + prefix over waves, ascending),
+//      store them with device-coherent stores and publish the step flag.
+// Nets small enough for one workgroup skip the flags.  Several nets run in
+// one launch (continuous batching): the grid is the concatenation of their
+// workgroup ranges and each net synchronizes only its own workgroups.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+
+#include "bp_device.h"
+#include "bp_host.h"
+
+namespace bp {
+
+constexpr int kNetThreads = 512;
+constexpr int kNetWaves = kNetThreads / kWave;
+constexpr int kNPT = 8;                        // neurons per thread
+constexpr int kRangeMax = kNetThreads * kNPT;  // neurons per workgroup
+constexpr int kIdBatch = 2048;                 // firing rows staged per pass
+constexpr int kMaxWgPerNet = 1024;
+constexpr int kMaxBatch = 48;
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+struct NetDev {
+  int32_t model, n, n_exc, conn, K, block, nb, ref_steps;
+  uint64_t seed;
+  float w_exc, w_inh, de, di, a, v_rest, v_th, v_reset, e_exc, e_inh, r, i_ext;
+  int32_t n_wg, range;
+  float* V;
+  float* ge;
+  float* gi;
+  int32_t* ref;
+  const int32_t* indptr;
+  const int32_t* indices;
+  const int32_t* blkptr;  // [n][nb + 1] block index of the stored rows, or null
+  int32_t* lists;         // [2][n_wg][range] spike ids by step parity
+  int32_t* lcount;        // [2][n_wg]
+  uint32_t* flags;        // [n_wg] steps completed
+  unsigned long long* events;  // [n_wg] synaptic events delivered
+  uint32_t* error;
+};
+
+struct NetLaunch {
+  const NetDev* net;
+  uint8_t* raster;
+  int32_t* counts;
+  const float* iext;
+  int64_t t0;
+  int32_t n_steps;
+  int32_t wg_begin;
+  int32_t n_wg;
+  int32_t pad;
+};
+
+struct BatchArgs {
+  int32_t n_nets;
+  uint32_t spin_limit;
+  NetLaunch e[kMaxBatch];
+};
+
+struct NetShared {
+  uint32_t cE[kRangeMax];
+  uint32_t cI[kRangeMax];
+  int ids[kIdBatch];
+  int pref[kIdBatch + 1];
+  int start[kIdBatch];
+  int srcpref[kMaxWgPerNet + 1];
+  int wcnt[kNPT * kNetWaves];
+  int scan[kNetWaves + 1];
+  int abort_flag;
+  int total;
+};
+
+// Wait (bounded) until flags[i] >= t for every workgroup i != self.
+__device__ __forceinline__ void wait_flags(const NetDev& N, int self, int64_t t, uint32_t spin_limit, NetShared& sh) {
+  for (int i = threadIdx.x; i < N.n_wg; i += kNetThreads) {
+    if (i == self) continue;
+    uint32_t spins = 0;
+    while ((int32_t)(ld_coh(&N.flags[i]) - (uint32_t)t) < 0) {
+      if (++spins > spin_limit) {
+        atomicOr(N.error, 1u);
+        sh.abort_flag = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kNetThreads) net_run_k(BatchArgs args) {
+  __shared__ NetShared sh;
+  int e = 0;
+  while (e < args.n_nets && (int)blockIdx.x >= args.e[e].wg_begin + args.e[e].n_wg) ++e;
+  if (e >= args.n_nets) return;
+  const NetLaunch L = args.e[e];
+  const NetDev N = *L.net;
+  const int w = (int)blockIdx.x - L.wg_begin;
+  const int tid = threadIdx.x, wave = tid / kWave;
+  const int32_t lo = w * N.range;
+  const int32_t hi = min(lo + N.range, N.n);
+  const int32_t R = hi - lo;
+
+  float V[kNPT], ge[kNPT], gi[kNPT];
+  int32_t ref[kNPT];
+#pragma unroll
+  for (int i = 0; i < kNPT; ++i) {
+    const int k = i * kNetThreads + tid;
+    V[i] = ge[i] = gi[i] = 0.f;
+    ref[i] = 0;
+    if (k < R) {
+      V[i] = N.V[lo + k];
+      ge[i] = N.ge[lo + k];
+      gi[i] = N.gi[lo + k];
+      ref[i] = N.ref[lo + k];
+    }
+  }
+  for (int k = tid; k < R; k += kNetThreads) {
+    sh.cE[k] = 0u;
+    sh.cI[k] = 0u;
+  }
+  if (tid == 0) sh.abort_flag = 0;
+  __syncthreads();
+
+  const int32_t B = N.block;
+  const int32_t b_lo = B > 0 ? lo / B : 0;
+  const int32_t b_hi = B > 0 ? (hi - 1) / B : 0;
+  const int32_t nbt = b_hi - b_lo + 1;
+  unsigned long long ev_local = 0;
+
+  for (int32_t s = 0; s < L.n_steps; ++s) {
+    const int64_t t = L.t0 + s;
+    const int pin = (int)((t + 1) & 1);  // parity of step t-1
+    const int pout = (int)(t & 1);
+    if (N.n_wg > 1) wait_flags(N, w, t, args.spin_limit, sh);
+    __syncthreads();
+    if (sh.abort_flag) break;
+
+    // spike counts of step t-1 per workgroup -> prefix
+    int A = 0;
+    for (int base = 0; base < N.n_wg; base += kNetThreads) {
+      const int i = base + tid;
+      const int c = (i < N.n_wg) ? ld_coh(&N.lcount[pin * N.n_wg + i]) : 0;
+      int tot;
+      const int ex = block_excl_scan(c, sh.scan, &tot);
+      if (i < N.n_wg) sh.srcpref[i] = A + ex;
+      A += tot;
+    }
+    if (tid == 0) sh.srcpref[N.n_wg] = A;
+    __syncthreads();
+    if (w == 0 && tid == 0 && L.counts && s > 0) L.counts[s - 1] = A;
+
+    for (int q0 = 0; q0 < A; q0 += kIdBatch) {
+      const int nact = min(kIdBatch, A - q0);
+      for (int q = tid; q < nact; q += kNetThreads) {
+        const int g = q0 + q;
+        int l = 0, h = N.n_wg;  // largest l with srcpref[l] <= g
+        while (h - l > 1) {
+          const int m = (l + h) >> 1;
+          if (sh.srcpref[m] <= g) l = m; else h = m;
+        }
+        sh.ids[q] = ld_coh(&N.lists[((size_t)pin * N.n_wg + l) * N.range + (g - sh.srcpref[l])]);
+      }
+      __syncthreads();
+      if (N.conn == 1) {
+        // regenerate the blocks of each firing row that overlap [lo, hi)
+        const int items = nact * nbt;
+        for (int it = tid; it < items; it += kNetThreads) {
+          const int ai = it / nbt;
+          const uint32_t b = (uint32_t)(b_lo + it % nbt);
+          const uint32_t j = (uint32_t)sh.ids[ai];
+          uint32_t* cnt = ((int32_t)j < N.n_exc) ? sh.cE : sh.cI;
+          gen_block(N.seed, (uint32_t)N.K, N.n, B, j, b, lo, hi, [&](int32_t pos, uint32_t) {
+            atomicAdd(&cnt[pos - lo], 1u);
+            ++ev_local;
+          });
+        }
+      } else {
+        // stored rows: segment of each firing row inside [lo, hi)
+        int total = 0;
+        for (int base = 0; base < nact; base += kNetThreads) {
+          const int i = base + tid;
+          int st = 0, len = 0;
+          if (i < nact) {
+            const int32_t j = sh.ids[i];
+            if (N.n_wg == 1) {
+              st = N.indptr[j];
+              len = N.indptr[j + 1] - st;
+            } else if (N.blkptr) {
+              const int32_t* bp = N.blkptr + (size_t)j * (N.nb + 1);
+              st = bp[b_lo];
+              len = bp[b_hi + 1] - st;
+            } else {
+              int32_t l = N.indptr[j], h = N.indptr[j + 1];
+              while (l < h) {
+                const int32_t m = (l + h) >> 1;
+                if (N.indices[m] < lo) l = m + 1; else h = m;
+              }
+              st = l;
+              h = N.indptr[j + 1];
+              while (l < h) {
+                const int32_t m = (l + h) >> 1;
+                if (N.indices[m] < hi) l = m + 1; else h = m;
+              }
+              len = l - st;
+            }
+          }
+          int tot;
+          const int ex = block_excl_scan(len, sh.scan, &tot);
+          if (i < nact) {
+            sh.pref[i] = total + ex;
+            sh.start[i] = st;
+          }
+          total += tot;
+        }
+        if (tid == 0) sh.pref[nact] = total;
+        __syncthreads();
+        const int per = (total + kNetWaves - 1) / kNetWaves;
+        const int e0 = wave * per, e1 = min(e0 + per, total);
+        if (e0 < e1) {
+          int l = 0, h = nact;
+          while (h - l > 1) {
+            const int m = (l + h) >> 1;
+            if (sh.pref[m] <= e0) l = m; else h = m;
+          }
+          int r = l;
+          for (int ee = e0 + lane_id(); ee - lane_id() < e1; ee += kWave) {
+            if (ee < e1) {
+              while (r + 1 < nact && sh.pref[r + 1] <= ee) ++r;
+              const int32_t col = N.indices[sh.start[r] + (ee - sh.pref[r])];
+              if (col >= lo && col < hi) {
+                atomicAdd(&((sh.ids[r] < N.n_exc) ? sh.cE : sh.cI)[col - lo], 1u);
+                ++ev_local;
+              }
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+
+    // neuron update: exactly the oracle's FP32 operation order
+    uint32_t sbits = 0;
+    const float* iext = L.iext;
+#pragma unroll
+    for (int i = 0; i < kNPT; ++i) {
+      const int k = i * kNetThreads + tid;
+      if (k < R) {
+        const uint32_t ce = sh.cE[k], ci = sh.cI[k];
+        sh.cE[k] = 0u;
+        sh.cI[k] = 0u;
+        const float xe = (float)ce * N.w_exc;
+        const float xi = (float)ci * N.w_inh;
+        ge[i] = ge[i] * N.de + xe;
+        gi[i] = gi[i] * N.di + xi;
+        bool spk = false;
+        if (ref[i] > 0) {
+          ref[i] -= 1;
+        } else {
+          float ix = N.i_ext;
+          if (iext) ix = ix + iext[lo + k];
+          float I;
+          if (N.model == 0) I = ge[i] * (N.e_exc - V[i]) + gi[i] * (N.e_inh - V[i]) + ix;
+          else I = ge[i] + gi[i] + ix;
+          float v = V[i] + N.a * ((N.v_rest - V[i]) + N.r * I);
+          if (v > N.v_th) {
+            spk = true;
+            v = N.v_reset;
+            ref[i] = N.ref_steps;
+          }
+          V[i] = v;
+        }
+        if (spk) sbits |= 1u << i;
+        if (L.raster) L.raster[(size_t)s * N.n + lo + k] = spk ? 1 : 0;
+      }
+    }
+    // compaction of the own spikes, ascending in neuron id
+#pragma unroll
+    for (int i = 0; i < kNPT; ++i) {
+      const uint64_t m = __ballot((sbits >> i) & 1u);
+      if (lane_id() == 0) sh.wcnt[i * kNetWaves + wave] = __popcll(m);
+    }
+    __syncthreads();
+    if (wave == 0) {
+      const int v = sh.wcnt[lane_id()];
+      const int inc = wave_incl_scan(v);
+      sh.wcnt[lane_id()] = inc - v;
+      if (lane_id() == kWave - 1) sh.total = inc;
+    }
+    __syncthreads();
+    int32_t* out = N.lists + ((size_t)pout * N.n_wg + w) * N.range;
+#pragma unroll
+    for (int i = 0; i < kNPT; ++i) {
+      const uint64_t m = __ballot((sbits >> i) & 1u);
+      if ((sbits >> i) & 1u) st_coh(&out[sh.wcnt[i * kNetWaves + wave] + mask_rank(m)], lo + i * kNetThreads + tid);
+    }
+    if (tid == 0) st_coh(&N.lcount[pout * N.n_wg + w], sh.total);
+    vm_drain();
+    __syncthreads();
+    if (N.n_wg > 1 && tid == 0) st_coh(&N.flags[w], (uint32_t)(t + 1));
+  }
+
+#pragma unroll
+  for (int i = 0; i < kNPT; ++i) {
+    const int k = i * kNetThreads + tid;
+    if (k < R) {
+      N.V[lo + k] = V[i];
+      N.ge[lo + k] = ge[i];
+      N.gi[lo + k] = gi[i];
+      N.ref[lo + k] = ref[i];
+    }
+  }
+  // synaptic events delivered by this workgroup
+  const unsigned long long ev = wave_sum_u64(ev_local);
+  __shared__ unsigned long long ev_s[kNetWaves];
+  if (lane_id() == 0) ev_s[wave] = ev;
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long tot = 0;
+    for (int q = 0; q < kNetWaves; ++q) tot += ev_s[q];
+    N.events[w] += tot;
+  }
+  // spike count of the last step
+  if (L.counts && L.n_steps > 0 && w == 0 && !sh.abort_flag) {
+    const int64_t t_end = L.t0 + L.n_steps;
+    if (N.n_wg > 1) wait_flags(N, 0, t_end, args.spin_limit, sh);
+    __syncthreads();
+    const int par = (int)((t_end - 1) & 1);
+    int c = 0;
+    for (int i = tid; i < N.n_wg; i += kNetThreads) c += ld_coh(&N.lcount[par * N.n_wg + i]);
+    int tot;
+    block_excl_scan(c, sh.scan, &tot);
+    if (tid == 0) L.counts[L.n_steps - 1] = tot;
+  }
+}
+
+// Initial state: V0 from the hash (FP64 arithmetic, one rounding), zero
+// conductances, counters, lists, flags.
+__global__ void net_init_k(const NetDev* __restrict__ Np, float v0_lo, float v0_hi) {
+  const NetDev N = *Np;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < N.n) {
+    const uint32_t wd = hash_word(N.seed, kStreamV0, (uint32_t)i, 0u, 0u);
+    const double u = (double)(wd >> 8) * (1.0 / 16777216.0);
+    N.V[i] = (float)((double)v0_lo + ((double)v0_hi - (double)v0_lo) * u);
+    N.ge[i] = 0.f;
+    N.gi[i] = 0.f;
+    N.ref[i] = 0;
+  }
+  if (i < 2 * (int64_t)N.n_wg) N.lcount[i] = 0;
+  if (i < N.n_wg) {
+    N.flags[i] = 0u;
+    N.events[i] = 0ull;
+  }
+  if (i == 0) *N.error = 0u;
+}
+
+// Checkpoint export / import.
+__global__ void net_get_state_k(const NetDev* __restrict__ Np, int par, float* V, float* ge, float* gi, int32_t* ref,
+                                uint8_t* s) {
+  const NetDev N = *Np;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < N.n) {
+    V[i] = N.V[i];
+    ge[i] = N.ge[i];
+    gi[i] = N.gi[i];
+    ref[i] = N.ref[i];
+    // spike of neuron i in the last step: search the owner's list
+    const int w = (int)(i / N.range);
+    const int32_t* l = N.lists + ((size_t)par * N.n_wg + w) * N.range;
+    const int c = N.lcount[par * N.n_wg + w];
+    int a = 0, b = c;
+    while (a < b) {
+      const int m = (a + b) >> 1;
+      if (l[m] < i) a = m + 1; else b = m;
+    }
+    s[i] = (a < c && l[a] == i) ? 1 : 0;
+  }
+}
+
+__global__ void __launch_bounds__(kNetThreads) net_set_state_k(const NetDev* __restrict__ Np, int par, uint32_t step,
+                                                                const float* V, const float* ge, const float* gi,
+                                                                const int32_t* ref, const uint8_t* s) {
+  __shared__ int scan[kNetWaves + 1];
+  __shared__ int base_s;
+  const NetDev N = *Np;
+  const int w = blockIdx.x;
+  const int32_t lo = w * N.range, hi = min(lo + N.range, N.n);
+  if (threadIdx.x == 0) base_s = 0;
+  __syncthreads();
+  int32_t* out = N.lists + ((size_t)par * N.n_wg + w) * N.range;
+  for (int32_t k0 = lo; k0 < hi; k0 += kNetThreads) {
+    const int32_t k = k0 + threadIdx.x;
+    int on = 0;
+    if (k < hi) {
+      N.V[k] = V[k];
+      N.ge[k] = ge[k];
+      N.gi[k] = gi[k];
+      N.ref[k] = ref[k];
+      on = s[k] != 0;
+    }
+    int tot;
+    const int ex = block_excl_scan(on, scan, &tot);
+    if (on) out[base_s + ex] = k;
+    __syncthreads();
+    if (threadIdx.x == 0) base_s += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    N.lcount[par * N.n_wg + w] = base_s;
+    N.flags[w] = step;
+  }
+}
+
+__global__ void net_events_k(const NetDev* __restrict__ Np, unsigned long long* dst) {
+  const NetDev N = *Np;
+  unsigned long long s = 0;
+  for (int i = threadIdx.x; i < N.n_wg; i += blockDim.x) s += N.events[i];
+  s = wave_sum_u64(s);
+  __shared__ unsigned long long red[16];
+  if (lane_id() == 0) red[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int q = 0; q < (int)(blockDim.x / kWave); ++q) t += red[q];
+    *dst = t;
+  }
+}
+
+// ------------------------------------------------------------------ host side
+struct Layout {
+  int32_t n_wg, range, nb;
+  int64_t nnz_cap;
+  bool blk;
+  size_t off_hdr, off_V, off_ge, off_gi, off_ref, off_lists, off_lcount, off_flags, off_events, off_error,
+      off_indptr, off_indices, off_blkptr, total;
+};
+
+static int64_t nnz_upper_bound(const bp_net_desc* d) {
+  const double n = d->n;
+  const double per_row = n * 2.0 / ((double)d->max_gap + 1.0) + 1.0;
+  const double mean = n * per_row;
+  return (int64_t)(mean + 8.0 * sqrt(n * (per_row + 1.0)) + 4096.0);
+}
+
+static bp_status make_layout(const bp_net_desc* d, Layout* L) {
+  BP_REQUIRE(d != nullptr, "null descriptor");
+  BP_REQUIRE(d->n > 0, "n must be > 0");
+  BP_REQUIRE(d->n_exc >= 0 && d->n_exc <= d->n, "n_exc must be in [0, n]");
+  BP_REQUIRE(d->model == BP_COBA || d->model == BP_CUBA, "unknown model %d", d->model);
+  BP_REQUIRE(d->conn == BP_CONN_CSR || d->conn == BP_CONN_JIT, "unknown connectivity %d", d->conn);
+  BP_REQUIRE(d->max_gap >= 1, "max_gap must be >= 1");
+  BP_REQUIRE(d->block >= 0, "block must be >= 0");
+  BP_REQUIRE(d->dt > 0.f && d->tau_m > 0.f && d->tau_e > 0.f && d->tau_i > 0.f && d->tau_ref >= 0.f,
+             "time constants and dt must be positive");
+  BP_REQUIRE(d->max_wgs >= 0, "max_wgs must be >= 0");
+  const int32_t n = d->n;
+  int32_t range, n_wg;
+  if (n <= kRangeMax) {
+    range = n;
+    n_wg = 1;
+  } else {
+    const int32_t cap = d->max_wgs > 0 ? d->max_wgs : device_cu_count();
+    int64_t r = (n + (int64_t)cap - 1) / cap;
+    if (r < kNetThreads) r = kNetThreads;
+    if (d->block > 0 && d->block <= kRangeMax) r = (r + d->block - 1) / d->block * d->block;
+    if (r > kRangeMax) r = kRangeMax;
+    range = (int32_t)r;
+    n_wg = (int32_t)((n + r - 1) / r);
+  }
+  BP_REQUIRE(n_wg <= kMaxWgPerNet, "network too large: %d workgroups of %d neurons (max %d workgroups)", n_wg,
+             range, kMaxWgPerNet);
+  L->n_wg = n_wg;
+  L->range = range;
+  L->nb = d->block > 0 ? (int32_t)(((int64_t)n + d->block - 1) / d->block) : 1;
+  L->nnz_cap = d->conn == BP_CONN_CSR ? nnz_upper_bound(d) : 0;
+  L->blk = d->conn == BP_CONN_CSR && n_wg > 1 && d->block > 0;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes, 256);
+    return at;
+  };
+  L->off_hdr = take(sizeof(NetDev));
+  L->off_V = take((size_t)n * 4);
+  L->off_ge = take((size_t)n * 4);
+  L->off_gi = take((size_t)n * 4);
+  L->off_ref = take((size_t)n * 4);
+  L->off_lists = take((size_t)2 * n_wg * range * 4);
+  L->off_lcount = take((size_t)2 * n_wg * 4);
+  L->off_flags = take((size_t)n_wg * 4);
+  L->off_events = take((size_t)n_wg * 8);
+  L->off_error = take(4);
+  L->off_indptr = d->conn == BP_CONN_CSR ? take((size_t)(n + 1) * 4) : 0;
+  L->off_indices = d->conn == BP_CONN_CSR ? take((size_t)L->nnz_cap * 4) : 0;
+  L->off_blkptr = L->blk ? take((size_t)n * (L->nb + 1) * 4) : 0;
+  L->total = o;
+  return BP_OK;
+}
+
+}  // namespace bp
+
+using namespace bp;
+
+struct bp_net_s {
+  NetDev host;
+  NetDev* dev;
+  bp_net_desc desc;
+  Layout lay;
+  int64_t step;
+  int64_t nnz;
+  uint32_t magic;
+};
+
+static constexpr uint32_t kNetMagic = 0xB1A1B1A1u;
+
+static bp_status check_net(bp_net net) {
+  if (!net || net->magic != kNetMagic) return set_error(BP_ESTATE, "invalid or destroyed network handle");
+  return BP_OK;
+}
+
+static bp_status launch_batch(const bp_net* nets, int32_t n_nets, const int64_t* n_steps, int32_t* const* counts,
+                              uint8_t* const* rasters, const float* const* iext, hipStream_t st) {
+  BP_REQUIRE(n_nets >= 0 && n_nets <= kMaxBatch, "batch of %d nets (max %d)", n_nets, kMaxBatch);
+  BatchArgs args{};
+  args.spin_limit = kSpinLimit;
+  int32_t wg = 0;
+  bool coop = false;
+  for (int32_t i = 0; i < n_nets; ++i) {
+    bp_status s = check_net(nets[i]);
+    if (s) return s;
+    BP_REQUIRE(n_steps[i] >= 0 && n_steps[i] <= INT32_MAX, "n_steps out of range");
+    for (int32_t q = 0; q < i; ++q) BP_REQUIRE(nets[q] != nets[i], "a net appears twice in one batch");
+    if (n_steps[i] == 0) continue;
+    NetLaunch& L = args.e[args.n_nets++];
+    L.net = nets[i]->dev;
+    L.raster = rasters ? rasters[i] : nullptr;
+    L.counts = counts ? counts[i] : nullptr;
+    L.iext = iext ? iext[i] : nullptr;
+    L.t0 = nets[i]->step;
+    L.n_steps = (int32_t)n_steps[i];
+    L.wg_begin = wg;
+    L.n_wg = nets[i]->lay.n_wg;
+    wg += L.n_wg;
+    if (L.n_wg > 1) coop = true;
+  }
+  if (args.n_nets == 0) return BP_OK;
+  if (coop) {
+    void* kargs[] = {&args};
+    hipError_t e = hipLaunchCooperativeKernel((const void*)net_run_k, dim3(wg), dim3(kNetThreads), kargs, 0, st);
+    if (e != hipSuccess)
+      return set_error(BP_EDEVICE, "cooperative launch of %d workgroups failed: %s", wg, hipGetErrorString(e));
+  } else {
+    net_run_k<<<wg, kNetThreads, 0, st>>>(args);
+    BP_LAUNCHED("net_run_k");
+  }
+  for (int32_t i = 0; i < n_nets; ++i) nets[i]->step += n_steps[i];
+  return BP_OK;
+}
+
+extern "C" {
+
+bp_status bp_net_bytes(const bp_net_desc* d, size_t* bytes) {
+  Layout L;
+  bp_status s = make_layout(d, &L);
+  if (s) return s;
+  BP_REQUIRE(bytes != nullptr, "null bytes");
+  *bytes = L.total;
+  return BP_OK;
+}
+
+bp_status bp_create_net(const bp_net_desc* d, void* ws, size_t bytes, bp_stream stream, bp_net* out) {
+  Layout L;
+  bp_status s = make_layout(d, &L);
+  if (s) return s;
+  BP_REQUIRE(out != nullptr && ws != nullptr, "null pointer");
+  if (bytes < L.total) return set_error(BP_ENOMEM, "workspace too small: %zu < %zu bytes", bytes, L.total);
+  hipStream_t st = as_stream(stream);
+  bp_net net = new (std::nothrow) bp_net_s();
+  if (!net) return set_error(BP_ENOMEM, "host allocation failed");
+  char* base = (char*)ws;
+  NetDev& H = net->host;
+  H.model = d->model;
+  H.n = d->n;
+  H.n_exc = d->n_exc;
+  H.conn = d->conn;
+  H.K = d->max_gap;
+  H.block = d->block;
+  H.nb = L.nb;
+  H.ref_steps = (int32_t)floor((double)d->tau_ref / (double)d->dt + 0.5);
+  H.seed = d->seed;
+  H.w_exc = d->w_exc;
+  H.w_inh = d->w_inh;
+  H.de = (float)exp(-(double)d->dt / (double)d->tau_e);
+  H.di = (float)exp(-(double)d->dt / (double)d->tau_i);
+  H.a = (float)((double)d->dt / (double)d->tau_m);
+  H.v_rest = d->v_rest;
+  H.v_th = d->v_th;
+  H.v_reset = d->v_reset;
+  H.e_exc = d->e_exc;
+  H.e_inh = d->e_inh;
+  H.r = d->r;
+  H.i_ext = d->i_ext;
+  H.n_wg = L.n_wg;
+  H.range = L.range;
+  H.V = (float*)(base + L.off_V);
+  H.ge = (float*)(base + L.off_ge);
+  H.gi = (float*)(base + L.off_gi);
+  H.ref = (int32_t*)(base + L.off_ref);
+  H.lists = (int32_t*)(base + L.off_lists);
+  H.lcount = (int32_t*)(base + L.off_lcount);
+  H.flags = (uint32_t*)(base + L.off_flags);
+  H.events = (unsigned long long*)(base + L.off_events);
+  H.error = (uint32_t*)(base + L.off_error);
+  H.indptr = d->conn == BP_CONN_CSR ? (const int32_t*)(base + L.off_indptr) : nullptr;
+  H.indices = d->conn == BP_CONN_CSR ? (const int32_t*)(base + L.off_indices) : nullptr;
+  H.blkptr = L.blk ? (const int32_t*)(base + L.off_blkptr) : nullptr;
+  net->dev = (NetDev*)(base + L.off_hdr);
+  net->desc = *d;
+  net->lay = L;
+  net->step = 0;
+  net->nnz = 0;
+  net->magic = kNetMagic;
+  auto fail = [&](bp_status code) {
+    net->magic = 0;
+    delete net;
+    return code;
+  };
+  hipError_t e = hipMemcpyAsync(net->dev, &net->host, sizeof(NetDev), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return fail(set_error(BP_EDEVICE, "header copy failed: %s", hipGetErrorString(e)));
+  const int64_t init_n = d->n > 2 * L.n_wg ? d->n : 2 * L.n_wg;
+  net_init_k<<<(unsigned)((init_n + 255) / 256), 256, 0, st>>>(net->dev, d->v0_lo, d->v0_hi);
+  if ((e = hipGetLastError()) != hipSuccess)
+    return fail(set_error(BP_EDEVICE, "net_init_k launch failed: %s", hipGetErrorString(e)));
+  if (d->conn == BP_CONN_CSR) {
+    bp_jit_conn c{};
+    c.n_pre = d->n;
+    c.n_post = d->n;
+    c.max_gap = d->max_gap;
+    c.block = d->block;
+    c.seed = d->seed;
+    int32_t* indptr = (int32_t*)(base + L.off_indptr);
+    int32_t* indices = (int32_t*)(base + L.off_indices);
+    if ((s = bp_csr_count(&c, indptr, stream))) return fail(s);
+    int32_t nnz = 0;
+    if ((e = hipMemcpyAsync(&nnz, indptr + d->n, 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+      return fail(set_error(BP_EDEVICE, "reading nnz failed: %s", hipGetErrorString(e)));
+    if (nnz < 0) return fail(set_error(BP_EUNSUPPORTED, "more than 2^31-1 synapses"));
+    if (nnz > L.nnz_cap)
+      return fail(set_error(BP_ENOMEM, "nnz %d above the workspace bound %lld", nnz, (long long)L.nnz_cap));
+    net->nnz = nnz;
+    if ((s = bp_csr_fill(&c, indptr, indices, stream))) return fail(s);
+    if (L.blk && (s = launch_tile_index(indptr, indices, d->n, d->block, L.nb, (int32_t*)(base + L.off_blkptr), st)))
+      return fail(s);
+  }
+  *out = net;
+  return BP_OK;
+}
+
+bp_status bp_run(bp_net net, int64_t n_steps, const float* i_ext_vec, uint8_t* raster, int32_t* counts,
+                 bp_stream stream) {
+  bp_status s = check_net(net);
+  if (s) return s;
+  BP_REQUIRE(n_steps >= 0, "negative n_steps");
+  return launch_batch(&net, 1, &n_steps, &counts, &raster, &i_ext_vec, as_stream(stream));
+}
+
+bp_status bp_step(bp_net net, const float* i_ext_vec, uint8_t* spikes, bp_stream stream) {
+  return bp_run(net, 1, i_ext_vec, spikes, nullptr, stream);
+}
+
+bp_status bp_run_batch(const bp_net* nets, int32_t n_nets, const int64_t* n_steps, int32_t* const* counts,
+                       bp_stream stream) {
+  BP_REQUIRE(n_nets >= 0, "negative n_nets");
+  if (n_nets == 0) return BP_OK;
+  BP_REQUIRE(nets && n_steps, "null pointer");
+  return launch_batch(nets, n_nets, n_steps, counts, nullptr, nullptr, as_stream(stream));
+}
+
+bp_status bp_net_get_info(bp_net net, bp_net_info* info) {
+  bp_status s = check_net(net);
+  if (s) return s;
+  BP_REQUIRE(info != nullptr, "null info");
+  info->n = net->desc.n;
+  info->n_wg = net->lay.n_wg;
+  info->wg_range = net->lay.range;
+  info->nnz = net->nnz;
+  info->step = net->step;
+  info->bytes_used = net->lay.total;
+  info->events_dev = (const uint64_t*)net->host.events;
+  info->error_dev = net->host.error;
+  return BP_OK;
+}
+
+bp_status bp_net_events(bp_net net, uint64_t* dst, bp_stream stream) {
+  bp_status s = check_net(net);
+  if (s) return s;
+  BP_REQUIRE(dst != nullptr, "null dst");
+  net_events_k<<<1, 256, 0, as_stream(stream)>>>(net->dev, (unsigned long long*)dst);
+  BP_LAUNCHED("net_events_k");
+  return BP_OK;
+}
+
+size_t bp_state_bytes(bp_net net) {
+  if (check_net(net)) return 0;
+  const size_t n = (size_t)net->desc.n;
+  return n * (4 + 4 + 4 + 4 + 1);
+}
+
+bp_status bp_get_state(bp_net net, void* dst, size_t bytes, bp_stream stream) {
+  bp_status s = check_net(net);
+  if (s) return s;
+  BP_REQUIRE(dst != nullptr, "null dst");
+  BP_REQUIRE(bytes >= bp_state_bytes(net), "state buffer too small");
+  const int64_t n = net->desc.n;
+  char* p = (char*)dst;
+  const int par = (int)((net->step + 1) & 1);
+  net_get_state_k<<<(unsigned)((n + 255) / 256), 256, 0, as_stream(stream)>>>(
+      net->dev, par, (float*)p, (float*)(p + 4 * n), (float*)(p + 8 * n), (int32_t*)(p + 12 * n), (uint8_t*)(p + 16 * n));
+  BP_LAUNCHED("net_get_state_k");
+  return BP_OK;
+}
+
+bp_status bp_set_state(bp_net net, const void* src, size_t bytes, int64_t step, bp_stream stream) {
+  bp_status s = check_net(net);
+  if (s) return s;
+  BP_REQUIRE(src != nullptr, "null src");
+  BP_REQUIRE(bytes >= bp_state_bytes(net), "state buffer too small");
+  BP_REQUIRE(step >= 0 && step <= 0xFFFFFFFFLL, "step out of range");
+  const int64_t n = net->desc.n;
+  const char* p = (const char*)src;
+  const int par = (int)((step + 1) & 1);
+  net_set_state_k<<<net->lay.n_wg, kNetThreads, 0, as_stream(stream)>>>(
+      net->dev, par, (uint32_t)step, (const float*)p, (const float*)(p + 4 * n), (const float*)(p + 8 * n),
+      (const int32_t*)(p + 12 * n), (const uint8_t*)(p + 16 * n));
+  BP_LAUNCHED("net_set_state_k");
+  net->step = step;
+  return BP_OK;
+}
+
+bp_status bp_destroy_net(bp_net net) {
+  bp_status s = check_net(net);
+  if (s) return s;
+  net->magic = 0;
+  delete net;
+  return BP_OK;
+}
+
+}  // extern "C"
