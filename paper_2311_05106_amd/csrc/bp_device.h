@@ -148,14 +148,17 @@ __device__ __forceinline__ int mask_rank(uint64_t mask) {
   return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Inclusive prefix sum across the wave.
+// Inclusive prefix sum across the wave with DPP: shifts by 1, 2, 4, 8 inside
+// each row of 16 lanes, then the last lane of row 0 / 2 is added to rows 1 / 3
+// (row_bcast:15) and the last lane of row 1 to rows 2 and 3 (row_bcast:31).
+// Lanes without a source keep the `old` operand, 0.
 __device__ __forceinline__ int wave_incl_scan(int v) {
-  const int l = lane_id();
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const int t = __shfl_up(v, o, kWave);
-    if (l >= o) v += t;
-  }
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15 -> rows 1, 3
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31 -> rows 2, 3
   return v;
 }
 
@@ -195,6 +198,38 @@ __device__ __forceinline__ int block_excl_scan(int v, int* scratch, int* total) 
   return r;
 }
 
+// Two exclusive prefix sums over the workgroup sharing one set of barriers.
+// `scratch` holds at least 2 * (blockDim.x / 64 + 1) ints of LDS.
+__device__ __forceinline__ void block_excl_scan2(int a, int b, int* scratch, int* ea, int* eb, int* ta, int* tb) {
+  const int l = lane_id(), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  const int ia = wave_incl_scan(a), ib = wave_incl_scan(b);
+  int* sa = scratch;
+  int* sb = scratch + nw + 1;
+  if (l == kWave - 1) {
+    sa[w] = ia;
+    sb[w] = ib;
+  }
+  __syncthreads();
+  if (w == 0) {
+    const int xa = (l < nw) ? sa[l] : 0, xb = (l < nw) ? sb[l] : 0;
+    const int ya = wave_incl_scan(xa), yb = wave_incl_scan(xb);
+    if (l < nw) {
+      sa[l] = ya - xa;
+      sb[l] = yb - xb;
+    }
+    if (l == nw - 1) {
+      sa[nw] = ya;
+      sb[nw] = yb;
+    }
+  }
+  __syncthreads();
+  *ea = sa[w] + ia - a;
+  *eb = sb[w] + ib - b;
+  *ta = sa[nw];
+  *tb = sb[nw];
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // Device-coherent accesses for data exchanged between workgroups of one
 // launch (possibly on different XCDs, whose L2 caches are not coherent with
@@ -214,6 +249,12 @@ __device__ __forceinline__ void st_coh(int* p, int v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_coh(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_coh64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coh64(uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // Wait until every vector memory operation this wave issued has completed

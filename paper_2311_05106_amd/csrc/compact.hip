@@ -63,7 +63,8 @@ __global__ void __launch_bounds__(kCompactThreads) compact_write_k(const uint8_t
   while (bits) {
     const int q = __ffs(bits) - 1;
     bits &= bits - 1;
-    ids[off++] = (int32_t)(base + q);
+    if (off < n) ids[off] = (int32_t)(base + q);
+    ++off;
   }
   if (blockIdx.x == (unsigned)(ntiles - 1) && threadIdx.x == 0) *count = base_s + tile_tot;
 }

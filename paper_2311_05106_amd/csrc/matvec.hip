@@ -60,7 +60,8 @@ __device__ __forceinline__ int compact_piece(const uint8_t* __restrict__ ev, int
   while (bits) {
     const int q = __ffs(bits) - 1;
     bits &= bits - 1;
-    sh.ids[off++] = r0 + base + q;
+    if (off < kMvPiece) sh.ids[off] = r0 + base + q;
+    ++off;
   }
   __syncthreads();
   return tot;

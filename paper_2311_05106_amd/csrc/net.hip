@@ -5,20 +5,29 @@
 //
 // Each workgroup owns a contiguous range of neurons: their V, ge, gi and
 // refractory counters stay in registers for the whole launch.  One step:
-//   1. wait until every workgroup of the net has published the spikes of the
-//      previous step (per-workgroup step flags, device-coherent loads);
-//   2. gather the compacted spike lists of all workgroups;
-//   3. for every firing presynaptic row, accumulate the targets that fall in
+//   1. gather the spikes of the previous step from every workgroup of the
+//      net (see the record format below);
+//   2. for every firing presynaptic row, accumulate the targets that fall in
 //      the own range into LDS integer counters (excitatory and inhibitory
 //      separately): stored CSR segments are streamed, JIT rows are
 //      regenerated per post block from the seed;
-//   4. update the own neurons (synaptic decay + input, COBA/CUBA current,
+//   3. update the own neurons (synaptic decay + input, COBA/CUBA current,
 //      forward Euler, refractoriness, threshold, reset);
-//   5. compact the own spikes (wave ballots + prefix over waves, ascending),
-//      store them with device-coherent stores and publish the step flag.
-// Nets small enough for one workgroup skip the flags.  Several nets run in
-// one launch (continuous batching): the grid is the concatenation of their
-// workgroup ranges and each net synchronizes only its own workgroups.
+//   4. compact the own spikes (wave ballots + prefix over waves, ascending)
+//      and publish them.
+// Spike records: per workgroup and step parity an array of 64-bit slots,
+// slot 0 = (tag, count), slot 1 + q = (tag, neuron id), tag = step + 1 in the
+// high word.  Each slot is written with one device-coherent 64-bit store, so
+// a reader accepts a slot only when its tag is the step it waits for: the
+// writer never waits for its stores to land.  The writer pushes the header
+// and the first 15 ids into a private inbox of every other workgroup of the
+// net, so each reader polls only its own inbox lines (no line is polled by
+// many workgroups) and needs one memory round trip once the data is there;
+// longer lists are completed from the writer's own record.  A one-workgroup
+// net keeps its own list in LDS between steps.
+// Several nets run in one launch (continuous batching): the grid is the
+// concatenation of their workgroup ranges and each net exchanges records only
+// among its own workgroups.
 #include <math.h>
 #include <string.h>
 
@@ -29,12 +38,14 @@
 
 namespace bp {
 
-constexpr int kNetThreads = 512;
+constexpr int kNetThreads = 1024;
 constexpr int kNetWaves = kNetThreads / kWave;
-constexpr int kNPT = 8;                        // neurons per thread
+constexpr int kNPT = 4;                        // neurons per thread
 constexpr int kRangeMax = kNetThreads * kNPT;  // neurons per workgroup
-constexpr int kIdBatch = 2048;                 // firing rows staged per pass
-constexpr int kMaxWgPerNet = 1024;
+constexpr int kIdBatch = 4096;                 // firing rows staged per pass
+constexpr int kMaxWgPerNet = 512;  // one gathering thread per source
+constexpr int kInbox = 16;         // slots per (destination, source) inbox: header + 15 ids
+constexpr int kSpec = 7;                    // ids loaded together with a header
 constexpr int kMaxBatch = 48;
 constexpr uint32_t kSpinLimit = 1u << 22;
 
@@ -50,9 +61,8 @@ struct NetDev {
   const int32_t* indptr;
   const int32_t* indices;
   const int32_t* blkptr;  // [n][nb + 1] block index of the stored rows, or null
-  int32_t* lists;         // [2][n_wg][range] spike ids by step parity
-  int32_t* lcount;        // [2][n_wg]
-  uint32_t* flags;        // [n_wg] steps completed
+  uint64_t* rec;          // [2][n_wg][range + 1] spike records by step parity
+  uint64_t* inbox;        // [2][n_wg dst][n_wg src][kInbox] copies pushed to each reader
   unsigned long long* events;  // [n_wg] synaptic events delivered
   uint32_t* error;
 };
@@ -79,21 +89,65 @@ struct NetShared {
   uint32_t cE[kRangeMax];
   uint32_t cI[kRangeMax];
   int ids[kIdBatch];
+  int own[kRangeMax];  // own spikes of this step, ascending
   int pref[kIdBatch + 1];
   int start[kIdBatch];
   int srcpref[kMaxWgPerNet + 1];
+  int expref[kMaxWgPerNet + 1];
   int wcnt[kNPT * kNetWaves];
-  int scan[kNetWaves + 1];
+  int scan[2 * (kNetWaves + 1)];
   int abort_flag;
   int total;
+  int nloc;  // own spikes of the last step kept in ids[] (one-workgroup nets), -1 if not
 };
 
-// Wait (bounded) until flags[i] >= t for every workgroup i != self.
-__device__ __forceinline__ void wait_flags(const NetDev& N, int self, int64_t t, uint32_t spin_limit, NetShared& sh) {
-  for (int i = threadIdx.x; i < N.n_wg; i += kNetThreads) {
-    if (i == self) continue;
+__device__ __forceinline__ uint64_t pack(uint32_t tag, uint32_t v) { return ((uint64_t)tag << 32) | v; }
+__device__ __forceinline__ uint32_t tag_of(uint64_t s) { return (uint32_t)(s >> 32); }
+
+__device__ __forceinline__ uint64_t* record(const NetDev& N, int par, int w) {
+  return N.rec + ((size_t)par * N.n_wg + w) * (size_t)(N.range + 1);
+}
+
+__device__ __forceinline__ uint64_t* inbox(const NetDev& N, int par, int dst, int src) {
+  return N.inbox + (((size_t)par * N.n_wg + dst) * N.n_wg + src) * kInbox;
+}
+
+// Load slot q of a record until it carries `tag` (bounded).
+__device__ __forceinline__ uint64_t wait_slot(const uint64_t* r, int q, uint32_t tag, uint64_t first, uint32_t spin_limit,
+                                              const NetDev& N, NetShared& sh) {
+  uint64_t v = first;
+  uint32_t spins = 0;
+  while (tag_of(v) != tag) {
+    if (++spins > spin_limit) {
+      atomicOr(N.error, 1u);
+      sh.abort_flag = 1;
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    v = ld_coh64(&r[q]);
+  }
+  return v;
+}
+
+// Gathers the spikes of the previous step (records tagged `tag` of parity
+// `par`) into sh.ids, in passes of kIdBatch; returns the total, calls
+// `process(n)` for every pass of n ids.
+template <class Process>
+__device__ __forceinline__ int gather_and_process(const NetDev& N, int self, int par, uint32_t tag,
+                                                  uint32_t spin_limit, NetShared& sh, Process&& process) {
+  const int tid = threadIdx.x;
+  const bool src = tid < N.n_wg;
+  // several workgroups: header and first ids from the own inbox; one
+  // workgroup: its own record (a one-workgroup net has no inbox)
+  const uint64_t* r = !src ? nullptr : (N.n_wg > 1 ? inbox(N, par, self, tid) : record(N, par, tid));
+  uint64_t h = 0, v[kSpec];
+  if (src) {
     uint32_t spins = 0;
-    while ((int32_t)(ld_coh(&N.flags[i]) - (uint32_t)t) < 0) {
+    while (true) {
+      h = ld_coh64(&r[0]);
+#pragma unroll
+      for (int q = 0; q < kSpec; ++q) v[q] = ld_coh64(&r[1 + q]);
+      if (tag_of(h) == tag) break;
       if (++spins > spin_limit) {
         atomicOr(N.error, 1u);
         sh.abort_flag = 1;
@@ -102,6 +156,53 @@ __device__ __forceinline__ void wait_flags(const NetDev& N, int self, int64_t t,
       __builtin_amdgcn_s_sleep(1);
     }
   }
+  const int cnt = (src && tag_of(h) == tag) ? min((int)(uint32_t)h, N.range) : 0;
+  if (src) {
+#pragma unroll
+    for (int q = 0; q < kSpec; ++q)
+      if (q < cnt) v[q] = wait_slot(r, 1 + q, tag, v[q], spin_limit, N, sh);
+  }
+  const int extra = cnt > kSpec ? cnt - kSpec : 0;
+  int cpos, epos, A, E;
+  block_excl_scan2(cnt, extra, sh.scan, &cpos, &epos, &A, &E);
+  if (src) {
+    sh.srcpref[tid] = cpos;
+    sh.expref[tid] = epos;
+  }
+  if (tid == 0) {
+    sh.srcpref[N.n_wg] = A;
+    sh.expref[N.n_wg] = E;
+  }
+  __syncthreads();
+  if (sh.abort_flag) return -1;
+  for (int q0 = 0; q0 < A; q0 += kIdBatch) {
+    const int n = min(kIdBatch, A - q0);
+#pragma unroll
+    for (int q = 0; q < kSpec; ++q) {
+      const int pos = cpos + q - q0;
+      if (q < cnt && pos >= 0 && pos < n) sh.ids[pos] = (int)(uint32_t)v[q];
+    }
+    // ids beyond the first kSpec of each record, spread over the workgroup
+    for (int e = tid; e < E; e += kNetThreads) {
+      int l = 0, hh = N.n_wg;  // largest l with expref[l] <= e
+      while (hh - l > 1) {
+        const int m = (l + hh) >> 1;
+        if (sh.expref[m] <= e) l = m; else hh = m;
+      }
+      const int q = kSpec + (e - sh.expref[l]);
+      const int pos = sh.srcpref[l] + q - q0;
+      const int cnt_l = sh.srcpref[l + 1] - sh.srcpref[l];
+      if (pos >= 0 && pos < n && q < cnt_l && q < N.range) {
+        const uint64_t* rr = (N.n_wg > 1 && q < kInbox - 1) ? inbox(N, par, self, l) : record(N, par, l);
+        const uint64_t x = wait_slot(rr, 1 + q, tag, ld_coh64(&rr[1 + q]), spin_limit, N, sh);
+        sh.ids[pos] = (int)(uint32_t)x;
+      }
+    }
+    __syncthreads();
+    if (sh.abort_flag) return -1;
+    process(n);
+  }
+  return A;
 }
 
 __global__ void __launch_bounds__(kNetThreads) net_run_k(BatchArgs args) {
@@ -135,7 +236,10 @@ __global__ void __launch_bounds__(kNetThreads) net_run_k(BatchArgs args) {
     sh.cE[k] = 0u;
     sh.cI[k] = 0u;
   }
-  if (tid == 0) sh.abort_flag = 0;
+  if (tid == 0) {
+    sh.abort_flag = 0;
+    sh.nloc = -1;
+  }
   __syncthreads();
 
   const int32_t B = N.block;
@@ -144,129 +248,121 @@ __global__ void __launch_bounds__(kNetThreads) net_run_k(BatchArgs args) {
   const int32_t nbt = b_hi - b_lo + 1;
   unsigned long long ev_local = 0;
 
+  // accumulate the targets of the staged firing rows sh.ids[0, nact)
+  auto propagate = [&](int nact) {
+    if (N.conn == 1) {
+      const int items = nact * nbt;
+      for (int it = tid; it < items; it += kNetThreads) {
+        const int ai = it / nbt;
+        const uint32_t b = (uint32_t)(b_lo + it % nbt);
+        const uint32_t j = (uint32_t)sh.ids[ai];
+        uint32_t* cnt = ((int32_t)j < N.n_exc) ? sh.cE : sh.cI;
+        gen_block(N.seed, (uint32_t)N.K, N.n, B, j, b, lo, hi, [&](int32_t pos, uint32_t) {
+          atomicAdd(&cnt[pos - lo], 1u);
+          ++ev_local;
+        });
+      }
+    } else {
+      int total = 0;
+      for (int base = 0; base < nact; base += kNetThreads) {
+        const int i = base + tid;
+        int st = 0, len = 0;
+        if (i < nact) {
+          const int32_t j = sh.ids[i];
+          if (N.n_wg == 1) {
+            st = N.indptr[j];
+            len = N.indptr[j + 1] - st;
+          } else if (N.blkptr) {
+            const int32_t* bp = N.blkptr + (size_t)j * (N.nb + 1);
+            st = bp[b_lo];
+            len = bp[b_hi + 1] - st;
+          } else {
+            int32_t l = N.indptr[j], h = N.indptr[j + 1];
+            while (l < h) {
+              const int32_t m = (l + h) >> 1;
+              if (N.indices[m] < lo) l = m + 1; else h = m;
+            }
+            st = l;
+            h = N.indptr[j + 1];
+            while (l < h) {
+              const int32_t m = (l + h) >> 1;
+              if (N.indices[m] < hi) l = m + 1; else h = m;
+            }
+            len = l - st;
+          }
+        }
+        int tot;
+        const int ex = block_excl_scan(len, sh.scan, &tot);
+        if (i < nact) {
+          sh.pref[i] = total + ex;
+          sh.start[i] = st;
+        }
+        total += tot;
+      }
+      if (tid == 0) sh.pref[nact] = total;
+      __syncthreads();
+      const int per = (total + kNetWaves - 1) / kNetWaves;
+      const int e0 = wave * per, e1 = min(e0 + per, total);
+      if (e0 < e1) {
+        int l = 0, h = nact;
+        while (h - l > 1) {
+          const int m = (l + h) >> 1;
+          if (sh.pref[m] <= e0) l = m; else h = m;
+        }
+        int r = l;
+        for (int ee = e0 + lane_id(); ee - lane_id() < e1; ee += kWave) {
+          if (ee < e1) {
+            while (r + 1 < nact && sh.pref[r + 1] <= ee) ++r;
+            const int32_t col = N.indices[sh.start[r] + (ee - sh.pref[r])];
+            if (col >= lo && col < hi) {
+              atomicAdd(&((sh.ids[r] < N.n_exc) ? sh.cE : sh.cI)[col - lo], 1u);
+              ++ev_local;
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  };
+
   for (int32_t s = 0; s < L.n_steps; ++s) {
     const int64_t t = L.t0 + s;
     const int pin = (int)((t + 1) & 1);  // parity of step t-1
     const int pout = (int)(t & 1);
-    if (N.n_wg > 1) wait_flags(N, w, t, args.spin_limit, sh);
-    __syncthreads();
-    if (sh.abort_flag) break;
-
-    // spike counts of step t-1 per workgroup -> prefix
-    int A = 0;
-    for (int base = 0; base < N.n_wg; base += kNetThreads) {
-      const int i = base + tid;
-      const int c = (i < N.n_wg) ? ld_coh(&N.lcount[pin * N.n_wg + i]) : 0;
-      int tot;
-      const int ex = block_excl_scan(c, sh.scan, &tot);
-      if (i < N.n_wg) sh.srcpref[i] = A + ex;
-      A += tot;
+    int A;
+    if (sh.nloc >= 0) {
+      A = sh.nloc;  // own list of the last step, still in LDS
+      if (A > 0) propagate(A);
+    } else {
+      A = gather_and_process(N, w, pin, (uint32_t)t, args.spin_limit, sh, propagate);
+      if (A < 0) break;
     }
-    if (tid == 0) sh.srcpref[N.n_wg] = A;
-    __syncthreads();
     if (w == 0 && tid == 0 && L.counts && s > 0) L.counts[s - 1] = A;
-
-    for (int q0 = 0; q0 < A; q0 += kIdBatch) {
-      const int nact = min(kIdBatch, A - q0);
-      for (int q = tid; q < nact; q += kNetThreads) {
-        const int g = q0 + q;
-        int l = 0, h = N.n_wg;  // largest l with srcpref[l] <= g
-        while (h - l > 1) {
-          const int m = (l + h) >> 1;
-          if (sh.srcpref[m] <= g) l = m; else h = m;
-        }
-        sh.ids[q] = ld_coh(&N.lists[((size_t)pin * N.n_wg + l) * N.range + (g - sh.srcpref[l])]);
-      }
-      __syncthreads();
-      if (N.conn == 1) {
-        // regenerate the blocks of each firing row that overlap [lo, hi)
-        const int items = nact * nbt;
-        for (int it = tid; it < items; it += kNetThreads) {
-          const int ai = it / nbt;
-          const uint32_t b = (uint32_t)(b_lo + it % nbt);
-          const uint32_t j = (uint32_t)sh.ids[ai];
-          uint32_t* cnt = ((int32_t)j < N.n_exc) ? sh.cE : sh.cI;
-          gen_block(N.seed, (uint32_t)N.K, N.n, B, j, b, lo, hi, [&](int32_t pos, uint32_t) {
-            atomicAdd(&cnt[pos - lo], 1u);
-            ++ev_local;
-          });
-        }
-      } else {
-        // stored rows: segment of each firing row inside [lo, hi)
-        int total = 0;
-        for (int base = 0; base < nact; base += kNetThreads) {
-          const int i = base + tid;
-          int st = 0, len = 0;
-          if (i < nact) {
-            const int32_t j = sh.ids[i];
-            if (N.n_wg == 1) {
-              st = N.indptr[j];
-              len = N.indptr[j + 1] - st;
-            } else if (N.blkptr) {
-              const int32_t* bp = N.blkptr + (size_t)j * (N.nb + 1);
-              st = bp[b_lo];
-              len = bp[b_hi + 1] - st;
-            } else {
-              int32_t l = N.indptr[j], h = N.indptr[j + 1];
-              while (l < h) {
-                const int32_t m = (l + h) >> 1;
-                if (N.indices[m] < lo) l = m + 1; else h = m;
-              }
-              st = l;
-              h = N.indptr[j + 1];
-              while (l < h) {
-                const int32_t m = (l + h) >> 1;
-                if (N.indices[m] < hi) l = m + 1; else h = m;
-              }
-              len = l - st;
-            }
-          }
-          int tot;
-          const int ex = block_excl_scan(len, sh.scan, &tot);
-          if (i < nact) {
-            sh.pref[i] = total + ex;
-            sh.start[i] = st;
-          }
-          total += tot;
-        }
-        if (tid == 0) sh.pref[nact] = total;
-        __syncthreads();
-        const int per = (total + kNetWaves - 1) / kNetWaves;
-        const int e0 = wave * per, e1 = min(e0 + per, total);
-        if (e0 < e1) {
-          int l = 0, h = nact;
-          while (h - l > 1) {
-            const int m = (l + h) >> 1;
-            if (sh.pref[m] <= e0) l = m; else h = m;
-          }
-          int r = l;
-          for (int ee = e0 + lane_id(); ee - lane_id() < e1; ee += kWave) {
-            if (ee < e1) {
-              while (r + 1 < nact && sh.pref[r + 1] <= ee) ++r;
-              const int32_t col = N.indices[sh.start[r] + (ee - sh.pref[r])];
-              if (col >= lo && col < hi) {
-                atomicAdd(&((sh.ids[r] < N.n_exc) ? sh.cE : sh.cI)[col - lo], 1u);
-                ++ev_local;
-              }
-            }
-          }
-        }
-      }
-      __syncthreads();
-    }
 
     // neuron update: exactly the oracle's FP32 operation order
     uint32_t sbits = 0;
     const float* iext = L.iext;
+    uint32_t ce[kNPT], ci[kNPT];
+#pragma unroll
+    for (int i = 0; i < kNPT; ++i) {
+      const int k = i * kNetThreads + tid;
+      ce[i] = k < R ? sh.cE[k] : 0u;
+      ci[i] = k < R ? sh.cI[k] : 0u;
+    }
 #pragma unroll
     for (int i = 0; i < kNPT; ++i) {
       const int k = i * kNetThreads + tid;
       if (k < R) {
-        const uint32_t ce = sh.cE[k], ci = sh.cI[k];
         sh.cE[k] = 0u;
         sh.cI[k] = 0u;
-        const float xe = (float)ce * N.w_exc;
-        const float xi = (float)ci * N.w_inh;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kNPT; ++i) {
+      const int k = i * kNetThreads + tid;
+      if (k < R) {
+        const float xe = (float)ce[i] * N.w_exc;
+        const float xi = (float)ci[i] * N.w_inh;
         ge[i] = ge[i] * N.de + xe;
         gi[i] = gi[i] * N.di + xi;
         bool spk = false;
@@ -304,16 +400,36 @@ __global__ void __launch_bounds__(kNetThreads) net_run_k(BatchArgs args) {
       if (lane_id() == kWave - 1) sh.total = inc;
     }
     __syncthreads();
-    int32_t* out = N.lists + ((size_t)pout * N.n_wg + w) * N.range;
+    const uint32_t tag = (uint32_t)(t + 1);
+    const int total = min(sh.total, R);
+    const bool keep_local = N.n_wg == 1 && total <= kIdBatch;
 #pragma unroll
     for (int i = 0; i < kNPT; ++i) {
       const uint64_t m = __ballot((sbits >> i) & 1u);
-      if ((sbits >> i) & 1u) st_coh(&out[sh.wcnt[i * kNetWaves + wave] + mask_rank(m)], lo + i * kNetThreads + tid);
+      if ((sbits >> i) & 1u) {
+        const int pos = sh.wcnt[i * kNetWaves + wave] + mask_rank(m);
+        const int k = lo + i * kNetThreads + tid;
+        if (pos < R) sh.own[pos] = k;
+        if (keep_local && pos < total) sh.ids[pos] = k;
+      }
     }
-    if (tid == 0) st_coh(&N.lcount[pout * N.n_wg + w], sh.total);
-    vm_drain();
     __syncthreads();
-    if (N.n_wg > 1 && tid == 0) st_coh(&N.flags[w], (uint32_t)(t + 1));
+    // full own record (persistence, long lists) ...
+    uint64_t* out = record(N, pout, w);
+    for (int q = tid; q < total; q += kNetThreads) st_coh64(&out[1 + q], pack(tag, (uint32_t)sh.own[q]));
+    if (tid == 0) st_coh64(&out[0], pack(tag, (uint32_t)total));
+    // ... and the header + first ids pushed to every reader's inbox
+    if (N.n_wg > 1) {
+      const int m = min(total, kInbox - 1) + 1;
+      const int items = N.n_wg * m;
+      for (int x = tid; x < items; x += kNetThreads) {
+        const int d = x / m, q = x - d * m;
+        const uint64_t v = q == 0 ? pack(tag, (uint32_t)total) : pack(tag, (uint32_t)sh.own[q - 1]);
+        st_coh64(inbox(N, pout, d, w) + q, v);
+      }
+    }
+    if (tid == 0) sh.nloc = keep_local ? total : -1;
+    __syncthreads();
   }
 
 #pragma unroll
@@ -336,14 +452,16 @@ __global__ void __launch_bounds__(kNetThreads) net_run_k(BatchArgs args) {
     for (int q = 0; q < kNetWaves; ++q) tot += ev_s[q];
     N.events[w] += tot;
   }
-  // spike count of the last step
+  // spike count of the last step: the headers of every workgroup
   if (L.counts && L.n_steps > 0 && w == 0 && !sh.abort_flag) {
     const int64_t t_end = L.t0 + L.n_steps;
-    if (N.n_wg > 1) wait_flags(N, 0, t_end, args.spin_limit, sh);
-    __syncthreads();
     const int par = (int)((t_end - 1) & 1);
     int c = 0;
-    for (int i = tid; i < N.n_wg; i += kNetThreads) c += ld_coh(&N.lcount[par * N.n_wg + i]);
+    if (tid < N.n_wg) {
+      const uint64_t* r = N.n_wg > 1 ? inbox(N, par, 0, tid) : record(N, par, tid);
+      const uint64_t hh = wait_slot(r, 0, (uint32_t)t_end, ld_coh64(&r[0]), args.spin_limit, N, sh);
+      if (tag_of(hh) == (uint32_t)t_end) c = (int)(uint32_t)hh;
+    }
     int tot;
     block_excl_scan(c, sh.scan, &tot);
     if (tid == 0) L.counts[L.n_steps - 1] = tot;
@@ -351,7 +469,8 @@ __global__ void __launch_bounds__(kNetThreads) net_run_k(BatchArgs args) {
 }
 
 // Initial state: V0 from the hash (FP64 arithmetic, one rounding), zero
-// conductances, counters, lists, flags.
+// conductances and counters; every record slot invalid, except the headers of
+// the initial (empty) spike set of step -1, tagged 0 in parity 1.
 __global__ void net_init_k(const NetDev* __restrict__ Np, float v0_lo, float v0_hi) {
   const NetDev N = *Np;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -363,17 +482,27 @@ __global__ void net_init_k(const NetDev* __restrict__ Np, float v0_lo, float v0_
     N.gi[i] = 0.f;
     N.ref[i] = 0;
   }
-  if (i < 2 * (int64_t)N.n_wg) N.lcount[i] = 0;
-  if (i < N.n_wg) {
-    N.flags[i] = 0u;
-    N.events[i] = 0ull;
+  const int64_t per = (int64_t)N.range + 1;
+  const int64_t slots = 2 * (int64_t)N.n_wg * per;
+  if (i < slots) {
+    const bool hdr1 = (i / per) >= N.n_wg && (i % per) == 0;
+    N.rec[i] = hdr1 ? 0ull : (0xFFFFFFFFull << 32);
   }
+  if (N.n_wg > 1) {
+    const int64_t ib = 2 * (int64_t)N.n_wg * N.n_wg * kInbox;
+    if (i < ib) {
+      const bool hdr1 = (i / ((int64_t)N.n_wg * N.n_wg * kInbox)) == 1 && (i % kInbox) == 0;
+      N.inbox[i] = hdr1 ? 0ull : (0xFFFFFFFFull << 32);
+    }
+  }
+  if (i < N.n_wg) N.events[i] = 0ull;
   if (i == 0) *N.error = 0u;
 }
 
-// Checkpoint export / import.
-__global__ void net_get_state_k(const NetDev* __restrict__ Np, int par, float* V, float* ge, float* gi, int32_t* ref,
-                                uint8_t* s) {
+// Checkpoint export: state and the spikes of the last step (records of parity
+// par, tagged `tag`).
+__global__ void net_get_state_k(const NetDev* __restrict__ Np, int par, uint32_t tag, float* V, float* ge, float* gi,
+                                int32_t* ref, uint8_t* s) {
   const NetDev N = *Np;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < N.n) {
@@ -381,19 +510,21 @@ __global__ void net_get_state_k(const NetDev* __restrict__ Np, int par, float* V
     ge[i] = N.ge[i];
     gi[i] = N.gi[i];
     ref[i] = N.ref[i];
-    // spike of neuron i in the last step: search the owner's list
     const int w = (int)(i / N.range);
-    const int32_t* l = N.lists + ((size_t)par * N.n_wg + w) * N.range;
-    const int c = N.lcount[par * N.n_wg + w];
-    int a = 0, b = c;
+    const uint64_t* r = N.rec + ((size_t)par * N.n_wg + w) * (size_t)(N.range + 1);
+    const uint64_t h = r[0];
+    const int c = ((uint32_t)(h >> 32) == tag) ? (int)(uint32_t)h : 0;
+    int a = 0, b = c;  // ids are ascending
     while (a < b) {
       const int m = (a + b) >> 1;
-      if (l[m] < i) a = m + 1; else b = m;
+      if ((int64_t)(uint32_t)r[1 + m] < i) a = m + 1; else b = m;
     }
-    s[i] = (a < c && l[a] == i) ? 1 : 0;
+    s[i] = (a < c && (int64_t)(uint32_t)r[1 + a] == i) ? 1 : 0;
   }
 }
 
+// Checkpoint import by the owning workgroup: invalidates both record
+// parities, then writes the spikes of step `step - 1` tagged `step`.
 __global__ void __launch_bounds__(kNetThreads) net_set_state_k(const NetDev* __restrict__ Np, int par, uint32_t step,
                                                                 const float* V, const float* ge, const float* gi,
                                                                 const int32_t* ref, const uint8_t* s) {
@@ -402,9 +533,17 @@ __global__ void __launch_bounds__(kNetThreads) net_set_state_k(const NetDev* __r
   const NetDev N = *Np;
   const int w = blockIdx.x;
   const int32_t lo = w * N.range, hi = min(lo + N.range, N.n);
+  for (int p = 0; p < 2; ++p) {
+    uint64_t* r = N.rec + ((size_t)p * N.n_wg + w) * (size_t)(N.range + 1);
+    for (int q = threadIdx.x; q <= N.range; q += kNetThreads) r[q] = 0xFFFFFFFFull << 32;
+    if (N.n_wg > 1)
+      for (int x = threadIdx.x; x < N.n_wg * kInbox; x += kNetThreads)
+        inbox(N, p, x / kInbox, w)[x % kInbox] = 0xFFFFFFFFull << 32;
+  }
   if (threadIdx.x == 0) base_s = 0;
+  vm_drain();  // the invalidations land before the record is rewritten below
   __syncthreads();
-  int32_t* out = N.lists + ((size_t)par * N.n_wg + w) * N.range;
+  uint64_t* out = N.rec + ((size_t)par * N.n_wg + w) * (size_t)(N.range + 1);
   for (int32_t k0 = lo; k0 < hi; k0 += kNetThreads) {
     const int32_t k = k0 + threadIdx.x;
     int on = 0;
@@ -417,14 +556,20 @@ __global__ void __launch_bounds__(kNetThreads) net_set_state_k(const NetDev* __r
     }
     int tot;
     const int ex = block_excl_scan(on, scan, &tot);
-    if (on) out[base_s + ex] = k;
+    if (on) out[1 + base_s + ex] = ((uint64_t)step << 32) | (uint32_t)k;
     __syncthreads();
     if (threadIdx.x == 0) base_s += tot;
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    N.lcount[par * N.n_wg + w] = base_s;
-    N.flags[w] = step;
+  if (threadIdx.x == 0) out[0] = ((uint64_t)step << 32) | (uint32_t)base_s;
+  vm_drain();
+  __syncthreads();
+  if (N.n_wg > 1) {
+    const int m = min(base_s, kInbox - 1) + 1;
+    for (int x = threadIdx.x; x < N.n_wg * m; x += kNetThreads) {
+      const int d = x / m, q = x - d * m;
+      inbox(N, par, d, w)[q] = q == 0 ? (((uint64_t)step << 32) | (uint32_t)base_s) : out[q];
+    }
   }
 }
 
@@ -448,7 +593,7 @@ struct Layout {
   int32_t n_wg, range, nb;
   int64_t nnz_cap;
   bool blk;
-  size_t off_hdr, off_V, off_ge, off_gi, off_ref, off_lists, off_lcount, off_flags, off_events, off_error,
+  size_t off_hdr, off_V, off_ge, off_gi, off_ref, off_rec, off_inbox, off_events, off_error,
       off_indptr, off_indices, off_blkptr, total;
 };
 
@@ -502,9 +647,9 @@ static bp_status make_layout(const bp_net_desc* d, Layout* L) {
   L->off_ge = take((size_t)n * 4);
   L->off_gi = take((size_t)n * 4);
   L->off_ref = take((size_t)n * 4);
-  L->off_lists = take((size_t)2 * n_wg * range * 4);
-  L->off_lcount = take((size_t)2 * n_wg * 4);
-  L->off_flags = take((size_t)n_wg * 4);
+  // + kSpec slots: the gather loads a header and the next kSpec slots together
+  L->off_rec = take(((size_t)2 * n_wg * (range + 1) + kSpec) * 8);
+  L->off_inbox = n_wg > 1 ? take((size_t)2 * n_wg * n_wg * kInbox * 8) : 0;
   L->off_events = take((size_t)n_wg * 8);
   L->off_error = take(4);
   L->off_indptr = d->conn == BP_CONN_CSR ? take((size_t)(n + 1) * 4) : 0;
@@ -623,9 +768,8 @@ bp_status bp_create_net(const bp_net_desc* d, void* ws, size_t bytes, bp_stream 
   H.ge = (float*)(base + L.off_ge);
   H.gi = (float*)(base + L.off_gi);
   H.ref = (int32_t*)(base + L.off_ref);
-  H.lists = (int32_t*)(base + L.off_lists);
-  H.lcount = (int32_t*)(base + L.off_lcount);
-  H.flags = (uint32_t*)(base + L.off_flags);
+  H.rec = (uint64_t*)(base + L.off_rec);
+  H.inbox = L.n_wg > 1 ? (uint64_t*)(base + L.off_inbox) : nullptr;
   H.events = (unsigned long long*)(base + L.off_events);
   H.error = (uint32_t*)(base + L.off_error);
   H.indptr = d->conn == BP_CONN_CSR ? (const int32_t*)(base + L.off_indptr) : nullptr;
@@ -644,7 +788,9 @@ bp_status bp_create_net(const bp_net_desc* d, void* ws, size_t bytes, bp_stream 
   };
   hipError_t e = hipMemcpyAsync(net->dev, &net->host, sizeof(NetDev), hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return fail(set_error(BP_EDEVICE, "header copy failed: %s", hipGetErrorString(e)));
-  const int64_t init_n = d->n > 2 * L.n_wg ? d->n : 2 * L.n_wg;
+  int64_t slots = 2 * (int64_t)L.n_wg * (L.range + 1);
+  if (L.n_wg > 1 && 2 * (int64_t)L.n_wg * L.n_wg * kInbox > slots) slots = 2 * (int64_t)L.n_wg * L.n_wg * kInbox;
+  const int64_t init_n = d->n > slots ? d->n : slots;
   net_init_k<<<(unsigned)((init_n + 255) / 256), 256, 0, st>>>(net->dev, d->v0_lo, d->v0_hi);
   if ((e = hipGetLastError()) != hipSuccess)
     return fail(set_error(BP_EDEVICE, "net_init_k launch failed: %s", hipGetErrorString(e)));
@@ -733,7 +879,7 @@ bp_status bp_get_state(bp_net net, void* dst, size_t bytes, bp_stream stream) {
   char* p = (char*)dst;
   const int par = (int)((net->step + 1) & 1);
   net_get_state_k<<<(unsigned)((n + 255) / 256), 256, 0, as_stream(stream)>>>(
-      net->dev, par, (float*)p, (float*)(p + 4 * n), (float*)(p + 8 * n), (int32_t*)(p + 12 * n), (uint8_t*)(p + 16 * n));
+      net->dev, par, (uint32_t)net->step, (float*)p, (float*)(p + 4 * n), (float*)(p + 8 * n), (int32_t*)(p + 12 * n), (uint8_t*)(p + 16 * n));
   BP_LAUNCHED("net_get_state_k");
   return BP_OK;
 }
