@@ -294,7 +294,8 @@ bp_status bp_destroy_net(bp_net net);
  * max(0, relu_a (relu_width - |x|)), x = V - theta; detach_reset = 1 treats
  * (1 - z_{t-1}) as a constant. */
 typedef struct {
-  int32_t B, C, N, O, T;
+  int32_t B, C, N, O, T;  /* batch, input channels, neurons (<= 1024), classes (<= 64), steps */
+  int32_t nnz;            /* recurrent synapses (indptr[N]) */
   int32_t surrogate;    /* 0 sigmoid, 1 relu */
   int32_t detach_reset;
   int32_t ckpt_every;   /* checkpoint interval of the forward pass (> 0) */
@@ -309,22 +310,28 @@ typedef struct {
   const float* b_out;     /* device float[O] */
 } bp_snn;
 
-/* Checkpoint buffer bytes: (floor((T-1)/ckpt_every) + 1) checkpoints of
- * (I, V) float[B, N] and z uint8[B, N], plus spike-count sums float[B, N]. */
+/* Checkpoint buffer bytes: ceil(T / ckpt_every) checkpoints of (I, V)
+ * float[B, N] and z uint8[B, N] (the state before each segment), the spike
+ * counts float[B, N] and the transposed recurrent connectivity.  Written by
+ * bp_snn_forward, read by bp_snn_backward. */
 size_t bp_snn_ckpt_bytes(const bp_snn* m);
-/* Scratch for the reverse pass (one checkpoint segment of V and z per sample). */
+/* Scratch of the reverse pass: one segment of (V, z) per sample and
+ * per-sample gradient partials (reduced in sample order, so the result does
+ * not depend on scheduling). */
 size_t bp_snn_ws_bytes(const bp_snn* m);
 
 /* Forward pass: logits (device float[B, O]), loss (device float[1]),
- * checkpoints into ckpt (device, bp_snn_ckpt_bytes). raster (nullable,
- * device uint8[T, B, N]) receives the spikes. */
+ * checkpoints into ckpt (device, bp_snn_ckpt_bytes).  raster (nullable,
+ * device uint8[T, B, N]) receives the spikes.  The recurrent input of each
+ * neuron is summed over its firing presynaptic neurons in ascending order
+ * (deterministic, so the reverse pass recomputes identical spikes). */
 bp_status bp_snn_forward(const bp_snn* m, void* ckpt, float* logits, float* loss, uint8_t* raster,
                          bp_stream stream);
 
 /* Reverse pass from the checkpoints: recomputes each segment forward, then
  * walks it backward.  Gradients (device, overwritten, nullable):
  * dW_in float[C, N], dw_rec float[nnz], dW_out float[N, O], db_out float[O].
- * logits are the forward's output. */
+ * logits are the forward's output; ws: bp_snn_ws_bytes bytes. */
 bp_status bp_snn_backward(const bp_snn* m, const void* ckpt, const float* logits, float* dW_in, float* dw_rec,
                           float* dW_out, float* db_out, void* ws, size_t ws_bytes, bp_stream stream);
 

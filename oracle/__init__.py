@@ -95,7 +95,7 @@ def lib():
                                      C.c_void_p]
         L.or_snn_grad.restype = C.c_int
         L.or_snn_grad.argtypes = [C.POINTER(SnnParams), _u8p, _i32p, _f64p, _i32p, _i32p, _f64p, _f64p, _f64p,
-                                  C.c_void_p, C.POINTER(C.c_double), _f64p, C.c_void_p,
+                                  C.c_void_p, C.POINTER(C.c_double), _f64p, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         _lib = L
     return _lib
@@ -290,11 +290,13 @@ def snn_params(B, C_, N, O, T, alpha, beta, theta=1.0, slope=4.0, surrogate=0, s
                      relu_width)
 
 
-def snn_grad(P, x, labels, W_in, indptr, indices, w_rec, W_out, b_out, z_force=None, want_z=False):
+def snn_grad(P, x, labels, W_in, indptr, indices, w_rec, W_out, b_out, z_force=None, want_z=False,
+             want_margin=False):
     B, N, O, T, Cc = P.B, P.N, P.O, P.T, P.C
     loss = C.c_double(0.0)
     logits = np.empty((B, O), np.float64)
     z_out = np.empty((T, B, N), np.uint8) if want_z else None
+    vm = np.empty((T, B, N), np.float64) if want_margin else None
     dW_in = np.empty((Cc, N), np.float64)
     nnz = int(indptr[-1])
     dw_rec = np.empty(max(nnz, 1), np.float64)
@@ -305,8 +307,8 @@ def snn_grad(P, x, labels, W_in, indptr, indices, w_rec, W_out, b_out, z_force=N
                            np.ascontiguousarray(W_in, np.float64), np.ascontiguousarray(indptr, np.int32),
                            np.ascontiguousarray(indices, np.int32), np.ascontiguousarray(w_rec, np.float64),
                            np.ascontiguousarray(W_out, np.float64), np.ascontiguousarray(b_out, np.float64),
-                           _ptr(zf), C.byref(loss), logits, _ptr(z_out), _ptr(dW_in), _ptr(dw_rec),
+                           _ptr(zf), C.byref(loss), logits, _ptr(z_out), _ptr(vm), _ptr(dW_in), _ptr(dw_rec),
                            _ptr(dW_out), _ptr(db_out))
     assert rc == 0
-    return dict(loss=loss.value, logits=logits, z=z_out, dW_in=dW_in, dw_rec=dw_rec[:nnz], dW_out=dW_out,
-                db_out=db_out)
+    return dict(loss=loss.value, logits=logits, z=z_out, vmargin=vm, dW_in=dW_in, dw_rec=dw_rec[:nnz],
+                dW_out=dW_out, db_out=db_out)

@@ -51,14 +51,15 @@ static double surrogate(const or_snn* P, double v) {
  * pass are taken from it instead of from the threshold (teacher forcing with
  * another implementation's spike decisions; states are still recomputed).
  * Outputs: loss, logits [B, O], z_out (nullable, [T, B, N] of the spikes used,
- * thresholded in hard mode), gradients (each nullable) with the shapes of the
- * parameters.  Returns 0, or -1 on allocation failure.
+ * thresholded in hard mode), vmargin (nullable, [T, B, N]: V_t - theta, to
+ * check another implementation's spike decisions), gradients (each nullable)
+ * with the shapes of the parameters.  Returns 0, or -1 on allocation failure.
  */
 int or_snn_grad(const or_snn* P, const uint8_t* x, const int32_t* labels, const double* W_in,
                 const int32_t* indptr, const int32_t* indices, const double* w_rec,
                 const double* W_out, const double* b_out, const uint8_t* z_force, double* loss,
-                double* logits, uint8_t* z_out, double* dW_in, double* dw_rec, double* dW_out,
-                double* db_out) {
+                double* logits, uint8_t* z_out, double* vmargin, double* dW_in, double* dw_rec,
+                double* dW_out, double* db_out) {
   const int32_t B = P->B, C = P->C, N = P->N, O = P->O, T = P->T;
   const size_t TBN = (size_t)T * B * N;
   int32_t nnz = indptr[N];
@@ -101,6 +102,7 @@ int or_snn_grad(const or_snn* P, const uint8_t* x, const int32_t* labels, const 
         else if (P->smooth) z = sig(P->slope * (Vt[k] - P->theta));
         else z = Vt[k] > P->theta ? 1.0 : 0.0;
         Zt[k] = z;
+        if (vmargin) vmargin[((size_t)t * B + b) * N + k] = Vt[k] - P->theta;
         zsum[(size_t)b * N + k] += z;
         if (z_out) z_out[((size_t)t * B + b) * N + k] = (uint8_t)(z > 0.5);
       }

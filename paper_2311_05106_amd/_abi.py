@@ -41,7 +41,7 @@ class NetInfo(C.Structure):
 
 class Snn(C.Structure):
     _fields_ = [("B", C.c_int32), ("C", C.c_int32), ("N", C.c_int32), ("O", C.c_int32), ("T", C.c_int32),
-                ("surrogate", C.c_int32), ("detach_reset", C.c_int32), ("ckpt_every", C.c_int32),
+                ("nnz", C.c_int32), ("surrogate", C.c_int32), ("detach_reset", C.c_int32), ("ckpt_every", C.c_int32),
                 ("alpha", C.c_float), ("beta", C.c_float), ("theta", C.c_float), ("slope", C.c_float),
                 ("relu_a", C.c_float), ("relu_width", C.c_float),
                 ("x", C.c_void_p), ("labels", C.c_void_p), ("W_in", C.c_void_p), ("indptr", C.c_void_p),

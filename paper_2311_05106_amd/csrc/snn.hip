@@ -1,22 +1,450 @@
 // Recurrent LIF network trained by backpropagation through time with a
-// surrogate spike derivative (Section 5.3; Appendix I).
+// surrogate spike derivative (Section 5.3; Appendix I; every operator has a
+// reverse mode, Section 4.1).
+//
+// One workgroup per sample, one thread per neuron.  Forward step t:
+//   I = alpha I + sum over firing input channels (ascending) of W_in[c, k]
+//             + sum over firing presynaptic neurons j (ascending) of w_jk
+//   V = beta V (1 - z_prev) + (1 - beta) I ;  z = [V > theta]
+// The recurrent sum is pulled through the transposed connectivity (built on
+// the device), so each neuron adds its inputs in a fixed order: the forward
+// pass and its recomputation inside the reverse pass give identical spikes.
+// The forward stores the state before every ckpt_every-th step; the reverse
+// pass walks the segments from the last, recomputes each one, and runs the
+// recurrence backward through it.  Weight gradients are accumulated per
+// sample by the thread that owns each entry, then summed over samples in
+// sample order.
+#include <math.h>
+
 #include "bp_device.h"
 #include "bp_host.h"
+
+namespace bp {
+
+constexpr int kSnnMaxN = 1024;
+constexpr int kSnnMaxC = 4096;
+constexpr int kSnnMaxO = 64;
+
+struct SnnLayout {
+  int32_t nck;
+  size_t off_I, off_V, off_z, off_zsum, off_cptr, off_cj, off_cidx, ck_total;
+  size_t off_segV, off_segz, off_pin, off_prec, off_dlog, ws_total;
+};
+
+static SnnLayout snn_layout(const bp_snn* m) {
+  SnnLayout L{};
+  const size_t BN = (size_t)m->B * m->N;
+  L.nck = (m->T + m->ckpt_every - 1) / m->ckpt_every;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes, 256);
+    return at;
+  };
+  L.off_I = take(L.nck * BN * 4);
+  L.off_V = take(L.nck * BN * 4);
+  L.off_z = take(L.nck * BN);
+  L.off_zsum = take(BN * 4);
+  L.off_cptr = take(((size_t)m->N + 1) * 4);
+  L.off_cj = take((size_t)(m->nnz > 0 ? m->nnz : 1) * 4);
+  L.off_cidx = take((size_t)(m->nnz > 0 ? m->nnz : 1) * 4);
+  L.ck_total = o;
+  o = 0;
+  L.off_segV = take((size_t)m->B * m->ckpt_every * m->N * 4);
+  L.off_segz = take((size_t)m->B * m->ckpt_every * m->N);
+  L.off_pin = take((size_t)m->B * m->C * m->N * 4);
+  L.off_prec = take((size_t)m->B * (m->nnz > 0 ? m->nnz : 1) * 4);
+  L.off_dlog = take((size_t)m->B * m->O * 4);
+  L.ws_total = o;
+  return L;
+}
+
+struct SnnDev {
+  int32_t B, C, N, O, T, nnz, surrogate, detach, E, nck;
+  float alpha, beta, omb, theta, slope, relu_a, relu_w;
+  const uint8_t* x;
+  const int32_t* labels;
+  const float* W_in;
+  const int32_t* indptr;
+  const int32_t* indices;
+  const float* w_rec;
+  const float* W_out;
+  const float* b_out;
+  float* ckI;
+  float* ckV;
+  uint8_t* ckz;
+  float* zsum;
+  int32_t* cptr;
+  int32_t* cj;
+  int32_t* cidx;
+};
+
+// Transposed connectivity: for post neuron k the (pre j, CSR position)
+// pairs with j ascending.  Rows are sorted, so membership is a binary search.
+__global__ void __launch_bounds__(1024) snn_csc_k(SnnDev m) {
+  __shared__ int scratch[2 * (1024 / kWave + 1)];
+  __shared__ int base_s;
+  if (threadIdx.x == 0) base_s = 0;
+  __syncthreads();
+  for (int k0 = 0; k0 < m.N; k0 += blockDim.x) {
+    const int k = k0 + threadIdx.x;
+    int cnt = 0;
+    if (k < m.N)
+      for (int j = 0; j < m.N; ++j) {
+        int lo = m.indptr[j], hi = m.indptr[j + 1];
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (m.indices[mid] < k) lo = mid + 1; else hi = mid;
+        }
+        if (lo < m.indptr[j + 1] && m.indices[lo] == k) ++cnt;
+      }
+    int tot;
+    const int ex = block_excl_scan(cnt, scratch, &tot);
+    int pos = base_s + ex;
+    if (k < m.N) {
+      m.cptr[k] = pos;
+      for (int j = 0; j < m.N; ++j) {
+        int lo = m.indptr[j], hi = m.indptr[j + 1];
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (m.indices[mid] < k) lo = mid + 1; else hi = mid;
+        }
+        if (lo < m.indptr[j + 1] && m.indices[lo] == k && pos < m.nnz) {
+          m.cj[pos] = j;
+          m.cidx[pos] = lo;
+          ++pos;
+        }
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) base_s += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) m.cptr[m.N] = base_s;
+}
+
+struct SnnShared {
+  uint8_t zprev[kSnnMaxN];
+  int ch[kSnnMaxC];
+  int scratch[2 * (1024 / kWave + 1)];
+  int nch;
+  float red[kSnnMaxO][1024 / kWave];
+};
+
+// Firing input channels of sample b at step t -> sh.ch (ascending), sh.nch.
+__device__ __forceinline__ void stage_inputs(const SnnDev& m, int b, int t, SnnShared& sh) {
+  const uint8_t* xt = m.x + ((size_t)t * m.B + b) * m.C;
+  int base = 0;
+  for (int c0 = 0; c0 < m.C; c0 += blockDim.x) {
+    const int c = c0 + threadIdx.x;
+    const int on = (c < m.C && xt[c]) ? 1 : 0;
+    int tot;
+    const int ex = block_excl_scan(on, sh.scratch, &tot);
+    if (on) sh.ch[base + ex] = c;
+    base += tot;
+  }
+  if (threadIdx.x == 0) sh.nch = base;
+  __syncthreads();
+}
+
+// One forward step for neuron k (valid) given sh.zprev and sh.ch; returns z.
+__device__ __forceinline__ bool fwd_step(const SnnDev& m, int k, bool valid, float& I, float& V, const SnnShared& sh) {
+  if (!valid) return false;
+  float acc = m.alpha * I;
+  for (int q = 0; q < sh.nch; ++q) acc = acc + m.W_in[(size_t)sh.ch[q] * m.N + k];
+  const int e_end = min(m.cptr[k + 1], m.nnz);
+  for (int e = m.cptr[k]; e < e_end; ++e)
+    if (sh.zprev[m.cj[e]]) acc = acc + m.w_rec[m.cidx[e]];
+  I = acc;
+  const float vp = sh.zprev[k] ? 0.0f : V;
+  V = m.beta * vp + m.omb * I;
+  return V > m.theta;
+}
+
+__global__ void __launch_bounds__(1024) snn_forward_k(SnnDev m, float* logits, uint8_t* raster) {
+  __shared__ SnnShared sh;
+  const int b = blockIdx.x, k = threadIdx.x;
+  const bool valid = k < m.N;
+  float I = 0.f, V = 0.f, zs = 0.f;
+  if (valid) sh.zprev[k] = 0;
+  __syncthreads();
+  for (int t = 0; t < m.T; ++t) {
+    if (t % m.E == 0 && valid) {
+      const size_t o = ((size_t)(t / m.E) * m.B + b) * m.N + k;
+      m.ckI[o] = I;
+      m.ckV[o] = V;
+      m.ckz[o] = sh.zprev[k];
+    }
+    stage_inputs(m, b, t, sh);
+    const bool z = fwd_step(m, k, valid, I, V, sh);
+    __syncthreads();
+    if (valid) {
+      sh.zprev[k] = z ? 1 : 0;
+      zs += z ? 1.f : 0.f;
+      if (raster) raster[((size_t)t * m.B + b) * m.N + k] = z ? 1 : 0;
+    }
+    __syncthreads();
+  }
+  if (valid) m.zsum[(size_t)b * m.N + k] = zs;
+  // logits[b, o] = b_out[o] + sum_k zsum[k] / T * W_out[k, o]
+  const int nw = blockDim.x / kWave, wv = threadIdx.x / kWave;
+  for (int o = 0; o < m.O; ++o) {
+    float p = valid ? zs / (float)m.T * m.W_out[(size_t)k * m.O + o] : 0.f;
+    p = wave_sum_f(p);
+    if (lane_id() == 0) sh.red[o][wv] = p;
+  }
+  __syncthreads();
+  if (threadIdx.x < m.O) {
+    float s = m.b_out[threadIdx.x];
+    for (int w = 0; w < nw; ++w) s += sh.red[threadIdx.x][w];
+    logits[(size_t)b * m.O + threadIdx.x] = s;
+  }
+}
+
+// loss = mean over samples of logsumexp(logits) - logits[label];
+// dlog[b, o] = (softmax(logits_b)[o] - [o == label]) / B.  One thread per sample.
+__global__ void snn_loss_k(SnnDev m, const float* logits, float* loss, float* dlog) {
+  __shared__ float part[1024];
+  float acc = 0.f;
+  for (int b = threadIdx.x; b < m.B; b += blockDim.x) {
+    const float* lg = logits + (size_t)b * m.O;
+    float mx = lg[0];
+    for (int o = 1; o < m.O; ++o) mx = fmaxf(mx, lg[o]);
+    float se = 0.f;
+    for (int o = 0; o < m.O; ++o) se += expf(lg[o] - mx);
+    const float lse = mx + logf(se);
+    acc += lse - lg[m.labels[b]];
+    if (dlog)
+      for (int o = 0; o < m.O; ++o)
+        dlog[(size_t)b * m.O + o] = (expf(lg[o] - lse) - (o == m.labels[b] ? 1.f : 0.f)) / (float)m.B;
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0 && loss) {
+    float s = 0.f;
+    for (int i = 0; i < (int)blockDim.x; ++i) s += part[i];
+    *loss = s / (float)m.B;
+  }
+}
+
+__device__ __forceinline__ float surrogate(const SnnDev& m, float v) {
+  const float x = v - m.theta;
+  if (m.surrogate == 1) return fmaxf(0.f, m.relu_a * (m.relu_w - fabsf(x)));
+  const float s = 1.f / (1.f + expf(-m.slope * x));
+  return m.slope * s * (1.f - s);
+}
+
+struct SnnBwdShared {
+  SnnShared f;
+  float dI[kSnnMaxN];
+  float dlog[kSnnMaxO];
+};
+
+__global__ void __launch_bounds__(1024) snn_backward_k(SnnDev m, const float* dlog_all, float* segV, uint8_t* segz,
+                                                       float* pin, float* prec) {
+  __shared__ SnnBwdShared sh;
+  const int b = blockIdx.x, k = threadIdx.x;
+  const bool valid = k < m.N;
+  float* pin_b = pin + (size_t)b * m.C * m.N;
+  float* prec_b = prec + (size_t)b * m.nnz;
+  for (size_t i = threadIdx.x; i < (size_t)m.C * m.N; i += blockDim.x) pin_b[i] = 0.f;
+  for (int i = threadIdx.x; i < m.nnz; i += blockDim.x) prec_b[i] = 0.f;
+  if (threadIdx.x < m.O) sh.dlog[threadIdx.x] = dlog_all[(size_t)b * m.O + threadIdx.x];
+  if (valid) sh.dI[k] = 0.f;
+  __syncthreads();
+  float gd = 0.f;
+  if (valid) {
+    for (int o = 0; o < m.O; ++o) gd += m.W_out[(size_t)k * m.O + o] * sh.dlog[o];
+    gd = gd / (float)m.T;
+  }
+  float dVn = 0.f;
+  float* sV = segV + (size_t)b * m.E * m.N;
+  uint8_t* sz = segz + (size_t)b * m.E * m.N;
+  for (int seg = m.nck - 1; seg >= 0; --seg) {
+    const int t0 = seg * m.E, t1 = min(t0 + m.E, m.T);
+    // recompute the segment from its checkpoint
+    float I = 0.f, V = 0.f;
+    uint8_t z_start = 0;
+    if (valid) {
+      const size_t o = ((size_t)seg * m.B + b) * m.N + k;
+      I = m.ckI[o];
+      V = m.ckV[o];
+      z_start = m.ckz[o];
+      sh.f.zprev[k] = z_start;
+    }
+    __syncthreads();
+    for (int t = t0; t < t1; ++t) {
+      stage_inputs(m, b, t, sh.f);
+      const bool z = fwd_step(m, k, valid, I, V, sh.f);
+      __syncthreads();
+      if (valid) {
+        sh.f.zprev[k] = z ? 1 : 0;
+        sV[(size_t)(t - t0) * m.N + k] = V;
+        sz[(size_t)(t - t0) * m.N + k] = z ? 1 : 0;
+      }
+      __syncthreads();
+    }
+    // reverse through the segment
+    for (int t = t1 - 1; t >= t0; --t) {
+      const bool last = (t + 1 >= m.T);
+      float dI = 0.f;
+      if (valid) {
+        const float Vt = sV[(size_t)(t - t0) * m.N + k];
+        const bool zt = sz[(size_t)(t - t0) * m.N + k] != 0;
+        float dz = gd;
+        if (!last) {
+          float g = 0.f;
+          for (int idx = m.indptr[k]; idx < m.indptr[k + 1]; ++idx) g += m.w_rec[idx] * sh.dI[m.indices[idx]];
+          dz += g;
+          if (!m.detach) dz += dVn * (-m.beta * Vt);
+        }
+        float dV = dz * surrogate(m, Vt);
+        if (!last) dV += dVn * m.beta * (zt ? 0.f : 1.f);
+        dI = dV * m.omb;
+        if (!last) dI += sh.dI[k] * m.alpha;
+        dVn = dV;
+      }
+      __syncthreads();
+      if (valid) sh.dI[k] = dI;
+      // z_{t-1} of this sample: from the segment scratch or the checkpoint
+      if (valid) sh.f.zprev[k] = (t > t0) ? sz[(size_t)(t - 1 - t0) * m.N + k] : z_start;
+      stage_inputs(m, b, t, sh.f);  // ends with a barrier
+      if (valid) {
+        for (int q = 0; q < sh.f.nch; ++q) pin_b[(size_t)sh.f.ch[q] * m.N + k] += dI;
+        if (t > 0 && sh.f.zprev[k])
+          for (int idx = m.indptr[k]; idx < m.indptr[k + 1]; ++idx) prec_b[idx] += sh.dI[m.indices[idx]];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void snn_reduce_k(const float* part, int B, size_t n, float* out) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int b = 0; b < B; ++b) s += part[(size_t)b * n + i];
+  out[i] = s;
+}
+
+// dW_out[k, o] = sum_b zsum[b, k] / T * dlog[b, o];  db_out[o] = sum_b dlog[b, o]
+__global__ void snn_readout_grad_k(SnnDev m, const float* dlog, float* dW_out, float* db_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (dW_out && i < m.N * m.O) {
+    const int k = i / m.O, o = i % m.O;
+    float s = 0.f;
+    for (int b = 0; b < m.B; ++b) s += m.zsum[(size_t)b * m.N + k] / (float)m.T * dlog[(size_t)b * m.O + o];
+    dW_out[i] = s;
+  }
+  if (db_out && i < m.O) {
+    float s = 0.f;
+    for (int b = 0; b < m.B; ++b) s += dlog[(size_t)b * m.O + i];
+    db_out[i] = s;
+  }
+}
+
+static bp_status check_snn(const bp_snn* m) {
+  BP_REQUIRE(m != nullptr, "null descriptor");
+  BP_REQUIRE(m->B > 0 && m->C > 0 && m->N > 0 && m->O > 0 && m->T > 0, "sizes must be positive");
+  BP_REQUIRE(m->N <= kSnnMaxN, "N must be <= %d", kSnnMaxN);
+  BP_REQUIRE(m->C <= kSnnMaxC, "C must be <= %d", kSnnMaxC);
+  BP_REQUIRE(m->O <= kSnnMaxO, "O must be <= %d", kSnnMaxO);
+  BP_REQUIRE(m->nnz >= 0, "nnz must be >= 0");
+  BP_REQUIRE(m->ckpt_every > 0, "ckpt_every must be > 0");
+  BP_REQUIRE(m->surrogate == 0 || m->surrogate == 1, "surrogate must be 0 or 1");
+  BP_REQUIRE(m->x && m->labels && m->W_in && m->indptr && m->W_out && m->b_out, "null input");
+  BP_REQUIRE(m->nnz == 0 || (m->indices && m->w_rec), "null recurrent weights");
+  return BP_OK;
+}
+
+static SnnDev snn_dev(const bp_snn* m, void* ckpt) {
+  const SnnLayout L = snn_layout(m);
+  SnnDev d{};
+  d.B = m->B; d.C = m->C; d.N = m->N; d.O = m->O; d.T = m->T; d.nnz = m->nnz;
+  d.surrogate = m->surrogate; d.detach = m->detach_reset; d.E = m->ckpt_every; d.nck = L.nck;
+  d.alpha = m->alpha; d.beta = m->beta; d.omb = 1.0f - m->beta; d.theta = m->theta; d.slope = m->slope;
+  d.relu_a = m->relu_a; d.relu_w = m->relu_width;
+  d.x = m->x; d.labels = m->labels; d.W_in = m->W_in; d.indptr = m->indptr; d.indices = m->indices;
+  d.w_rec = m->w_rec; d.W_out = m->W_out; d.b_out = m->b_out;
+  char* c = (char*)ckpt;
+  d.ckI = (float*)(c + L.off_I);
+  d.ckV = (float*)(c + L.off_V);
+  d.ckz = (uint8_t*)(c + L.off_z);
+  d.zsum = (float*)(c + L.off_zsum);
+  d.cptr = (int32_t*)(c + L.off_cptr);
+  d.cj = (int32_t*)(c + L.off_cj);
+  d.cidx = (int32_t*)(c + L.off_cidx);
+  return d;
+}
+
+static int snn_threads(int N) { return ((N + kWave - 1) / kWave) * kWave; }
+
+}  // namespace bp
 
 using namespace bp;
 
 extern "C" {
 
-size_t bp_snn_ckpt_bytes(const bp_snn* m) { return 0; }
-size_t bp_snn_ws_bytes(const bp_snn* m) { return 0; }
+size_t bp_snn_ckpt_bytes(const bp_snn* m) {
+  if (check_snn(m)) return 0;
+  return snn_layout(m).ck_total;
+}
+
+size_t bp_snn_ws_bytes(const bp_snn* m) {
+  if (check_snn(m)) return 0;
+  return snn_layout(m).ws_total;
+}
 
 bp_status bp_snn_forward(const bp_snn* m, void* ckpt, float* logits, float* loss, uint8_t* raster, bp_stream stream) {
-  return set_error(BP_EUNSUPPORTED, "not built yet");
+  bp_status s = check_snn(m);
+  if (s) return s;
+  BP_REQUIRE(ckpt && logits, "null output");
+  hipStream_t st = as_stream(stream);
+  const SnnDev d = snn_dev(m, ckpt);
+  snn_csc_k<<<1, 1024, 0, st>>>(d);
+  BP_LAUNCHED("snn_csc_k");
+  snn_forward_k<<<m->B, snn_threads(m->N), 0, st>>>(d, logits, raster);
+  BP_LAUNCHED("snn_forward_k");
+  if (loss) {
+    snn_loss_k<<<1, 1024, 0, st>>>(d, logits, loss, nullptr);
+    BP_LAUNCHED("snn_loss_k");
+  }
+  return BP_OK;
 }
 
 bp_status bp_snn_backward(const bp_snn* m, const void* ckpt, const float* logits, float* dW_in, float* dw_rec,
                           float* dW_out, float* db_out, void* ws, size_t ws_bytes, bp_stream stream) {
-  return set_error(BP_EUNSUPPORTED, "not built yet");
+  bp_status s = check_snn(m);
+  if (s) return s;
+  BP_REQUIRE(ckpt && logits && ws, "null pointer");
+  const SnnLayout L = snn_layout(m);
+  BP_REQUIRE(ws_bytes >= L.ws_total, "workspace too small (%zu < %zu)", ws_bytes, L.ws_total);
+  hipStream_t st = as_stream(stream);
+  const SnnDev d = snn_dev(m, const_cast<void*>(ckpt));
+  char* w = (char*)ws;
+  float* dlog = (float*)(w + L.off_dlog);
+  snn_loss_k<<<1, 1024, 0, st>>>(d, logits, nullptr, dlog);
+  BP_LAUNCHED("snn_loss_k");
+  float* pin = (float*)(w + L.off_pin);
+  float* prec = (float*)(w + L.off_prec);
+  snn_backward_k<<<m->B, snn_threads(m->N), 0, st>>>(d, dlog, (float*)(w + L.off_segV), (uint8_t*)(w + L.off_segz),
+                                                      pin, prec);
+  BP_LAUNCHED("snn_backward_k");
+  if (dW_in) {
+    const size_t n = (size_t)m->C * m->N;
+    snn_reduce_k<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(pin, m->B, n, dW_in);
+    BP_LAUNCHED("snn_reduce_k");
+  }
+  if (dw_rec && m->nnz > 0) {
+    snn_reduce_k<<<(unsigned)((m->nnz + 255) / 256), 256, 0, st>>>(prec, m->B, (size_t)m->nnz, dw_rec);
+    BP_LAUNCHED("snn_reduce_k");
+  }
+  if (dW_out || db_out) {
+    const int n = m->N * m->O > m->O ? m->N * m->O : m->O;
+    snn_readout_grad_k<<<(n + 255) / 256, 256, 0, st>>>(d, dlog, dW_out, db_out);
+    BP_LAUNCHED("snn_readout_grad_k");
+  }
+  return BP_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,148 @@
+"""GPU parity of the recurrent LIF network's forward pass and checkpointed
+BPTT against the FP64 oracle.  The oracle is teacher-forced with the GPU's
+spikes; every GPU spike decision must agree with the FP64 membrane potential
+except within 1e-4 of threshold.  Loss and logits: 1e-5 relative; gradients:
+relative L2 error below 1e-4.  Checkpoint interval does not change the
+gradient bits."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synthetic as S
+
+pytestmark = pytest.mark.gpu
+dev = "cuda"
+
+
+@pytest.fixture(scope="module")
+def mods():
+    import paper_2311_05106_amd as bp
+    import paper_2311_05106_amd.autograd as A
+    return bp, A
+
+
+def make_case(B, Cc, N, Ocls, T, p, seed, win_scale=1.0, rec_scale=1.0, in_lo=5.0, in_hi=50.0):
+    K = O.max_gap(p)
+    ip, ix = O.csr_build(seed, K, N, N, 0)
+    x = S.poisson_inputs(T, B, Cc, 1.0, seed, in_lo, in_hi)
+    lab = S.labels(B, Ocls, seed)
+    W_in, w_rec, W_out, b_out = S.snn_weights(Cc, N, Ocls, ix.size, seed, rec_std=1.0 / math.sqrt(max(p * N, 1)))
+    W_in = (W_in * win_scale).astype(np.float32)
+    w_rec = (w_rec * rec_scale).astype(np.float32)
+    return dict(ip=ip, ix=ix, x=x, labels=lab, W_in=W_in, w_rec=w_rec, W_out=W_out, b_out=b_out)
+
+
+def run_gpu(A, case, B, Cc, N, Ocls, T, ckpt_every, **cfg):
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    model = A.SNN(B, Cc, N, Ocls, T, t(case["ip"]), t(case["ix"]), ckpt_every=ckpt_every, **cfg)
+    args = (t(case["x"]), t(case["labels"]), t(case["W_in"]), t(case["w_rec"]), t(case["W_out"]), t(case["b_out"]))
+    fwd = model.forward(*args, want_raster=True)
+    g = model.backward(fwd, *args)
+    out = {k: v.cpu().numpy() for k, v in g.items()}
+    out.update(loss=float(fwd["loss"].item()), logits=fwd["logits"].cpu().numpy(), raster=fwd["raster"].cpu().numpy())
+    return out
+
+
+def oracle_forced(case, B, Cc, N, Ocls, T, raster, **cfg):
+    P = O.snn_params(B, Cc, N, Ocls, T, alpha=cfg["alpha"], beta=cfg["beta"], theta=cfg.get("theta", 1.0),
+                     slope=cfg.get("slope", 4.0), surrogate=cfg.get("surrogate", 0),
+                     detach_reset=cfg.get("detach_reset", 1))
+    f64 = lambda a: np.asarray(a, np.float64)
+    return O.snn_grad(P, case["x"], case["labels"], f64(case["W_in"]), case["ip"], case["ix"], f64(case["w_rec"]),
+                      f64(case["W_out"]), f64(case["b_out"]), z_force=raster, want_margin=True)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a.astype(np.float64) - b) / max(np.linalg.norm(b), 1e-30))
+
+
+CFG = dict(alpha=math.exp(-1 / 5), beta=math.exp(-1 / 20), theta=1.0, slope=4.0)
+
+
+@pytest.mark.parametrize("surrogate,detach", [(0, 1), (0, 0), (1, 1)])
+def test_snn_small_against_oracle(mods, surrogate, detach):
+    bp, A = mods
+    B, Cc, N, Ocls, T = 4, 16, 64, 5, 60
+    case = make_case(B, Cc, N, Ocls, T, 0.2, 3, win_scale=6.0, rec_scale=2.0, in_lo=20, in_hi=200)
+    cfg = dict(CFG, surrogate=surrogate, detach_reset=detach)
+    g = run_gpu(A, case, B, Cc, N, Ocls, T, 20, **cfg)
+    r = oracle_forced(case, B, Cc, N, Ocls, T, g["raster"], **cfg)
+    z = g["raster"].astype(bool)
+    assert 0.01 < z.mean() < 0.9
+    m = r["vmargin"]
+    assert not np.any(z & (m < -1e-4)) and not np.any(~z & (m > 1e-4)), "spike decision disagrees with FP64"
+    assert g["loss"] == pytest.approx(r["loss"], rel=1e-5)
+    np.testing.assert_allclose(g["logits"], r["logits"], rtol=1e-5, atol=1e-6)
+    for k in ("dW_in", "dw_rec", "dW_out", "db_out"):
+        assert rel_l2(g[k], r[k]) < 1e-4, (k, rel_l2(g[k], r[k]))
+
+
+def test_checkpoint_interval_does_not_change_bits(mods):
+    bp, A = mods
+    B, Cc, N, Ocls, T = 3, 16, 64, 5, 57
+    case = make_case(B, Cc, N, Ocls, T, 0.2, 5, win_scale=6.0, rec_scale=2.0, in_lo=20, in_hi=200)
+    a = run_gpu(A, case, B, Cc, N, Ocls, T, 10, **CFG)
+    b = run_gpu(A, case, B, Cc, N, Ocls, T, T, **CFG)       # one segment: full storage
+    c = run_gpu(A, case, B, Cc, N, Ocls, T, 1, **CFG)       # every step checkpointed
+    for k in ("dW_in", "dw_rec", "dW_out", "db_out", "logits", "raster"):
+        np.testing.assert_array_equal(a[k], b[k])
+        np.testing.assert_array_equal(a[k], c[k])
+    assert a["loss"] == b["loss"] == c["loss"]
+
+
+def test_snn_full_config_against_oracle(mods):
+    # batch 256, 128 Poisson inputs (5-50 Hz), 512 neurons with p = 0.1
+    # recurrent CSR, 10 classes, 250 steps of 1 ms, checkpoints every 50.
+    bp, A = mods
+    B, Cc, N, Ocls, T = 256, 128, 512, 10, 250
+    case = make_case(B, Cc, N, Ocls, T, 0.1, 0, win_scale=4.0)
+    g = run_gpu(A, case, B, Cc, N, Ocls, T, 50, **CFG)
+    assert g["raster"].mean() > 1e-3
+    r = oracle_forced(case, B, Cc, N, Ocls, T, g["raster"], **CFG)
+    z = g["raster"].astype(bool)
+    m = r["vmargin"]
+    assert not np.any(z & (m < -1e-4)) and not np.any(~z & (m > 1e-4))
+    assert g["loss"] == pytest.approx(r["loss"], rel=1e-5)
+    for k in ("dW_in", "dw_rec", "dW_out", "db_out"):
+        assert rel_l2(g[k], r[k]) < 1e-4, (k, rel_l2(g[k], r[k]))
+
+
+def test_snn_autograd_function(mods):
+    bp, A = mods
+    B, Cc, N, Ocls, T = 4, 16, 64, 5, 40
+    case = make_case(B, Cc, N, Ocls, T, 0.2, 7, win_scale=6.0, rec_scale=2.0, in_lo=20, in_hi=200)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    model = A.SNN(B, Cc, N, Ocls, T, t(case["ip"]), t(case["ix"]), ckpt_every=10, **CFG)
+    params = [t(case[k]).requires_grad_(True) for k in ("W_in", "w_rec", "W_out", "b_out")]
+    loss = A.SnnLoss.apply(*params, model, t(case["x"]), t(case["labels"]))
+    (2.0 * loss).backward()
+    direct = run_gpu(A, case, B, Cc, N, Ocls, T, 10, **CFG)
+    for p, k in zip(params, ("dW_in", "dw_rec", "dW_out", "db_out")):
+        np.testing.assert_array_equal(p.grad.cpu().numpy(), 2.0 * direct[k])
+
+
+def test_operator_autograd_functions(mods):
+    bp, A = mods
+    n_pre, n_post = 3000, 2000
+    ip, ix = O.csr_build(4, O.max_gap(0.01), n_pre, n_post, 0)
+    data = S.hetero_data(ix.size, 2)
+    e = S.events(n_pre, 0.2, 1)
+    dy = S.cotangent(n_post, 1).astype(np.float32)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    d = t(data).requires_grad_(True)
+    y = A.EventCSRMatvec.apply(t(e), d, t(ip), t(ix), n_post)
+    y.backward(t(dy))
+    _, d_data, _ = O.event_csr_vjp(ip, ix, data, 0.0, n_post, e, dy.astype(np.float64))
+    np.testing.assert_array_equal(d.grad.cpu().numpy(), d_data.astype(np.float32))
+    # JIT product: gradient of (w0, w1)
+    c = bp.JitConn(n_pre, n_post, K=O.max_gap(0.01), block=512, seed=3, wkind=bp.W_NORMAL, w0=0.5, w1=0.1)
+    w01 = torch.tensor([0.5, 0.1], dtype=torch.float32, device=dev, requires_grad=True)
+    yj = A.JitConnMatvec.apply(t(e), w01, c)
+    yj.backward(t(dy))
+    _, g0, g1 = O.jit_vjp(3, O.max_gap(0.01), 512, 1, np.float32(0.5), np.float32(0.1), n_post, e,
+                          dy.astype(np.float64))
+    gw = w01.grad.cpu().numpy()
+    assert abs(gw[0] - g0) <= 1e-4 * max(1.0, abs(g0)) and abs(gw[1] - g1) <= 1e-4 * max(1.0, abs(g1))
