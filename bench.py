@@ -187,6 +187,23 @@ def bench_ops(bp, torch, calls=10000):
     return out
 
 
+def bench_serving(bp, torch, n_requests=100, rate_hz=20.0, budget_gib=1.0, quantum=500, max_wgs=64):
+    """Serving workload: Poisson arrivals at rate_hz, N ~ log-uniform[1e3,
+    2e5], p = 80/N, duration ~ U(100, 2000) ms at dt = 0.1 ms, COBA or CUBA
+    with probability 1/2, per-request seed; continuous batching under an HBM
+    budget against the plain one-net-at-a-time path on the same GPU."""
+    import synthetic as S
+    from paper_2311_05106_amd import serving as sv
+    reqs = S.request_stream(n_requests, rate_hz, 0)
+    warm = S.request_stream(4, rate_hz, 1)
+    sv.serve_batched(warm, hbm_budget=int(budget_gib * 2**30), quantum=quantum, max_wgs=max_wgs)
+    a = sv.summarize(sv.serve_batched(reqs, hbm_budget=int(budget_gib * 2**30), quantum=quantum, max_wgs=max_wgs))
+    b = sv.summarize(sv.serve_plain(reqs))
+    return dict(workload=f"{n_requests} requests, Poisson {rate_hz:g} req/s, N ~ logU[1e3, 2e5], p=80/N, "
+                         f"duration U(100, 2000) ms, COBA/CUBA", hbm_budget_gib=budget_gib, quantum_steps=quantum,
+                max_wgs_per_net=max_wgs, batched=a, plain=b)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -238,6 +255,7 @@ def main():
     if not args.no_extra:
         line["c0"] = bench_c0(bp, torch)
         line["operator_sweep"] = bench_ops(bp, torch)
+        line["serving"] = bench_serving(bp, torch)
     print(json.dumps(line), flush=True)
 
 

@@ -230,6 +230,10 @@ typedef struct bp_net_s* bp_net;
  * exceeds it. */
 bp_status bp_net_bytes(const bp_net_desc* d, size_t* bytes);
 
+/* Workgroups the network runs on (all of them resident at once during a
+ * run; a batch of nets must fit the device together). */
+bp_status bp_net_workgroups(const bp_net_desc* d, int32_t* n_wg);
+
 /* Creates a network whose state, connectivity and scratch live in `ws`
  * (device, `bytes` >= bp_net_bytes; caller-owned, must outlive the net).
  * Builds the stored connectivity if any and the initial state.  Synchronizes

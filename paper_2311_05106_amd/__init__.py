@@ -182,6 +182,12 @@ def net_bytes(desc):
     return int(b.value)
 
 
+def net_workgroups(desc):
+    w = C.c_int32(0)
+    check(lib().bp_net_workgroups(C.byref(desc), C.byref(w)))
+    return int(w.value)
+
+
 class Net:
     """An E/I LIF network resident in a caller-owned device workspace."""
 

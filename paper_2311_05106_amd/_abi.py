@@ -69,6 +69,7 @@ SIGNATURES = {
     "bp_jit_conn_backward": (_i32, [C.POINTER(JitConn), _vp, _vp, _vp, _vp, _vp]),
     "bp_backward": (_i32, [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "bp_net_bytes": (_i32, [C.POINTER(NetDesc), C.POINTER(_sz)]),
+    "bp_net_workgroups": (_i32, [C.POINTER(NetDesc), C.POINTER(_i32)]),
     "bp_create_net": (_i32, [C.POINTER(NetDesc), _vp, _sz, _vp, C.POINTER(_vp)]),
     "bp_run": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp]),
     "bp_step": (_i32, [_vp, _vp, _vp, _vp]),

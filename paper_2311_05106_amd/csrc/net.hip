@@ -730,6 +730,15 @@ bp_status bp_net_bytes(const bp_net_desc* d, size_t* bytes) {
   return BP_OK;
 }
 
+bp_status bp_net_workgroups(const bp_net_desc* d, int32_t* n_wg) {
+  Layout L;
+  bp_status s = make_layout(d, &L);
+  if (s) return s;
+  BP_REQUIRE(n_wg != nullptr, "null n_wg");
+  *n_wg = L.n_wg;
+  return BP_OK;
+}
+
 bp_status bp_create_net(const bp_net_desc* d, void* ws, size_t bytes, bp_stream stream, bp_net* out) {
   Layout L;
   bp_status s = make_layout(d, &L);

@@ -1,0 +1,69 @@
+"""Continuous batching on the GPU: every request's per-step spike counts and
+synaptic event total are bit-identical to the same net run alone, whether it
+was admitted at once, later, or after waiting for budget; nets of different
+sizes, models (COBA/CUBA) and connectivity (stored/JIT) share launches."""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mods():
+    import paper_2311_05106_amd as bp
+    import paper_2311_05106_amd.serving as sv
+    return bp, sv
+
+
+def requests():
+    sizes = [1000, 3500, 5000, 12000, 2500, 60000, 20000, 1500, 8000, 4096]
+    steps = [300, 700, 450, 900, 150, 400, 600, 250, 500, 350]
+    return [dict(id=i, arrival=0.002 * i, n=n, steps=s, model=i % 2, seed=100 + i)
+            for i, (n, s) in enumerate(zip(sizes, steps))]
+
+
+def solo_counts(bp, sv, r, max_wgs):
+    net = bp.Net(sv.request_desc(r, max_wgs=max_wgs))
+    _, c = net.run(r["steps"], counts=True)
+    ev = int(net.events().item())
+    return c.cpu().numpy(), ev
+
+
+@pytest.mark.parametrize("budget_mb,quantum", [(8192, 200), (12, 130)])
+def test_batched_equals_alone(mods, budget_mb, quantum):
+    bp, sv = mods
+    reqs = requests()
+    res = sv.serve_batched(reqs, hbm_budget=budget_mb << 20, quantum=quantum, max_wgs=16, record_counts=True)
+    assert not res["rejected"]
+    recs = {r["id"]: r for r in res["records"]}
+    assert len(recs) == len(reqs)
+    if budget_mb == 12:
+        # the budget forced some requests to wait for others to retire
+        assert max(r["admitted"] - r["arrival"] for r in recs.values()) > 0.0
+    for r in reqs:
+        c, ev = solo_counts(bp, sv, r, 16)
+        got = recs[r["id"]]
+        assert got["error"] == 0
+        np.testing.assert_array_equal(got["counts"], c)
+        assert got["events"] == ev
+        assert c.sum() > 0
+
+
+def test_oversized_request_is_rejected_not_run(mods):
+    bp, sv = mods
+    reqs = requests()[:3]
+    big = dict(id=99, arrival=0.0, n=20000, steps=10, model=0, seed=1)  # stored CSR, about 8.6 MB
+    res = sv.serve_batched(reqs + [big], hbm_budget=4 << 20, quantum=200, max_wgs=16)
+    assert [r["id"] for r in res["rejected"]] == [99]
+    assert sorted(r["id"] for r in res["records"]) == [0, 1, 2]
+
+
+def test_plain_path_matches_event_totals(mods):
+    bp, sv = mods
+    reqs = requests()[:4]
+    a = sv.serve_batched(reqs, hbm_budget=8 << 30, quantum=256, max_wgs=16)
+    b = sv.serve_plain(reqs, max_wgs=16)
+    ea = {r["id"]: r["events"] for r in a["records"]}
+    eb = {r["id"]: r["events"] for r in b["records"]}
+    assert ea == eb
