@@ -133,7 +133,8 @@ def bench_ops(bp, torch, calls=10000):
     dev = "cuda"
     ip, ix = bp.csr_build(bp.JitConn(n, n, K=K, seed=0))
     nnz = ix.numel()
-    tp = bp.csr_tile_index(ip, ix, n, 8192)
+    tw = -(-n // 8)  # eight column tiles (one per XCD-sized share of the columns)
+    tp = bp.csr_tile_index(ip, ix, n, tw)
     data = torch.from_numpy(S.hetero_data(nnz, 1)).to(dev)
     rowlen = (ip[1:] - ip[:-1]).to(torch.int64)
     out = []
@@ -146,10 +147,10 @@ def bench_ops(bp, torch, calls=10000):
         jn = bp.JitConn(n, n, K=K, block=1024, seed=0, wkind=bp.W_NORMAL, w0=0.5, w1=0.1)
         y = torch.empty(n, dtype=torch.float32, device=dev)
         cases = [
-            ("event_csr_homo", lambda e: bp.event_csr_matvec(ip, ix, None, 0.5, n, e, tp, 8192, out=y, ws=ws_c),
-             bp.event_csr_ws(ip, ix, None, 0.5, n, tp, 8192), n + 8 * act + 8 * act + 4 * nnz_a + 4 * n),
-            ("event_csr_hetero", lambda e: bp.event_csr_matvec(ip, ix, data, 0.0, n, e, tp, 8192, out=y, ws=ws_c),
-             bp.event_csr_ws(ip, ix, data, 0.0, n, tp, 8192), n + 8 * act + 8 * act + 8 * nnz_a + 4 * n),
+            ("event_csr_homo", lambda e: bp.event_csr_matvec(ip, ix, None, 0.5, n, e, tp, tw, out=y, ws=ws_c),
+             bp.event_csr_ws(ip, ix, None, 0.5, n, tp, tw), n + 8 * act + 8 * act + 4 * nnz_a + 4 * n),
+            ("event_csr_hetero", lambda e: bp.event_csr_matvec(ip, ix, data, 0.0, n, e, tp, tw, out=y, ws=ws_c),
+             bp.event_csr_ws(ip, ix, data, 0.0, n, tp, tw), n + 8 * act + 8 * act + 8 * nnz_a + 4 * n),
             ("jit_homo", lambda e: bp.jit_conn_matvec(jc, e, out=y, ws=ws_c), bp.jit_ws(jc), 4 * nnz_a),
             ("jit_normal", lambda e: bp.jit_conn_matvec(jn, e, out=y, ws=ws_c), bp.jit_ws(jn), 8 * nnz_a),
         ]

@@ -18,8 +18,10 @@ constexpr int kWHomo = 0, kWNormal = 1, kWUniform = 2;
 // 32x32->64-bit products mixed into the other two counter words and the round
 // key; the key advances by the golden-ratio Weyl constants between rounds.
 // ---------------------------------------------------------------------------
+// Four named words (not an array: a select over array elements can be turned
+// into an indexed private-memory load, i.e. scratch traffic in inner loops).
 struct Words4 {
-  uint32_t w[4];
+  uint32_t x, y, z, w;
 };
 
 __device__ __forceinline__ Words4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
@@ -37,16 +39,13 @@ __device__ __forceinline__ Words4 philox10(uint32_t c0, uint32_t c1, uint32_t c2
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
-  return Words4{{c0, c1, c2, c3}};
+  return Words4{c0, c1, c2, c3};
 }
 
 __device__ __forceinline__ uint32_t pick(const Words4& q, uint32_t i) {
-  const uint32_t s = i & 3u;
-  uint32_t v = q.w[0];
-  v = (s == 1u) ? q.w[1] : v;
-  v = (s == 2u) ? q.w[2] : v;
-  v = (s == 3u) ? q.w[3] : v;
-  return v;
+  const uint32_t lo = (i & 1u) ? q.y : q.x;
+  const uint32_t hi = (i & 1u) ? q.w : q.z;
+  return (i & 2u) ? hi : lo;
 }
 
 // hash(seed, stream, a, b, k): word k mod 4 of Philox(counter (a, b, k/4, stream)).

@@ -3,25 +3,34 @@
 //
 // Forward layout: the postsynaptic range is cut into tiles of P columns that
 // fit in LDS, the presynaptic range into C chunks of rows.  Workgroup
-// (tile, chunk) compacts the spikes of its rows into LDS (ballot + prefix
-// sum, ascending), then streams the part of every firing row that falls in
-// its tile and accumulates into its LDS tile (integer counts for homogeneous
-// weights, FP32 otherwise).  With one chunk the tile is written to y
-// directly; with several, each chunk stores its tile to a partial buffer and
-// a second kernel sums the partials in chunk order (no global atomics: device
-// atomics run far below HBM rate on this chip).
-//   CSR rows are streamed coalesced; a wave walks a contiguous slice of the
-//   flattened (row, offset) space of the firing rows (merge-path split).
-//   JIT rows are regenerated per (row, block) by one lane each.
+// (tile, chunk) sweeps the spike bytes of its rows 16 per lane (one 16-byte
+// load), appends the firing rows to an LDS list (wave scan + one LDS atomic
+// per wave, so one barrier per sweep), and when the list is nearly full or
+// the rows are done, streams the part of every listed row that falls in its
+// tile into its LDS accumulator (integer counts for homogeneous weights,
+// FP32 otherwise).  With one chunk the tile is written to y directly; with
+// several, each chunk stores its tile to a partial buffer (16-bit counts when
+// homogeneous: a chunk adds at most one per row to any column) and a second
+// kernel sums the partials in chunk order (no global atomics: device atomics
+// run far below HBM rate on this chip).
+//   CSR segments are streamed by quarter-waves (16 lanes, 8 loads in flight
+//   per lane, the next segment's bounds fetched ahead), so a wave reads four
+//   segments per instruction, coalesced.
+//   JIT rows are regenerated per (row, block) by one lane each; the tile is
+//   one block, so no lane generates targets outside its tile, and with
+//   enough blocks to cover the chip no row chunks (and no partials) are used.
 #include "bp_device.h"
 #include "bp_host.h"
 
 namespace bp {
 
-constexpr int kMvThreads = 512;
-constexpr int kMvWaves = kMvThreads / kWave;
-constexpr int kMvPiece = kMvThreads * 4;  // rows compacted per piece
-constexpr int kTileMax = 16384;           // LDS tile columns (64 KB)
+constexpr int kMvThreads = 1024;
+constexpr int kRowsPerLane = 16;                   // one 16-byte load of spike bytes
+constexpr int kSweep = kMvThreads * kRowsPerLane;  // rows examined per sweep
+constexpr int kIdCap = kSweep + 4096;              // firing rows listed before a flush
+constexpr int kTileMax = 16384;                    // LDS tile columns (64 KB)
+constexpr int kGroup = 16;                         // lanes streaming one CSR segment
+constexpr int kUnroll = 8;                         // loads in flight per lane
 
 enum MvMode { kCsrHomo = 0, kCsrData = 1, kJitHomo = 2, kJitWeighted = 3 };
 
@@ -40,31 +49,46 @@ struct MvArgs {
 };
 
 struct MvShared {
-  int ids[kMvPiece];
-  int pref[kMvPiece + 1];
-  int start[kMvPiece];
-  int scan[kMvWaves + 1];
+  int ids[kIdCap];
+  int cnt[3];  // per-sweep append counters, rotated so one barrier per sweep suffices
 };
 
-// Compacts events[r0, r1) (r1 - r0 <= kMvPiece) into sh.ids, ascending.
-__device__ __forceinline__ int compact_piece(const uint8_t* __restrict__ ev, int32_t r0, int32_t r1, MvShared& sh) {
-  const int base = threadIdx.x * 4;
-  uint32_t bits = 0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int32_t r = r0 + base + q;
-    if (r < r1 && ev[r]) bits |= 1u << q;
+// Bit q set iff byte q of v is nonzero.
+__device__ __forceinline__ uint32_t nonzero_bytes(uint32_t v) {
+  const uint32_t t = (((v & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | v) & 0x80808080u;
+  return (t >> 7 | t >> 14 | t >> 21 | t >> 28) & 0xFu;
+}
+
+// Bit q set iff row r + q < r_end fires.
+__device__ __forceinline__ uint32_t spike_bits16(const uint8_t* __restrict__ ev, int32_t r, int32_t r_end,
+                                                 bool vec) {
+  if (vec && r + kRowsPerLane <= r_end) {
+    const uint4 v = *reinterpret_cast<const uint4*>(ev + r);
+    return nonzero_bytes(v.x) | nonzero_bytes(v.y) << 4 | nonzero_bytes(v.z) << 8 | nonzero_bytes(v.w) << 12;
   }
-  int tot;
-  int off = block_excl_scan(__popc(bits), sh.scan, &tot);
+  uint32_t b = 0;
+  for (int q = 0; q < kRowsPerLane; ++q)
+    if (r + q < r_end && ev[r + q]) b |= 1u << q;
+  return b;
+}
+
+// Appends rows r + q (bit q of bits) to ids[total + ...]: one LDS atomic per
+// wave reserves the wave's slots, a wave scan places each lane's rows.
+__device__ __forceinline__ void append_rows(uint32_t bits, int32_t r, int total, int* cnt, int* ids) {
+  const int c = __popc(bits);
+  const int inc = wave_incl_scan(c);
+  const int wtot = __builtin_amdgcn_readlane(inc, kWave - 1);
+  if (wtot == 0) return;
+  int base = 0;
+  if (lane_id() == kWave - 1) base = atomicAdd(cnt, wtot);
+  base = __builtin_amdgcn_readlane(base, kWave - 1);
+  int off = total + base + inc - c;
   while (bits) {
     const int q = __ffs(bits) - 1;
     bits &= bits - 1;
-    if (off < kMvPiece) sh.ids[off] = r0 + base + q;
+    if (off < kIdCap) ids[off] = r + q;
     ++off;
   }
-  __syncthreads();
-  return tot;
 }
 
 template <int MODE>
@@ -80,95 +104,91 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
   const int32_t r_begin = c * a.chunk_rows;
   const int32_t r_end = min(r_begin + a.chunk_rows, a.n_pre);
   for (int i = threadIdx.x; i < width; i += kMvThreads) acc[i] = (Acc)0;
+  if (threadIdx.x < 3) sh.cnt[threadIdx.x] = 0;
   __syncthreads();
+  const bool vec = ((reinterpret_cast<uintptr_t>(a.events) | (uintptr_t)r_begin) & 15) == 0;
 
-  for (int32_t r0 = r_begin; r0 < r_end; r0 += kMvPiece) {
-    const int n_act = compact_piece(a.events, r0, min(r0 + kMvPiece, r_end), sh);
-    if (n_act == 0) continue;
+  int total = 0;  // listed rows, equal in every lane
+  int s = 0;
+  for (int32_t r0 = r_begin; r0 < r_end; r0 += kSweep, ++s) {
+    const int32_t r = r0 + (int32_t)threadIdx.x * kRowsPerLane;
+    const uint32_t bits = r < r_end ? spike_bits16(a.events, r, r_end, vec) : 0u;
+    // the counter of the next sweep was last read before the previous barrier
+    if (threadIdx.x == 0) sh.cnt[(s + 1) % 3] = 0;
+    append_rows(bits, r, total, &sh.cnt[s % 3], sh.ids);
+    __syncthreads();
+    total += sh.cnt[s % 3];
+    if (total <= kIdCap - kSweep && r0 + kSweep < r_end) continue;
+    if (total > kIdCap) total = kIdCap;  // unreachable: a sweep adds at most kSweep rows
+
     if constexpr (MODE == kCsrHomo || MODE == kCsrData) {
-      // segment of each firing row inside this tile
-      int total = 0;
-      for (int base = 0; base < n_act; base += kMvThreads) {
-        const int i = base + threadIdx.x;
-        int st = 0, len = 0;
-        if (i < n_act) {
-          const int32_t j = sh.ids[i];
-          if (a.tile_ptr) {
-            const int32_t* tp = a.tile_ptr + (size_t)j * (a.n_tiles + 1) + t;
-            st = tp[0];
-            len = tp[1] - st;
-          } else {
-            st = a.indptr[j];
-            len = a.indptr[j + 1] - st;
+      // quarter-wave g streams the segments of rows g, g + G, ...; lane l
+      // reads entries l, l + 16, ... of a segment, kUnroll of them per pass
+      const int G = kMvThreads / kGroup;
+      const int g = threadIdx.x / kGroup, l = threadIdx.x % kGroup;
+      auto segment = [&](int i, int& st, int& ln) {
+        const int32_t j = sh.ids[i];
+        if (a.tile_ptr) {
+          const int32_t* tp = a.tile_ptr + (size_t)j * (a.n_tiles + 1) + t;
+          st = tp[0];
+          ln = tp[1] - st;
+        } else {
+          st = a.indptr[j];
+          ln = a.indptr[j + 1] - st;
+        }
+      };
+      int st = 0, ln = 0;
+      if (g < total) segment(g, st, ln);
+      for (int i = g; i < total; i += G) {
+        int nst = 0, nln = 0;
+        if (i + G < total) segment(i + G, nst, nln);
+        for (int base = 0; base < ln; base += kGroup * kUnroll) {
+          int col[kUnroll];
+          float val[kUnroll];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            const int e = base + l + kGroup * u;
+            col[u] = e < ln ? a.indices[st + e] : -1;
+            if constexpr (MODE == kCsrData) val[u] = e < ln ? a.data[st + e] : 0.f;
+          }
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            if (col[u] >= 0) {
+              if constexpr (MODE == kCsrHomo) atomicAdd(&acc[col[u] - lo], 1u);
+              else atomicAdd(&acc[col[u] - lo], val[u]);
+            }
           }
         }
-        int tot;
-        const int ex = block_excl_scan(len, sh.scan, &tot);
-        if (i < n_act) {
-          sh.pref[i] = total + ex;
-          sh.start[i] = st;
-        }
-        total += tot;
+        st = nst;
+        ln = nln;
       }
-      if (threadIdx.x == 0) sh.pref[n_act] = total;
-      __syncthreads();
-      // merge-path: wave w walks [e0, e1) of the flattened firing entries
-      const int wv = threadIdx.x / kWave, ln = lane_id();
-      const int per = (total + kMvWaves - 1) / kMvWaves;
-      const int e0 = wv * per, e1 = min(e0 + per, total);
-      if (e0 < e1) {
-        int lo_r = 0, hi_r = n_act;  // largest r with pref[r] <= e0
-        while (hi_r - lo_r > 1) {
-          const int mid = (lo_r + hi_r) >> 1;
-          if (sh.pref[mid] <= e0) lo_r = mid; else hi_r = mid;
-        }
-        int r = lo_r;
-        for (int e = e0 + ln; e < e1 + ln; e += 2 * kWave) {
-          const int ea = e, eb = e + kWave;
-          int ra = r;
-          while (ra + 1 < n_act && sh.pref[ra + 1] <= ea) ++ra;
-          int rb = ra;
-          while (rb + 1 < n_act && sh.pref[rb + 1] <= eb) ++rb;
-          const bool va = ea < e1, vb = eb < e1;
-          const int ia = va ? sh.start[ra] + (ea - sh.pref[ra]) : 0;
-          const int ib = vb ? sh.start[rb] + (eb - sh.pref[rb]) : 0;
-          const int ca = va ? a.indices[ia] : 0;
-          const int cb = vb ? a.indices[ib] : 0;
-          if constexpr (MODE == kCsrHomo) {
-            if (va) atomicAdd(&acc[ca - lo], 1u);
-            if (vb) atomicAdd(&acc[cb - lo], 1u);
-          } else {
-            const float da = va ? a.data[ia] : 0.f;
-            const float db = vb ? a.data[ib] : 0.f;
-            if (va) atomicAdd(&acc[ca - lo], da);
-            if (vb) atomicAdd(&acc[cb - lo], db);
-          }
-          r = rb;
-        }
-      }
-      __syncthreads();
     } else {
       // JIT: one lane per (firing row, block overlapping the tile)
       const int32_t B = a.jit.block;
       const int32_t b_lo = B > 0 ? lo / B : 0;
       const int32_t b_hi = B > 0 ? (hi - 1) / B : 0;
       const int32_t nbt = b_hi - b_lo + 1;
-      const int items = n_act * nbt;
+      const int items = total * nbt;
+      const uint64_t seed = a.jit.seed;
+      const uint32_t K = (uint32_t)a.jit.max_gap;
+      const int32_t wkind = a.jit.wkind, n_post = a.n_post;
+      const float w0 = a.jit.w0, w1 = a.jit.w1;
       for (int it = threadIdx.x; it < items; it += kMvThreads) {
-        const int ai = it / nbt;
-        const uint32_t b = (uint32_t)(b_lo + it % nbt);
+        const int ai = nbt == 1 ? it : it / nbt;
+        const uint32_t b = (uint32_t)(b_lo + (nbt == 1 ? 0 : it % nbt));
         const uint32_t j = (uint32_t)sh.ids[ai];
-        gen_block(a.jit.seed, (uint32_t)a.jit.max_gap, a.n_post, B, j, b, lo, hi, [&](int32_t pos, uint32_t m) {
+        gen_block(seed, K, n_post, B, j, b, lo, hi, [&](int32_t pos, uint32_t m) {
           if constexpr (MODE == kJitHomo) {
             atomicAdd(&acc[pos - lo], 1u);
           } else {
             float unit;
-            atomicAdd(&acc[pos - lo], jit_weight(a.jit.seed, a.jit.wkind, a.jit.w0, a.jit.w1, j, b, m, &unit));
+            atomicAdd(&acc[pos - lo], jit_weight(seed, wkind, w0, w1, j, b, m, &unit));
           }
         });
       }
-      __syncthreads();
     }
+    __syncthreads();  // list consumed before the next sweep overwrites it
+    total = 0;
   }
   __syncthreads();
   if (a.chunks == 1) {
@@ -177,28 +197,63 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
       if constexpr (MODE == kCsrHomo || MODE == kJitHomo) y[lo + i] = (float)acc[i] * a.w;
       else y[lo + i] = acc[i];
     }
+  } else if constexpr (MODE == kCsrHomo || MODE == kJitHomo) {
+    uint16_t* part = reinterpret_cast<uint16_t*>(a.out) + (size_t)c * a.n_post;
+    for (int i = threadIdx.x; i < width; i += kMvThreads) part[lo + i] = (uint16_t)acc[i];
   } else {
-    Acc* part = reinterpret_cast<Acc*>(a.out) + (size_t)c * a.n_post;
+    float* part = reinterpret_cast<float*>(a.out) + (size_t)c * a.n_post;
     for (int i = threadIdx.x; i < width; i += kMvThreads) part[lo + i] = acc[i];
   }
 }
 
-// y[k] = w * sum_c counts[c][k]  (integer sum, one FP32 rounding)
-__global__ void mv_reduce_counts_k(const uint32_t* __restrict__ part, int32_t chunks, int32_t n_post, float w,
+// y[k] = w * sum_c counts[c][k]  (integer sum, one FP32 rounding); four
+// consecutive columns per thread.
+__global__ void mv_reduce_counts_k(const uint16_t* __restrict__ part, int32_t chunks, int32_t n_post, float w,
                                    float* __restrict__ y) {
-  const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t k = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
   if (k >= n_post) return;
-  uint32_t s = 0;
-  for (int c = 0; c < chunks; ++c) s += part[(size_t)c * n_post + k];
-  y[k] = (float)s * w;
+  uint32_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  if (k + 4 <= n_post && (n_post & 3) == 0) {
+    for (int c = 0; c < chunks; ++c) {
+      const uint2 v = *reinterpret_cast<const uint2*>(part + (size_t)c * n_post + k);
+      s0 += v.x & 0xFFFFu;
+      s1 += v.x >> 16;
+      s2 += v.y & 0xFFFFu;
+      s3 += v.y >> 16;
+    }
+    y[k] = (float)s0 * w;
+    y[k + 1] = (float)s1 * w;
+    y[k + 2] = (float)s2 * w;
+    y[k + 3] = (float)s3 * w;
+  } else {
+    for (int q = 0; q < 4 && k + q < n_post; ++q) {
+      uint32_t s = 0;
+      for (int c = 0; c < chunks; ++c) s += part[(size_t)c * n_post + k + q];
+      y[k + q] = (float)s * w;
+    }
+  }
 }
-// y[k] = sum_c part[c][k] in chunk order
+// y[k] = sum_c part[c][k] in chunk order; four consecutive columns per thread.
 __global__ void mv_reduce_f32_k(const float* __restrict__ part, int32_t chunks, int32_t n_post, float* __restrict__ y) {
-  const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t k = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
   if (k >= n_post) return;
-  float s = 0.f;
-  for (int c = 0; c < chunks; ++c) s += part[(size_t)c * n_post + k];
-  y[k] = s;
+  if (k + 4 <= n_post && (n_post & 3) == 0) {
+    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int c = 0; c < chunks; ++c) {
+      const float4 v = *reinterpret_cast<const float4*>(part + (size_t)c * n_post + k);
+      s.x += v.x;
+      s.y += v.y;
+      s.z += v.z;
+      s.w += v.w;
+    }
+    *reinterpret_cast<float4*>(y + k) = s;
+  } else {
+    for (int q = 0; q < 4 && k + q < n_post; ++q) {
+      float s = 0.f;
+      for (int c = 0; c < chunks; ++c) s += part[(size_t)c * n_post + k + q];
+      y[k + q] = s;
+    }
+  }
 }
 
 // Unsorted CSR wider than one tile: counts / sums with device atomics.
@@ -296,7 +351,23 @@ struct MvPlan {
   size_t ws;
 };
 
-static int32_t target_wgs() { return 2 * device_cu_count(); }
+// Row chunks per column tile.  The scatter kernel holds one workgroup per
+// compute unit (LDS), so the grid aims at one wave of workgroups: no chunks
+// (no partials) once the tiles alone cover a quarter of the chip, else
+// enough chunks to fill it, each at least a quarter sweep of rows.  Chunk
+// starts are multiples of 16 (aligned spike loads); 16-bit partial counts
+// cap homogeneous chunks at 65520 rows.
+static void set_chunks(MvPlan& p, int32_t n_pre, bool homo, int32_t n_post) {
+  const int32_t cus = device_cu_count();
+  int32_t want = p.n_tiles >= cus / 4 ? 1 : max(1, cus / p.n_tiles);
+  want = max(1, min(want, (n_pre + kSweep / 4 - 1) / (kSweep / 4)));
+  if (homo && want > 1) want = max(want, (n_pre + 65519) / 65520);
+  int32_t rows = (n_pre + want - 1) / want;
+  rows = (rows + 15) & ~15;
+  p.chunk_rows = max(16, rows);
+  p.chunks = max(1, (n_pre + p.chunk_rows - 1) / p.chunk_rows);
+  p.ws = p.chunks > 1 ? (size_t)p.chunks * n_post * (homo ? 2 : 4) : 0;
+}
 
 static MvPlan plan_csr(const bp_csr* m) {
   MvPlan p{};
@@ -311,33 +382,27 @@ static MvPlan plan_csr(const bp_csr* m) {
     p.ws = (size_t)(m->n_post > 0 ? m->n_post : 1) * sizeof(uint32_t);
     return p;
   }
-  int32_t want = (target_wgs() + p.n_tiles - 1) / p.n_tiles;
-  const int32_t by_rows = (m->n_pre + kMvPiece - 1) / kMvPiece;  // at least one piece per chunk
-  p.chunks = max(1, min(want, max(by_rows, 1)));
-  p.chunk_rows = (m->n_pre + p.chunks - 1) / max(p.chunks, 1);
-  p.chunk_rows = max(1, p.chunk_rows);
-  p.chunks = max(1, (m->n_pre + p.chunk_rows - 1) / p.chunk_rows);
-  p.ws = p.chunks > 1 ? (size_t)p.chunks * m->n_post * sizeof(uint32_t) : 0;
+  set_chunks(p, m->n_pre, m->data == nullptr, m->n_post);
+  // 16-bit partial counts need at most one entry per row and column
+  if (!m->data && !m->sorted && p.chunks > 1) {
+    p.atomic_path = true;
+    p.ws = (size_t)(m->n_post > 0 ? m->n_post : 1) * sizeof(uint32_t);
+  }
   return p;
 }
 
 static MvPlan plan_jit(const bp_jit_conn* c) {
   MvPlan p{};
-  if (c->n_post <= kTileMax) {
+  if (c->block > 0 && c->block <= kTileMax && c->n_post > c->block) {
+    p.tile = c->block;  // one block per tile: every generated target lands in the tile
+  } else if (c->n_post <= kTileMax) {
     p.tile = c->n_post > 0 ? c->n_post : 1;
-  } else if (c->block > 0 && c->block <= kTileMax) {
-    p.tile = (kTileMax / c->block) * c->block;
   } else {
     p.tile = kTileMax;  // whole-row sequences regenerated up to each tile
   }
   p.n_tiles = (int32_t)(((int64_t)c->n_post + p.tile - 1) / p.tile);
   if (p.n_tiles < 1) p.n_tiles = 1;
-  int32_t want = (target_wgs() + p.n_tiles - 1) / p.n_tiles;
-  const int32_t by_rows = (c->n_pre + 255) / 256;
-  p.chunks = max(1, min(want, max(by_rows, 1)));
-  p.chunk_rows = max(1, (c->n_pre + p.chunks - 1) / p.chunks);
-  p.chunks = max(1, (c->n_pre + p.chunk_rows - 1) / p.chunk_rows);
-  p.ws = p.chunks > 1 ? (size_t)p.chunks * c->n_post * sizeof(uint32_t) : 0;
+  set_chunks(p, c->n_pre, c->wkind == kWHomo, c->n_post);
   return p;
 }
 
@@ -358,8 +423,8 @@ static bp_status launch_scatter(const MvArgs& a, const MvPlan& p, hipStream_t st
 static bp_status finish_partials(const MvPlan& p, bool homo, void* ws, int32_t n_post, float w, float* y,
                                  hipStream_t st) {
   if (p.chunks <= 1 || n_post == 0) return BP_OK;
-  const int g = (n_post + 255) / 256;
-  if (homo) mv_reduce_counts_k<<<g, 256, 0, st>>>((const uint32_t*)ws, p.chunks, n_post, w, y);
+  const int g = (n_post + 1023) / 1024;
+  if (homo) mv_reduce_counts_k<<<g, 256, 0, st>>>((const uint16_t*)ws, p.chunks, n_post, w, y);
   else mv_reduce_f32_k<<<g, 256, 0, st>>>((const float*)ws, p.chunks, n_post, y);
   BP_LAUNCHED("mv_reduce_k");
   return BP_OK;
