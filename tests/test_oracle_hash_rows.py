@@ -3,6 +3,7 @@ build (CPU only).  Each test checks the oracle against something other than
 itself: the paper's stated values and expectations, closed forms, exact
 probabilities, library statistics, or invariants."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -12,6 +13,31 @@ import oracle as O
 
 
 # ----------------------------------------------------------------- Philox
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def test_philox_known_answer_vectors():
+    # published known-answer vectors of Philox-4x32-10 (Salmon et al., SC'11)
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) if l.strip() and l[0] != "#"]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        out = O.philox(v[0:4], v[4:6])
+        assert [int(x) for x in out] == v[6:10]
+        many = O.philox_many(np.array([v[0:4]], np.uint32), np.array([v[4:6]], np.uint32))
+        assert [int(x) for x in many[0]] == v[6:10]
+
+
+def test_hash_words_follow_the_known_answer_counter_layout():
+    # H(seed, stream, a, b, k) = word k & 3 of Philox((a, b, k >> 2, stream), (lo(seed), hi(seed))):
+    # the third vector read through the hash interface
+    seed = (0x299f31d0 << 32) | 0xa4093822
+    a, b, blk, stream = 0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344
+    want = [0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1]
+    for w in range(4):
+        assert O.hash_word(seed, stream, a, b, (blk << 2) | w) == want[w]
+
+
 def test_philox_is_a_bijection_on_distinct_counters():
     # For a fixed key every Philox round is invertible, so distinct counters
     # never collide.  A dropped or mis-mixed word typically breaks this.
