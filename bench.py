@@ -2,7 +2,7 @@
 
 Headline workload: the COBA E/I LIF network scaled to 400,000 neurons
 (320,000 excitatory / 80,000 inhibitory), fixed-probability connectivity
-p = 80/N regenerated every step from the seed (JIT, post blocks of 1024),
+p = 80/N regenerated every step from the seed (JIT, post blocks of 2048),
 w_e = 0.6, w_i = 6.7, tau_e = 5 ms, tau_i = 10 ms, V_rest = -60 mV,
 V_th = -50 mV, refractory 5 ms, V0 ~ U(-60, -50) mV, I_ext = 20, dt = 0.1 ms,
 FP32 state.  One bench step = one simulation time step; the default K =
@@ -34,7 +34,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-C2_BLOCK = 1024
+C2_BLOCK = 2048
 
 
 def c2_desc(bp, n=400_000, seed=0):

@@ -116,20 +116,20 @@ __device__ __forceinline__ void gen_block(uint64_t seed, uint32_t K, int32_t n_p
   }
 }
 
-// Weight of connection m of (j, b) for the JIT weight kinds; *unit receives
-// the unit draw (z or u) for the reverse mode.
-__device__ __forceinline__ float jit_weight(uint64_t seed, int wkind, float w0, float w1, uint32_t j, uint32_t b,
-                                            uint32_t m, float* unit) {
+// Weight of connection m of (j, b) for the JIT weight kinds, read from the
+// W sub-stream of (j, b) through `wd` (connections are visited in increasing
+// m, so one Philox call serves two normal or four uniform weights); *unit
+// receives the unit draw (z or u) for the reverse mode.
+__device__ __forceinline__ float jit_weight(DrawSeq& wd, int wkind, float w0, float w1, uint32_t m, float* unit) {
   if (wkind == kWNormal) {
-    const Words4 q = philox10(j, b, m >> 1, kStreamW, (uint32_t)seed, (uint32_t)(seed >> 32));
-    const uint32_t wa = pick(q, 2u * m), wb = pick(q, 2u * m + 1u);
+    const uint32_t wa = wd(2u * m), wb = wd(2u * m + 1u);
     const float u1 = u_open0(wa), u2 = u_open1(wb);
     const float z = sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
     *unit = z;
     return w0 + w1 * z;
   }
   if (wkind == kWUniform) {
-    const float u = u_open1(hash_word(seed, kStreamW, j, b, m));
+    const float u = u_open1(wd(m));
     *unit = u;
     return w0 + (w1 - w0) * u;
   }
@@ -238,23 +238,35 @@ __device__ __forceinline__ void block_excl_scan2(int a, int b, int* scratch, int
 // (vm_drain) before the workgroup barrier that precedes its flag store; a
 // reader issues its coherent data loads only after it has observed the flag.
 // ---------------------------------------------------------------------------
+// Device-coherent (agent scope) relaxed loads and stores through the global
+// address space: global_* instructions count only in vmcnt, so a workgroup
+// barrier (which waits for lgkmcnt) never waits for them, as it would for
+// the generic flat_* forms.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* as_global(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* as_global(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
 __device__ __forceinline__ int ld_coh(const int* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(as_global(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint32_t ld_coh(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(as_global(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_coh(int* p, int v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(as_global(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_coh(uint32_t* p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(as_global(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint64_t ld_coh64(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(as_global(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_coh64(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(as_global(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // Wait until every vector memory operation this wave issued has completed
 // (s_waitcnt vmcnt(0); stores are counted by vmcnt on gfx9-family targets).

@@ -204,12 +204,13 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
         const int ai = nbt == 1 ? it : it / nbt;
         const uint32_t b = (uint32_t)(b_lo + (nbt == 1 ? 0 : it % nbt));
         const uint32_t j = (uint32_t)sh.ids[ai];
+        DrawSeq wd(seed, kStreamW, j, b);
         gen_block(seed, K, n_post, B, j, b, lo, hi, [&](int32_t pos, uint32_t m) {
           if constexpr (MODE == kJitHomo) {
             atomicAdd(&acc[pos - lo], 1u);
           } else {
             float unit;
-            atomicAdd(&acc[pos - lo], jit_weight(seed, wkind, w0, w1, j, b, m, &unit));
+            atomicAdd(&acc[pos - lo], jit_weight(wd, wkind, w0, w1, m, &unit));
           }
         });
       }
@@ -345,19 +346,23 @@ __global__ void jit_backward_k(bp_jit_conn c, const uint8_t* __restrict__ ev, co
     const int32_t nb = c.block > 0 ? (int32_t)(((int64_t)c.n_post + c.block - 1) / c.block) : 1;
     const bool on = ev[j] != 0;
     float acc = 0.f;
+    const uint64_t seed = c.seed;
+    const uint32_t K = (uint32_t)c.max_gap;
+    const int32_t n_post = c.n_post, B = c.block, wkind = c.wkind;
+    const float w0 = c.w0, w1 = c.w1;
     for (int32_t b = 0; b < nb; ++b) {
-      gen_block(c.seed, (uint32_t)c.max_gap, c.n_post, c.block, (uint32_t)j, (uint32_t)b, 0, c.n_post,
-                [&](int32_t pos, uint32_t m) {
-                  float unit;
-                  const float wjk = jit_weight(c.seed, c.wkind, c.w0, c.w1, (uint32_t)j, (uint32_t)b, m, &unit);
-                  const float g = dy[pos];
-                  acc += wjk * g;
-                  if (on) {
-                    if (c.wkind == kWNormal) { g0 += g; g1 += unit * g; }
-                    else if (c.wkind == kWUniform) { g0 += (1.f - unit) * g; g1 += unit * g; }
-                    else g0 += g;
-                  }
-                });
+      DrawSeq wd(seed, kStreamW, (uint32_t)j, (uint32_t)b);
+      gen_block(seed, K, n_post, B, (uint32_t)j, (uint32_t)b, 0, n_post, [&](int32_t pos, uint32_t m) {
+        float unit;
+        const float wjk = jit_weight(wd, wkind, w0, w1, m, &unit);
+        const float g = dy[pos];
+        acc += wjk * g;
+        if (on) {
+          // d w / d w0 and d w / d w1: (1, z) normal, (1 - u, u) uniform, (1, 0) homogeneous
+          g0 += (wkind == kWUniform ? 1.f - unit : 1.f) * g;
+          g1 += (wkind == kWHomo ? 0.f : unit) * g;
+        }
+      });
     }
     if (d_ev) d_ev[j] = acc;
   }

@@ -13,8 +13,8 @@
 //      regenerated per post block from the seed;
 //   3. update the own neurons (synaptic decay + input, COBA/CUBA current,
 //      forward Euler, refractoriness, threshold, reset);
-//   4. compact the own spikes (wave ballots + prefix over waves, ascending)
-//      and publish them.
+//   4. compact the own spikes (wave ballots, one LDS atomic per wave; the
+//      list order carries no meaning) and publish them.
 // Spike records: per workgroup and step parity an array of 64-bit slots,
 // slot 0 = (tag, count), slot 1 + q = (tag, neuron id), tag = step + 1 in the
 // high word.  Each slot is written with one device-coherent 64-bit store, so
@@ -22,8 +22,9 @@
 // writer never waits for its stores to land.  The writer pushes the header
 // and the first 15 ids into a private inbox of every other workgroup of the
 // net, so each reader polls only its own inbox lines (no line is polled by
-// many workgroups) and needs one memory round trip once the data is there;
-// longer lists are completed from the writer's own record.  A one-workgroup
+// many workgroups): a reader polls only the header slot (keeping polling
+// traffic low), then loads the ids that share its 128-byte line; longer lists
+// are completed from the writer's own record.  A one-workgroup
 // net keeps its own list in LDS between steps.
 // Several nets run in one launch (continuous batching): the grid is the
 // concatenation of their workgroup ranges and each net exchanges records only
@@ -45,7 +46,7 @@ constexpr int kRangeMax = kNetThreads * kNPT;  // neurons per workgroup
 constexpr int kIdBatch = 4096;                 // firing rows staged per pass
 constexpr int kMaxWgPerNet = 512;  // one gathering thread per source
 constexpr int kInbox = 16;         // slots per (destination, source) inbox: header + 15 ids
-constexpr int kSpec = 7;                    // ids loaded together with a header
+constexpr int kHeld = kInbox - 1;  // ids a gathering thread holds in registers (one 128-byte inbox line)
 constexpr int kMaxBatch = 48;
 constexpr uint32_t kSpinLimit = 1u << 22;
 
@@ -89,16 +90,14 @@ struct NetShared {
   uint32_t cE[kRangeMax];
   uint32_t cI[kRangeMax];
   int ids[kIdBatch];
-  int own[kRangeMax];  // own spikes of this step, ascending
+  int own[kRangeMax];  // own spikes of this step (order of the wave appends)
   int pref[kIdBatch + 1];
   int start[kIdBatch];
   int srcpref[kMaxWgPerNet + 1];
   int expref[kMaxWgPerNet + 1];
-  int wcnt[kNPT * kNetWaves];
   int scan[2 * (kNetWaves + 1)];
+  int ocnt[2];  // own spikes of the step, by step parity
   int abort_flag;
-  int total;
-  int nloc;  // own spikes of the last step kept in ids[] (one-workgroup nets), -1 if not
 };
 
 __device__ __forceinline__ uint64_t pack(uint32_t tag, uint32_t v) { return ((uint64_t)tag << 32) | v; }
@@ -140,29 +139,36 @@ __device__ __forceinline__ int gather_and_process(const NetDev& N, int self, int
   // several workgroups: header and first ids from the own inbox; one
   // workgroup: its own record (a one-workgroup net has no inbox)
   const uint64_t* r = !src ? nullptr : (N.n_wg > 1 ? inbox(N, par, self, tid) : record(N, par, tid));
-  uint64_t h = 0, v[kSpec];
+  // poll the header alone (light polling traffic), then load the ids
+  uint64_t h = 0;
   if (src) {
     uint32_t spins = 0;
     while (true) {
       h = ld_coh64(&r[0]);
-#pragma unroll
-      for (int q = 0; q < kSpec; ++q) v[q] = ld_coh64(&r[1 + q]);
       if (tag_of(h) == tag) break;
       if (++spins > spin_limit) {
         atomicOr(N.error, 1u);
         sh.abort_flag = 1;
         break;
       }
-      __builtin_amdgcn_s_sleep(1);
+      __builtin_amdgcn_s_sleep(2);
     }
   }
   const int cnt = (src && tag_of(h) == tag) ? min((int)(uint32_t)h, N.range) : 0;
-  if (src) {
+  // the first kHeld ids (the rest of the header's 128-byte line) into registers
+  int held[kHeld];
 #pragma unroll
-    for (int q = 0; q < kSpec; ++q)
-      if (q < cnt) v[q] = wait_slot(r, 1 + q, tag, v[q], spin_limit, N, sh);
+  for (int q = 0; q < kHeld; ++q) held[q] = 0;
+  if (src && cnt > 0) {
+    uint64_t u[kHeld];
+#pragma unroll
+    for (int q = 0; q < kHeld; ++q) u[q] = q < cnt ? ld_coh64(&r[1 + q]) : 0;
+#pragma unroll
+    for (int q = 0; q < kHeld; ++q)
+      if (q < cnt) held[q] = (int)(uint32_t)wait_slot(r, 1 + q, tag, u[q], spin_limit, N, sh);
   }
-  const int extra = cnt > kSpec ? cnt - kSpec : 0;
+  const int nheld = min(cnt, kHeld);
+  const int extra = cnt - nheld;
   int cpos, epos, A, E;
   block_excl_scan2(cnt, extra, sh.scan, &cpos, &epos, &A, &E);
   if (src) {
@@ -178,22 +184,23 @@ __device__ __forceinline__ int gather_and_process(const NetDev& N, int self, int
   for (int q0 = 0; q0 < A; q0 += kIdBatch) {
     const int n = min(kIdBatch, A - q0);
 #pragma unroll
-    for (int q = 0; q < kSpec; ++q) {
+    for (int q = 0; q < kHeld; ++q) {
       const int pos = cpos + q - q0;
-      if (q < cnt && pos >= 0 && pos < n) sh.ids[pos] = (int)(uint32_t)v[q];
+      if (q < nheld && pos >= 0 && pos < n) sh.ids[pos] = held[q];
     }
-    // ids beyond the first kSpec of each record, spread over the workgroup
+    // ids beyond the first kHeld of each record (from the record), spread
+    // over the workgroup
     for (int e = tid; e < E; e += kNetThreads) {
       int l = 0, hh = N.n_wg;  // largest l with expref[l] <= e
       while (hh - l > 1) {
         const int m = (l + hh) >> 1;
         if (sh.expref[m] <= e) l = m; else hh = m;
       }
-      const int q = kSpec + (e - sh.expref[l]);
+      const int q = kHeld + (e - sh.expref[l]);
       const int pos = sh.srcpref[l] + q - q0;
       const int cnt_l = sh.srcpref[l + 1] - sh.srcpref[l];
       if (pos >= 0 && pos < n && q < cnt_l && q < N.range) {
-        const uint64_t* rr = (N.n_wg > 1 && q < kInbox - 1) ? inbox(N, par, self, l) : record(N, par, l);
+        const uint64_t* rr = record(N, par, l);
         const uint64_t x = wait_slot(rr, 1 + q, tag, ld_coh64(&rr[1 + q]), spin_limit, N, sh);
         sh.ids[pos] = (int)(uint32_t)x;
       }
@@ -238,7 +245,7 @@ __global__ void __launch_bounds__(kNetThreads) net_run_k(BatchArgs args) {
   }
   if (tid == 0) {
     sh.abort_flag = 0;
-    sh.nloc = -1;
+    sh.ocnt[0] = sh.ocnt[1] = 0;
   }
   __syncthreads();
 
@@ -270,23 +277,23 @@ __global__ void __launch_bounds__(kNetThreads) net_run_k(BatchArgs args) {
         if (i < nact) {
           const int32_t j = sh.ids[i];
           if (N.n_wg == 1) {
-            st = N.indptr[j];
-            len = N.indptr[j + 1] - st;
+            st = as_global(N.indptr)[j];
+            len = as_global(N.indptr)[j + 1] - st;
           } else if (N.blkptr) {
-            const int32_t* bp = N.blkptr + (size_t)j * (N.nb + 1);
+            const auto* bp = as_global(N.blkptr) + (size_t)j * (N.nb + 1);
             st = bp[b_lo];
             len = bp[b_hi + 1] - st;
           } else {
-            int32_t l = N.indptr[j], h = N.indptr[j + 1];
+            int32_t l = as_global(N.indptr)[j], h = as_global(N.indptr)[j + 1];
             while (l < h) {
               const int32_t m = (l + h) >> 1;
-              if (N.indices[m] < lo) l = m + 1; else h = m;
+              if (as_global(N.indices)[m] < lo) l = m + 1; else h = m;
             }
             st = l;
-            h = N.indptr[j + 1];
+            h = as_global(N.indptr)[j + 1];
             while (l < h) {
               const int32_t m = (l + h) >> 1;
-              if (N.indices[m] < hi) l = m + 1; else h = m;
+              if (as_global(N.indices)[m] < hi) l = m + 1; else h = m;
             }
             len = l - st;
           }
@@ -313,7 +320,7 @@ __global__ void __launch_bounds__(kNetThreads) net_run_k(BatchArgs args) {
         for (int ee = e0 + lane_id(); ee - lane_id() < e1; ee += kWave) {
           if (ee < e1) {
             while (r + 1 < nact && sh.pref[r + 1] <= ee) ++r;
-            const int32_t col = N.indices[sh.start[r] + (ee - sh.pref[r])];
+            const int32_t col = as_global(N.indices)[sh.start[r] + (ee - sh.pref[r])];
             if (col >= lo && col < hi) {
               atomicAdd(&((sh.ids[r] < N.n_exc) ? sh.cE : sh.cI)[col - lo], 1u);
               ++ev_local;
@@ -325,19 +332,24 @@ __global__ void __launch_bounds__(kNetThreads) net_run_k(BatchArgs args) {
     __syncthreads();
   };
 
+  int nloc = -1;  // one workgroup: own spikes of the last step kept in sh.ids, -1 if not
   for (int32_t s = 0; s < L.n_steps; ++s) {
     const int64_t t = L.t0 + s;
     const int pin = (int)((t + 1) & 1);  // parity of step t-1
     const int pout = (int)(t & 1);
     int A;
-    if (sh.nloc >= 0) {
-      A = sh.nloc;  // own list of the last step, still in LDS
+    if (nloc >= 0) {
+      A = nloc;  // own list of the last step, still in LDS
       if (A > 0) propagate(A);
+      else __syncthreads();
     } else {
       A = gather_and_process(N, w, pin, (uint32_t)t, args.spin_limit, sh, propagate);
       if (A < 0) break;
     }
-    if (w == 0 && tid == 0 && L.counts && s > 0) L.counts[s - 1] = A;
+    // (every path above passed a barrier after the previous step's readers
+    // of the next step's spike counter)
+    if (tid == 0) sh.ocnt[(t + 1) & 1] = 0;
+    if (w == 0 && tid == 0 && L.counts && s > 0) as_global(L.counts)[s - 1] = A;
 
     // neuron update: exactly the oracle's FP32 operation order
     uint32_t sbits = 0;
@@ -370,7 +382,7 @@ __global__ void __launch_bounds__(kNetThreads) net_run_k(BatchArgs args) {
           ref[i] -= 1;
         } else {
           float ix = N.i_ext;
-          if (iext) ix = ix + iext[lo + k];
+          if (iext) ix = ix + as_global(iext)[lo + k];
           float I;
           if (N.model == 0) I = ge[i] * (N.e_exc - V[i]) + gi[i] * (N.e_inh - V[i]) + ix;
           else I = ge[i] + gi[i] + ix;
@@ -383,37 +395,31 @@ __global__ void __launch_bounds__(kNetThreads) net_run_k(BatchArgs args) {
           V[i] = v;
         }
         if (spk) sbits |= 1u << i;
-        if (L.raster) L.raster[(size_t)s * N.n + lo + k] = spk ? 1 : 0;
+        if (L.raster) as_global(L.raster)[(size_t)s * N.n + lo + k] = spk ? 1 : 0;
       }
     }
-    // compaction of the own spikes, ascending in neuron id
+    // compaction of the own spikes: one LDS atomic per wave and neuron slot
+    // reserves the wave's positions (the list order carries no meaning: every
+    // reader accumulates integer counts)
 #pragma unroll
     for (int i = 0; i < kNPT; ++i) {
       const uint64_t m = __ballot((sbits >> i) & 1u);
-      if (lane_id() == 0) sh.wcnt[i * kNetWaves + wave] = __popcll(m);
-    }
-    __syncthreads();
-    if (wave == 0) {
-      const int v = sh.wcnt[lane_id()];
-      const int inc = wave_incl_scan(v);
-      sh.wcnt[lane_id()] = inc - v;
-      if (lane_id() == kWave - 1) sh.total = inc;
+      if (m) {
+        int base = 0;
+        if (lane_id() == 0) base = atomicAdd(&sh.ocnt[t & 1], (int)__popcll(m));
+        base = __builtin_amdgcn_readfirstlane(base);
+        if ((sbits >> i) & 1u) {
+          const int pos = base + mask_rank(m);
+          const int k = lo + i * kNetThreads + tid;
+          if (pos < R) sh.own[pos] = k;
+          if (N.n_wg == 1 && pos < kIdBatch) sh.ids[pos] = k;
+        }
+      }
     }
     __syncthreads();
     const uint32_t tag = (uint32_t)(t + 1);
-    const int total = min(sh.total, R);
-    const bool keep_local = N.n_wg == 1 && total <= kIdBatch;
-#pragma unroll
-    for (int i = 0; i < kNPT; ++i) {
-      const uint64_t m = __ballot((sbits >> i) & 1u);
-      if ((sbits >> i) & 1u) {
-        const int pos = sh.wcnt[i * kNetWaves + wave] + mask_rank(m);
-        const int k = lo + i * kNetThreads + tid;
-        if (pos < R) sh.own[pos] = k;
-        if (keep_local && pos < total) sh.ids[pos] = k;
-      }
-    }
-    __syncthreads();
+    const int total = min(sh.ocnt[t & 1], R);
+    nloc = (N.n_wg == 1 && total <= kIdBatch) ? total : -1;
     // full own record (persistence, long lists) ...
     uint64_t* out = record(N, pout, w);
     for (int q = tid; q < total; q += kNetThreads) st_coh64(&out[1 + q], pack(tag, (uint32_t)sh.own[q]));
@@ -428,8 +434,6 @@ __global__ void __launch_bounds__(kNetThreads) net_run_k(BatchArgs args) {
         st_coh64(inbox(N, pout, d, w) + q, v);
       }
     }
-    if (tid == 0) sh.nloc = keep_local ? total : -1;
-    __syncthreads();
   }
 
 #pragma unroll
@@ -464,7 +468,7 @@ __global__ void __launch_bounds__(kNetThreads) net_run_k(BatchArgs args) {
     }
     int tot;
     block_excl_scan(c, sh.scan, &tot);
-    if (tid == 0) L.counts[L.n_steps - 1] = tot;
+    if (tid == 0) as_global(L.counts)[L.n_steps - 1] = tot;
   }
 }
 
@@ -499,27 +503,28 @@ __global__ void net_init_k(const NetDev* __restrict__ Np, float v0_lo, float v0_
   if (i == 0) *N.error = 0u;
 }
 
-// Checkpoint export: state and the spikes of the last step (records of parity
-// par, tagged `tag`).
-__global__ void net_get_state_k(const NetDev* __restrict__ Np, int par, uint32_t tag, float* V, float* ge, float* gi,
-                                int32_t* ref, uint8_t* s) {
+// Checkpoint export by the owning workgroup: state and the spikes of the last
+// step (records of parity par, tagged `tag`; ids in any order).
+__global__ void __launch_bounds__(kNetThreads) net_get_state_k(const NetDev* __restrict__ Np, int par, uint32_t tag,
+                                                                float* V, float* ge, float* gi, int32_t* ref,
+                                                                uint8_t* s) {
   const NetDev N = *Np;
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < N.n) {
+  const int w = blockIdx.x;
+  const int32_t lo = w * N.range, hi = min(lo + N.range, N.n);
+  for (int32_t i = lo + threadIdx.x; i < hi; i += kNetThreads) {
     V[i] = N.V[i];
     ge[i] = N.ge[i];
     gi[i] = N.gi[i];
     ref[i] = N.ref[i];
-    const int w = (int)(i / N.range);
-    const uint64_t* r = N.rec + ((size_t)par * N.n_wg + w) * (size_t)(N.range + 1);
-    const uint64_t h = r[0];
-    const int c = ((uint32_t)(h >> 32) == tag) ? (int)(uint32_t)h : 0;
-    int a = 0, b = c;  // ids are ascending
-    while (a < b) {
-      const int m = (a + b) >> 1;
-      if ((int64_t)(uint32_t)r[1 + m] < i) a = m + 1; else b = m;
-    }
-    s[i] = (a < c && (int64_t)(uint32_t)r[1 + a] == i) ? 1 : 0;
+    s[i] = 0;
+  }
+  __syncthreads();
+  const uint64_t* r = N.rec + ((size_t)par * N.n_wg + w) * (size_t)(N.range + 1);
+  const uint64_t h = r[0];
+  const int c = ((uint32_t)(h >> 32) == tag) ? min((int)(uint32_t)h, N.range) : 0;
+  for (int q = threadIdx.x; q < c; q += kNetThreads) {
+    const int32_t k = (int32_t)(uint32_t)r[1 + q];
+    if (k >= lo && k < hi) s[k] = 1;
   }
 }
 
@@ -647,8 +652,7 @@ static bp_status make_layout(const bp_net_desc* d, Layout* L) {
   L->off_ge = take((size_t)n * 4);
   L->off_gi = take((size_t)n * 4);
   L->off_ref = take((size_t)n * 4);
-  // + kSpec slots: the gather loads a header and the next kSpec slots together
-  L->off_rec = take(((size_t)2 * n_wg * (range + 1) + kSpec) * 8);
+  L->off_rec = take((size_t)2 * n_wg * (range + 1) * 8);
   L->off_inbox = n_wg > 1 ? take((size_t)2 * n_wg * n_wg * kInbox * 8) : 0;
   L->off_events = take((size_t)n_wg * 8);
   L->off_error = take(4);
@@ -887,7 +891,7 @@ bp_status bp_get_state(bp_net net, void* dst, size_t bytes, bp_stream stream) {
   const int64_t n = net->desc.n;
   char* p = (char*)dst;
   const int par = (int)((net->step + 1) & 1);
-  net_get_state_k<<<(unsigned)((n + 255) / 256), 256, 0, as_stream(stream)>>>(
+  net_get_state_k<<<net->lay.n_wg, kNetThreads, 0, as_stream(stream)>>>(
       net->dev, par, (uint32_t)net->step, (float*)p, (float*)(p + 4 * n), (float*)(p + 8 * n), (int32_t*)(p + 12 * n), (uint8_t*)(p + 16 * n));
   BP_LAUNCHED("net_get_state_k");
   return BP_OK;

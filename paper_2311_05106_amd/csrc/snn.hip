@@ -81,37 +81,48 @@ struct SnnDev {
 
 // Transposed connectivity: for post neuron k the (pre j, CSR position)
 // pairs with j ascending.  Rows are sorted, so membership is a binary search.
+// CSC transpose of the recurrent CSR (rows ascending within each column), one
+// workgroup: thread k finds column k's entries by a binary search in every
+// row; the CSR is first copied to LDS when it fits.
+constexpr int kCscLds = 30720;  // ints (120 KB)
 __global__ void __launch_bounds__(1024) snn_csc_k(SnnDev m) {
   __shared__ int scratch[2 * (1024 / kWave + 1)];
   __shared__ int base_s;
+  __shared__ int lds[kCscLds];
+  const bool in_lds = (int64_t)m.N + 1 + m.nnz <= kCscLds;
   if (threadIdx.x == 0) base_s = 0;
+  if (in_lds) {
+    for (int i = threadIdx.x; i <= m.N; i += blockDim.x) lds[i] = m.indptr[i];
+    for (int i = threadIdx.x; i < m.nnz; i += blockDim.x) lds[m.N + 1 + i] = m.indices[i];
+  }
   __syncthreads();
+  const int* ip = in_lds ? lds : m.indptr;
+  const int* ix = in_lds ? lds + m.N + 1 : m.indices;
+  // entry of row j holding column k, or -1
+  auto find = [&](int j, int k) {
+    int lo = ip[j], hi = ip[j + 1];
+    const int end = hi;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (ix[mid] < k) lo = mid + 1; else hi = mid;
+    }
+    return (lo < end && ix[lo] == k) ? lo : -1;
+  };
   for (int k0 = 0; k0 < m.N; k0 += blockDim.x) {
     const int k = k0 + threadIdx.x;
     int cnt = 0;
     if (k < m.N)
-      for (int j = 0; j < m.N; ++j) {
-        int lo = m.indptr[j], hi = m.indptr[j + 1];
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (m.indices[mid] < k) lo = mid + 1; else hi = mid;
-        }
-        if (lo < m.indptr[j + 1] && m.indices[lo] == k) ++cnt;
-      }
+      for (int j = 0; j < m.N; ++j) cnt += find(j, k) >= 0;
     int tot;
     const int ex = block_excl_scan(cnt, scratch, &tot);
     int pos = base_s + ex;
     if (k < m.N) {
       m.cptr[k] = pos;
       for (int j = 0; j < m.N; ++j) {
-        int lo = m.indptr[j], hi = m.indptr[j + 1];
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (m.indices[mid] < k) lo = mid + 1; else hi = mid;
-        }
-        if (lo < m.indptr[j + 1] && m.indices[lo] == k && pos < m.nnz) {
+        const int e = find(j, k);
+        if (e >= 0 && pos < m.nnz) {
           m.cj[pos] = j;
-          m.cidx[pos] = lo;
+          m.cidx[pos] = e;
           ++pos;
         }
       }
