@@ -122,9 +122,10 @@ __device__ __forceinline__ void gen_block(uint64_t seed, uint32_t K, int32_t n_p
 // receives the unit draw (z or u) for the reverse mode.
 __device__ __forceinline__ float jit_weight(DrawSeq& wd, int wkind, float w0, float w1, uint32_t m, float* unit) {
   if (wkind == kWNormal) {
+    // Box-Muller with the hardware log2 / sqrt / cos(2 pi x) instructions
     const uint32_t wa = wd(2u * m), wb = wd(2u * m + 1u);
     const float u1 = u_open0(wa), u2 = u_open1(wb);
-    const float z = sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
+    const float z = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1)) * __builtin_amdgcn_cosf(u2);
     *unit = z;
     return w0 + w1 * z;
   }
@@ -238,6 +239,18 @@ __device__ __forceinline__ void block_excl_scan2(int a, int b, int* scratch, int
 // (vm_drain) before the workgroup barrier that precedes its flag store; a
 // reader issues its coherent data loads only after it has observed the flag.
 // ---------------------------------------------------------------------------
+// FP32 add into LDS by compare-and-swap: on gfx950 the native LDS float
+// atomic add runs about 8x slower than this loop at low contention.
+__device__ __forceinline__ void lds_add_f32(float* p, float v) {
+  uint32_t* q = reinterpret_cast<uint32_t*>(p);
+  uint32_t old = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  while (true) {
+    const uint32_t seen = old;
+    old = atomicCAS(q, seen, __float_as_uint(__uint_as_float(seen) + v));
+    if (old == seen) break;
+  }
+}
+
 // Device-coherent (agent scope) relaxed loads and stores through the global
 // address space: global_* instructions count only in vmcnt, so a workgroup
 // barrier (which waits for lgkmcnt) never waits for them, as it would for

@@ -13,9 +13,10 @@
 // homogeneous: a chunk adds at most one per row to any column) and a second
 // kernel sums the partials in chunk order (no global atomics: device atomics
 // run far below HBM rate on this chip).
-//   CSR segments are streamed by quarter-waves (16 lanes, 8 loads in flight
-//   per lane, the next segment's bounds fetched ahead), so a wave reads four
-//   segments per instruction, coalesced.
+//   CSR segments are streamed by quarter-waves (16 lanes), several rows per
+//   group at once (40 loads in flight per lane for counts, the next rows'
+//   bounds fetched ahead), so a wave reads four segments per instruction,
+//   coalesced.
 //   JIT rows are regenerated per (row, block) by one lane each; the tile is
 //   one block, so no lane generates targets outside its tile, and with
 //   enough blocks to cover the chip no row chunks (and no partials) are used.
@@ -30,7 +31,7 @@ constexpr int kSweep = kMvThreads * kRowsPerLane;  // rows examined per sweep
 constexpr int kIdCap = kSweep + 4096;              // firing rows listed before a flush
 constexpr int kTileMax = 16384;                    // LDS tile columns (64 KB)
 constexpr int kGroup = 16;                         // lanes streaming one CSR segment
-constexpr int kUnroll = 8;                         // loads in flight per lane
+constexpr int kSegLoads = 10;                      // loads per lane and segment pass (160 entries)
 
 enum MvMode { kCsrHomo = 0, kCsrData = 1, kJitHomo = 2, kJitWeighted = 3 };
 
@@ -123,13 +124,15 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
 
     if constexpr (MODE == kCsrHomo || MODE == kCsrData) {
       // quarter-wave g streams the segments of rows g, g + G, ...; lane l
-      // reads entries l, l + 16, ... of a segment, kUnroll of them per pass
-      // of 128 entries.  Passes are software-pipelined: the loads of the next
-      // pass (same row or the next one, whose bounds are fetched a row ahead)
-      // are issued before the LDS adds of the current pass.
+      // reads entries l, l + 16, ... of a segment.  Rows go in batches of R
+      // per group: the loads of all R segments (kSegLoads per lane, 160
+      // entries each) are issued together, then the bounds of the next batch,
+      // then the LDS adds; the rare entries beyond 160 follow row by row.
+      constexpr int R = MODE == kCsrHomo ? 4 : 2;
+      constexpr int U = kSegLoads;
+      constexpr int kPass = kGroup * U;
       const int G = kMvThreads / kGroup;
       const int g = threadIdx.x / kGroup, l = threadIdx.x % kGroup;
-      constexpr int kPass = kGroup * kUnroll;
       auto segment = [&](int i, int& st, int& ln) {
         st = 0;
         ln = 0;
@@ -144,49 +147,54 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
           ln = a.indptr[j + 1] - st;
         }
       };
-      auto load = [&](int st, int ln, int base, int (&col)[kUnroll], float (&val)[kUnroll]) {
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const int e = base + l + kGroup * u;
-          col[u] = e < ln ? a.indices[st + e] : -1;
-          if constexpr (MODE == kCsrData) val[u] = e < ln ? a.data[st + e] : 0.f;
-        }
+      auto add = [&](int c, float v) {
+        if constexpr (MODE == kCsrHomo) atomicAdd(&acc[c - lo], 1u);
+        else lds_add_f32(&acc[c - lo], v);
       };
-      int i = g, st, ln, base = 0;
-      segment(i, st, ln);
-      int pst, pln;  // bounds of row i + G
-      segment(i + G, pst, pln);
-      int col[kUnroll];
-      float val[kUnroll];
-      load(st, ln, 0, col, val);
-      while (i < total) {
-        // next pass
-        int ni = i, nst = st, nln = ln, nbase = base + kPass;
-        if (nbase >= ln) {
-          ni = i + G;
-          nst = pst;
-          nln = pln;
-          nbase = 0;
-          segment(ni + G, pst, pln);
-        }
-        int ncol[kUnroll];
-        float nval[kUnroll];
-        load(nst, nln, nbase, ncol, nval);
+      int st[R], ln[R];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          if (col[u] >= 0) {
-            if constexpr (MODE == kCsrHomo) atomicAdd(&acc[col[u] - lo], 1u);
-            else atomicAdd(&acc[col[u] - lo], val[u]);
+      for (int r = 0; r < R; ++r) segment(g + r * G, st[r], ln[r]);
+      for (int i0 = g; i0 < total; i0 += R * G) {
+        int col[R][U];
+        float val[R][U];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int e = l + kGroup * u;
+            col[r][u] = e < ln[r] ? a.indices[st[r] + e] : -1;
+            if constexpr (MODE == kCsrData) val[r][u] = e < ln[r] ? a.data[st[r] + e] : 0.f;
           }
         }
-        i = ni;
-        st = nst;
-        ln = nln;
-        base = nbase;
+        int nst[R], nln[R];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          col[u] = ncol[u];
-          if constexpr (MODE == kCsrData) val[u] = nval[u];
+        for (int r = 0; r < R; ++r) segment(i0 + (R + r) * G, nst[r], nln[r]);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            if (col[r][u] >= 0) add(col[r][u], MODE == kCsrData ? val[r][u] : 0.f);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          for (int base = kPass; base < ln[r]; base += kPass) {
+            int c2[U];
+            float v2[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const int e = base + l + kGroup * u;
+              c2[u] = e < ln[r] ? a.indices[st[r] + e] : -1;
+              if constexpr (MODE == kCsrData) v2[u] = e < ln[r] ? a.data[st[r] + e] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+              if (c2[u] >= 0) add(c2[u], MODE == kCsrData ? v2[u] : 0.f);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          st[r] = nst[r];
+          ln[r] = nln[r];
         }
       }
     } else {
@@ -210,7 +218,7 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
             atomicAdd(&acc[pos - lo], 1u);
           } else {
             float unit;
-            atomicAdd(&acc[pos - lo], jit_weight(wd, wkind, w0, w1, m, &unit));
+            lds_add_f32(&acc[pos - lo], jit_weight(wd, wkind, w0, w1, m, &unit));
           }
         });
       }
@@ -384,14 +392,13 @@ struct MvPlan {
 };
 
 // Row chunks per column tile.  The scatter kernel holds one workgroup per
-// compute unit (LDS), so the grid aims at one wave of workgroups: no chunks
-// (no partials) once the tiles alone cover a quarter of the chip, else
-// enough chunks to fill it, each at least a quarter sweep of rows.  Chunk
-// starts are multiples of 16 (aligned spike loads); 16-bit partial counts
-// cap homogeneous chunks at 65520 rows.
+// compute unit (LDS), so the grid aims at one wave of workgroups: as many
+// chunks as keep tiles x chunks within the compute units, each at least a
+// quarter sweep of rows.  Chunk starts are multiples of 16 (aligned spike
+// loads); 16-bit partial counts cap homogeneous chunks at 65520 rows.
 static void set_chunks(MvPlan& p, int32_t n_pre, bool homo, int32_t n_post) {
   const int32_t cus = device_cu_count();
-  int32_t want = p.n_tiles >= cus / 4 ? 1 : max(1, cus / p.n_tiles);
+  int32_t want = max(1, cus / p.n_tiles);
   want = max(1, min(want, (n_pre + kSweep / 4 - 1) / (kSweep / 4)));
   if (homo && want > 1) want = max(want, (n_pre + 65519) / 65520);
   int32_t rows = (n_pre + want - 1) / want;
