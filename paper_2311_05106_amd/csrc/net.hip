@@ -212,14 +212,11 @@ __device__ __forceinline__ int gather_and_process(const NetDev& N, int self, int
   return A;
 }
 
-__global__ void __launch_bounds__(kNetThreads) net_run_k(BatchArgs args) {
-  __shared__ NetShared sh;
-  int e = 0;
-  while (e < args.n_nets && (int)blockIdx.x >= args.e[e].wg_begin + args.e[e].n_wg) ++e;
-  if (e >= args.n_nets) return;
-  const NetLaunch L = args.e[e];
-  const NetDev N = *L.net;
-  const int w = (int)blockIdx.x - L.wg_begin;
+// One workgroup's run of L.n_steps steps of net N (CONN: stored CSR = 0,
+// JIT = 1; specialised so each path keeps its own values in registers).
+template <int CONN>
+__device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, int w, uint32_t spin_limit,
+                                         NetShared& sh) {
   const int tid = threadIdx.x, wave = tid / kWave;
   const int32_t lo = w * N.range;
   const int32_t hi = min(lo + N.range, N.n);
@@ -257,7 +254,7 @@ __global__ void __launch_bounds__(kNetThreads) net_run_k(BatchArgs args) {
 
   // accumulate the targets of the staged firing rows sh.ids[0, nact)
   auto propagate = [&](int nact) {
-    if (N.conn == 1) {
+    if constexpr (CONN == 1) {
       const int items = nact * nbt;
       for (int it = tid; it < items; it += kNetThreads) {
         const int ai = it / nbt;
@@ -343,7 +340,7 @@ __global__ void __launch_bounds__(kNetThreads) net_run_k(BatchArgs args) {
       if (A > 0) propagate(A);
       else __syncthreads();
     } else {
-      A = gather_and_process(N, w, pin, (uint32_t)t, args.spin_limit, sh, propagate);
+      A = gather_and_process(N, w, pin, (uint32_t)t, spin_limit, sh, propagate);
       if (A < 0) break;
     }
     // (every path above passed a barrier after the previous step's readers
@@ -463,13 +460,25 @@ __global__ void __launch_bounds__(kNetThreads) net_run_k(BatchArgs args) {
     int c = 0;
     if (tid < N.n_wg) {
       const uint64_t* r = N.n_wg > 1 ? inbox(N, par, 0, tid) : record(N, par, tid);
-      const uint64_t hh = wait_slot(r, 0, (uint32_t)t_end, ld_coh64(&r[0]), args.spin_limit, N, sh);
+      const uint64_t hh = wait_slot(r, 0, (uint32_t)t_end, ld_coh64(&r[0]), spin_limit, N, sh);
       if (tag_of(hh) == (uint32_t)t_end) c = (int)(uint32_t)hh;
     }
     int tot;
     block_excl_scan(c, sh.scan, &tot);
     if (tid == 0) as_global(L.counts)[L.n_steps - 1] = tot;
   }
+}
+
+__global__ void __launch_bounds__(kNetThreads) net_run_k(BatchArgs args) {
+  __shared__ NetShared sh;
+  int e = 0;
+  while (e < args.n_nets && (int)blockIdx.x >= args.e[e].wg_begin + args.e[e].n_wg) ++e;
+  if (e >= args.n_nets) return;
+  const NetLaunch L = args.e[e];
+  const NetDev N = *L.net;
+  const int w = (int)blockIdx.x - L.wg_begin;
+  if (N.conn == 1) net_body<1>(L, N, w, args.spin_limit, sh);
+  else net_body<0>(L, N, w, args.spin_limit, sh);
 }
 
 // Initial state: V0 from the hash (FP64 arithmetic, one rounding), zero
