@@ -98,7 +98,12 @@ struct NetShared {
   int scan[2 * (kNetWaves + 1)];
   int ocnt[2];  // own spikes of the step, by step parity
   int abort_flag;
+  // neuron and synapse constants of the update, read from LDS there (as
+  // scalars they would crowd the scalar registers of the whole step loop)
+  float kc[12];
 };
+
+enum { kcWe, kcWi, kcDe, kcDi, kcIext, kcEe, kcEi, kcA, kcVrest, kcR, kcVth, kcVreset };
 
 __device__ __forceinline__ uint64_t pack(uint32_t tag, uint32_t v) { return ((uint64_t)tag << 32) | v; }
 __device__ __forceinline__ uint32_t tag_of(uint64_t s) { return (uint32_t)(s >> 32); }
@@ -126,6 +131,37 @@ __device__ __forceinline__ uint64_t wait_slot(const uint64_t* r, int q, uint32_t
     v = ld_coh64(&r[q]);
   }
   return v;
+}
+
+// Exclusive prefix sums of a and b over threads [0, nsrc) with one barrier
+// (the other threads pass zeros and skip the wave scans); totals to all.
+__device__ __forceinline__ void src_scan2(int a, int b, int nsrc, int* scratch, int* ea, int* eb, int* ta, int* tb) {
+  const int l = lane_id(), w = threadIdx.x / kWave;
+  const int nw = min((nsrc + kWave - 1) / kWave, kNetWaves);
+  int ia = 0, ib = 0;
+  if (w < nw) {
+    ia = wave_incl_scan(a);
+    ib = wave_incl_scan(b);
+    if (l == kWave - 1) {
+      scratch[w] = ia;
+      scratch[kNetWaves + w] = ib;
+    }
+  }
+  __syncthreads();
+  int pa = 0, pb = 0, sa = 0, sb = 0;
+  for (int q = 0; q < nw; ++q) {
+    const int x = scratch[q], y = scratch[kNetWaves + q];
+    if (q < w) {
+      pa += x;
+      pb += y;
+    }
+    sa += x;
+    sb += y;
+  }
+  *ea = pa + ia - a;
+  *eb = pb + ib - b;
+  *ta = sa;
+  *tb = sb;
 }
 
 // Gathers the spikes of the previous step (records tagged `tag` of parity
@@ -170,23 +206,27 @@ __device__ __forceinline__ int gather_and_process(const NetDev& N, int self, int
   const int nheld = min(cnt, kHeld);
   const int extra = cnt - nheld;
   int cpos, epos, A, E;
-  block_excl_scan2(cnt, extra, sh.scan, &cpos, &epos, &A, &E);
-  if (src) {
-    sh.srcpref[tid] = cpos;
-    sh.expref[tid] = epos;
-  }
-  if (tid == 0) {
-    sh.srcpref[N.n_wg] = A;
-    sh.expref[N.n_wg] = E;
-  }
-  __syncthreads();
+  src_scan2(cnt, extra, N.n_wg, sh.scan, &cpos, &epos, &A, &E);
   if (sh.abort_flag) return -1;
+  if (E > 0) {  // some list is longer than an inbox line: per-source offsets for the record loads
+    if (src) {
+      sh.srcpref[tid] = cpos;
+      sh.expref[tid] = epos;
+    }
+    if (tid == 0) {
+      sh.srcpref[N.n_wg] = A;
+      sh.expref[N.n_wg] = E;
+    }
+    __syncthreads();
+  }
   for (int q0 = 0; q0 < A; q0 += kIdBatch) {
     const int n = min(kIdBatch, A - q0);
+    if (src && nheld > 0) {  // waves without sources skip the staging
 #pragma unroll
-    for (int q = 0; q < kHeld; ++q) {
-      const int pos = cpos + q - q0;
-      if (q < nheld && pos >= 0 && pos < n) sh.ids[pos] = held[q];
+      for (int q = 0; q < kHeld; ++q) {
+        const int pos = cpos + q - q0;
+        if (q < nheld && pos >= 0 && pos < n) sh.ids[pos] = held[q];
+      }
     }
     // ids beyond the first kHeld of each record (from the record), spread
     // over the workgroup
@@ -243,6 +283,18 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
   if (tid == 0) {
     sh.abort_flag = 0;
     sh.ocnt[0] = sh.ocnt[1] = 0;
+    sh.kc[kcWe] = N.w_exc;
+    sh.kc[kcWi] = N.w_inh;
+    sh.kc[kcDe] = N.de;
+    sh.kc[kcDi] = N.di;
+    sh.kc[kcIext] = N.i_ext;
+    sh.kc[kcEe] = N.e_exc;
+    sh.kc[kcEi] = N.e_inh;
+    sh.kc[kcA] = N.a;
+    sh.kc[kcVrest] = N.v_rest;
+    sh.kc[kcR] = N.r;
+    sh.kc[kcVth] = N.v_th;
+    sh.kc[kcVreset] = N.v_reset;
   }
   __syncthreads();
 
@@ -355,38 +407,31 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
 #pragma unroll
     for (int i = 0; i < kNPT; ++i) {
       const int k = i * kNetThreads + tid;
-      ce[i] = k < R ? sh.cE[k] : 0u;
-      ci[i] = k < R ? sh.cI[k] : 0u;
+      // read and clear in one LDS exchange
+      ce[i] = k < R ? atomicExch(&sh.cE[k], 0u) : 0u;
+      ci[i] = k < R ? atomicExch(&sh.cI[k], 0u) : 0u;
     }
 #pragma unroll
     for (int i = 0; i < kNPT; ++i) {
       const int k = i * kNetThreads + tid;
       if (k < R) {
-        sh.cE[k] = 0u;
-        sh.cI[k] = 0u;
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < kNPT; ++i) {
-      const int k = i * kNetThreads + tid;
-      if (k < R) {
-        const float xe = (float)ce[i] * N.w_exc;
-        const float xi = (float)ci[i] * N.w_inh;
-        ge[i] = ge[i] * N.de + xe;
-        gi[i] = gi[i] * N.di + xi;
+        const float xe = (float)ce[i] * sh.kc[kcWe];
+        const float xi = (float)ci[i] * sh.kc[kcWi];
+        ge[i] = ge[i] * sh.kc[kcDe] + xe;
+        gi[i] = gi[i] * sh.kc[kcDi] + xi;
         bool spk = false;
         if (ref[i] > 0) {
           ref[i] -= 1;
         } else {
-          float ix = N.i_ext;
+          float ix = sh.kc[kcIext];
           if (iext) ix = ix + as_global(iext)[lo + k];
           float I;
-          if (N.model == 0) I = ge[i] * (N.e_exc - V[i]) + gi[i] * (N.e_inh - V[i]) + ix;
+          if (N.model == 0) I = ge[i] * (sh.kc[kcEe] - V[i]) + gi[i] * (sh.kc[kcEi] - V[i]) + ix;
           else I = ge[i] + gi[i] + ix;
-          float v = V[i] + N.a * ((N.v_rest - V[i]) + N.r * I);
-          if (v > N.v_th) {
+          float v = V[i] + sh.kc[kcA] * ((sh.kc[kcVrest] - V[i]) + sh.kc[kcR] * I);
+          if (v > sh.kc[kcVth]) {
             spk = true;
-            v = N.v_reset;
+            v = sh.kc[kcVreset];
             ref[i] = N.ref_steps;
           }
           V[i] = v;
