@@ -6,9 +6,12 @@
 //   I = alpha I + sum over firing input channels (ascending) of W_in[c, k]
 //             + sum over firing presynaptic neurons j (ascending) of w_jk
 //   V = beta V (1 - z_prev) + (1 - beta) I ;  z = [V > theta]
-// The recurrent sum is pulled through the transposed connectivity (built on
-// the device), so each neuron adds its inputs in a fixed order: the forward
-// pass and its recomputation inside the reverse pass give identical spikes.
+// The recurrent sum is event-driven: the rows of the neurons that fired are
+// pushed into an LDS accumulator, row after row in ascending order, each wave
+// adding the entries that fall in its 64 columns (a row holds a column at
+// most once), so each neuron adds its inputs in a fixed order and the
+// forward pass and its recomputation inside the reverse pass give identical
+// spikes.
 // The forward stores the state before every ckpt_every-th step; the reverse
 // pass walks the segments from the last, recomputes each one, and runs the
 // recurrence backward through it.  Weight gradients are accumulated per
@@ -27,7 +30,7 @@ constexpr int kSnnMaxO = 64;
 
 struct SnnLayout {
   int32_t nck;
-  size_t off_I, off_V, off_z, off_zsum, off_cptr, off_cj, off_cidx, ck_total;
+  size_t off_I, off_V, off_z, off_zsum, ck_total;
   size_t off_segV, off_segz, off_pin, off_prec, off_dlog, ws_total;
 };
 
@@ -45,9 +48,6 @@ static SnnLayout snn_layout(const bp_snn* m) {
   L.off_V = take(L.nck * BN * 4);
   L.off_z = take(L.nck * BN);
   L.off_zsum = take(BN * 4);
-  L.off_cptr = take(((size_t)m->N + 1) * 4);
-  L.off_cj = take((size_t)(m->nnz > 0 ? m->nnz : 1) * 4);
-  L.off_cidx = take((size_t)(m->nnz > 0 ? m->nnz : 1) * 4);
   L.ck_total = o;
   o = 0;
   L.off_segV = take((size_t)m->B * m->ckpt_every * m->N * 4);
@@ -74,99 +74,72 @@ struct SnnDev {
   float* ckV;
   uint8_t* ckz;
   float* zsum;
-  int32_t* cptr;
-  int32_t* cj;
-  int32_t* cidx;
 };
-
-// Transposed connectivity: for post neuron k the (pre j, CSR position)
-// pairs with j ascending.  Rows are sorted, so membership is a binary search.
-// CSC transpose of the recurrent CSR (rows ascending within each column), one
-// workgroup: thread k finds column k's entries by a binary search in every
-// row; the CSR is first copied to LDS when it fits.
-constexpr int kCscLds = 30720;  // ints (120 KB)
-__global__ void __launch_bounds__(1024) snn_csc_k(SnnDev m) {
-  __shared__ int scratch[2 * (1024 / kWave + 1)];
-  __shared__ int base_s;
-  __shared__ int lds[kCscLds];
-  const bool in_lds = (int64_t)m.N + 1 + m.nnz <= kCscLds;
-  if (threadIdx.x == 0) base_s = 0;
-  if (in_lds) {
-    for (int i = threadIdx.x; i <= m.N; i += blockDim.x) lds[i] = m.indptr[i];
-    for (int i = threadIdx.x; i < m.nnz; i += blockDim.x) lds[m.N + 1 + i] = m.indices[i];
-  }
-  __syncthreads();
-  const int* ip = in_lds ? lds : m.indptr;
-  const int* ix = in_lds ? lds + m.N + 1 : m.indices;
-  // entry of row j holding column k, or -1
-  auto find = [&](int j, int k) {
-    int lo = ip[j], hi = ip[j + 1];
-    const int end = hi;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (ix[mid] < k) lo = mid + 1; else hi = mid;
-    }
-    return (lo < end && ix[lo] == k) ? lo : -1;
-  };
-  for (int k0 = 0; k0 < m.N; k0 += blockDim.x) {
-    const int k = k0 + threadIdx.x;
-    int cnt = 0;
-    if (k < m.N)
-      for (int j = 0; j < m.N; ++j) cnt += find(j, k) >= 0;
-    int tot;
-    const int ex = block_excl_scan(cnt, scratch, &tot);
-    int pos = base_s + ex;
-    if (k < m.N) {
-      m.cptr[k] = pos;
-      for (int j = 0; j < m.N; ++j) {
-        const int e = find(j, k);
-        if (e >= 0 && pos < m.nnz) {
-          m.cj[pos] = j;
-          m.cidx[pos] = e;
-          ++pos;
-        }
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) base_s += tot;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) m.cptr[m.N] = base_s;
-}
 
 struct SnnShared {
   uint8_t zprev[kSnnMaxN];
   int ch[kSnnMaxC];
+  int sp[kSnnMaxN];     // neurons that fired at the previous step, ascending
+  float acc[kSnnMaxN];  // input current being accumulated
   int scratch[2 * (1024 / kWave + 1)];
-  int nch;
+  int nch, nsp;
   float red[kSnnMaxO][1024 / kWave];
 };
 
-// Firing input channels of sample b at step t -> sh.ch (ascending), sh.nch.
-__device__ __forceinline__ void stage_inputs(const SnnDev& m, int b, int t, SnnShared& sh) {
-  const uint8_t* xt = m.x + ((size_t)t * m.B + b) * m.C;
-  int base = 0;
-  for (int c0 = 0; c0 < m.C; c0 += blockDim.x) {
-    const int c = c0 + threadIdx.x;
-    const int on = (c < m.C && xt[c]) ? 1 : 0;
-    int tot;
-    const int ex = block_excl_scan(on, sh.scratch, &tot);
-    if (on) sh.ch[base + ex] = c;
-    base += tot;
+// Ascending lists of the firing input channels of sample b at step t (wave
+// 0) and of the neurons with sh.zprev set (the last wave), by wave ballots;
+// ends with a barrier.
+__device__ __forceinline__ void stage_lists(const SnnDev& m, int b, int t, SnnShared& sh) {
+  const int wv = threadIdx.x / kWave, l = lane_id(), last = blockDim.x / kWave - 1;
+  if (wv == 0) {
+    const uint8_t* xt = m.x + ((size_t)t * m.B + b) * m.C;
+    int base = 0;
+    for (int c0 = 0; c0 < m.C; c0 += kWave) {
+      const int c = c0 + l;
+      const bool on = c < m.C && xt[c];
+      const uint64_t msk = __ballot(on);
+      if (on) sh.ch[base + mask_rank(msk)] = c;
+      base += __popcll(msk);
+    }
+    if (l == 0) sh.nch = base;
   }
-  if (threadIdx.x == 0) sh.nch = base;
+  if (wv == last) {
+    int base = 0;
+    for (int k0 = 0; k0 < m.N; k0 += kWave) {
+      const int k = k0 + l;
+      const bool on = k < m.N && sh.zprev[k];
+      const uint64_t msk = __ballot(on);
+      if (on) sh.sp[base + mask_rank(msk)] = k;
+      base += __popcll(msk);
+    }
+    if (l == 0) sh.nsp = base;
+  }
   __syncthreads();
 }
 
-// One forward step for neuron k (valid) given sh.zprev and sh.ch; returns z.
-__device__ __forceinline__ bool fwd_step(const SnnDev& m, int k, bool valid, float& I, float& V, const SnnShared& sh) {
+// One forward step for neuron k given the lists of stage_lists; returns z.
+// Contains two barriers (every thread of the block must call it).
+__device__ __forceinline__ bool fwd_step(const SnnDev& m, int k, bool valid, float& I, float& V, SnnShared& sh) {
+  if (valid) {
+    float acc = m.alpha * I;
+    for (int q = 0; q < sh.nch; ++q) acc = acc + m.W_in[(size_t)sh.ch[q] * m.N + k];
+    sh.acc[k] = acc;
+  }
+  __syncthreads();
+  // recurrent input: rows of the fired neurons, ascending; wave w adds the
+  // entries of columns [64 w, 64 w + 64)
+  const int klo = (int)(threadIdx.x / kWave) * kWave, l = lane_id();
+  for (int r = 0; r < sh.nsp; ++r) {
+    const int j = sh.sp[r];
+    const int e1 = m.indptr[j + 1];
+    for (int e = m.indptr[j] + l; e < e1; e += kWave) {
+      const int kk = m.indices[e];
+      if (kk >= klo && kk < klo + kWave && kk < m.N) sh.acc[kk] = sh.acc[kk] + m.w_rec[e];
+    }
+  }
+  __syncthreads();
   if (!valid) return false;
-  float acc = m.alpha * I;
-  for (int q = 0; q < sh.nch; ++q) acc = acc + m.W_in[(size_t)sh.ch[q] * m.N + k];
-  const int e_end = min(m.cptr[k + 1], m.nnz);
-  for (int e = m.cptr[k]; e < e_end; ++e)
-    if (sh.zprev[m.cj[e]]) acc = acc + m.w_rec[m.cidx[e]];
-  I = acc;
+  I = sh.acc[k];
   const float vp = sh.zprev[k] ? 0.0f : V;
   V = m.beta * vp + m.omb * I;
   return V > m.theta;
@@ -186,9 +159,8 @@ __global__ void __launch_bounds__(1024) snn_forward_k(SnnDev m, float* logits, u
       m.ckV[o] = V;
       m.ckz[o] = sh.zprev[k];
     }
-    stage_inputs(m, b, t, sh);
+    stage_lists(m, b, t, sh);
     const bool z = fwd_step(m, k, valid, I, V, sh);
-    __syncthreads();
     if (valid) {
       sh.zprev[k] = z ? 1 : 0;
       zs += z ? 1.f : 0.f;
@@ -285,9 +257,8 @@ __global__ void __launch_bounds__(1024) snn_backward_k(SnnDev m, const float* dl
     }
     __syncthreads();
     for (int t = t0; t < t1; ++t) {
-      stage_inputs(m, b, t, sh.f);
+      stage_lists(m, b, t, sh.f);
       const bool z = fwd_step(m, k, valid, I, V, sh.f);
-      __syncthreads();
       if (valid) {
         sh.f.zprev[k] = z ? 1 : 0;
         sV[(size_t)(t - t0) * m.N + k] = V;
@@ -319,11 +290,19 @@ __global__ void __launch_bounds__(1024) snn_backward_k(SnnDev m, const float* dl
       if (valid) sh.dI[k] = dI;
       // z_{t-1} of this sample: from the segment scratch or the checkpoint
       if (valid) sh.f.zprev[k] = (t > t0) ? sz[(size_t)(t - 1 - t0) * m.N + k] : z_start;
-      stage_inputs(m, b, t, sh.f);  // ends with a barrier
-      if (valid) {
+      __syncthreads();
+      stage_lists(m, b, t, sh.f);  // ends with a barrier
+      if (valid)
         for (int q = 0; q < sh.f.nch; ++q) pin_b[(size_t)sh.f.ch[q] * m.N + k] += dI;
-        if (t > 0 && sh.f.zprev[k])
-          for (int idx = m.indptr[k]; idx < m.indptr[k + 1]; ++idx) prec_b[idx] += sh.dI[m.indices[idx]];
+      // rows of the neurons that fired at t - 1: wave w takes those of its 64
+      // neurons, lanes over the entries (each entry always by the same lane)
+      if (t > 0) {
+        const int klo = (int)(threadIdx.x / kWave) * kWave, l = lane_id();
+        for (uint64_t fired = __ballot(valid && sh.f.zprev[k]); fired; fired &= fired - 1) {
+          const int j = klo + __builtin_ctzll(fired);
+          const int e1 = m.indptr[j + 1];
+          for (int idx = m.indptr[j] + l; idx < e1; idx += kWave) prec_b[idx] += sh.dI[m.indices[idx]];
+        }
       }
       __syncthreads();
     }
@@ -382,9 +361,6 @@ static SnnDev snn_dev(const bp_snn* m, void* ckpt) {
   d.ckV = (float*)(c + L.off_V);
   d.ckz = (uint8_t*)(c + L.off_z);
   d.zsum = (float*)(c + L.off_zsum);
-  d.cptr = (int32_t*)(c + L.off_cptr);
-  d.cj = (int32_t*)(c + L.off_cj);
-  d.cidx = (int32_t*)(c + L.off_cidx);
   return d;
 }
 
@@ -412,8 +388,6 @@ bp_status bp_snn_forward(const bp_snn* m, void* ckpt, float* logits, float* loss
   BP_REQUIRE(ckpt && logits, "null output");
   hipStream_t st = as_stream(stream);
   const SnnDev d = snn_dev(m, ckpt);
-  snn_csc_k<<<1, 1024, 0, st>>>(d);
-  BP_LAUNCHED("snn_csc_k");
   snn_forward_k<<<m->B, snn_threads(m->N), 0, st>>>(d, logits, raster);
   BP_LAUNCHED("snn_forward_k");
   if (loss) {
