@@ -275,20 +275,20 @@ __global__ void __launch_bounds__(1024) snn_backward_k(SnnDev m, const float* dl
         const bool zt = sz[(size_t)(t - t0) * m.N + k] != 0;
         float dz = gd;
         if (!last) {
-          // own row, entries in order; loads issued 8 entries ahead
+          // own row, entries in order; loads issued 16 entries ahead
           float g = 0.f;
           const int e0 = m.indptr[k], e1 = m.indptr[k + 1];
           int idx = e0;
-          for (; idx + 8 <= e1; idx += 8) {
-            int c[8];
-            float wv[8];
+          for (; idx + 16 <= e1; idx += 16) {
+            int c[16];
+            float wv[16];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < 16; ++u) {
               c[u] = m.indices[idx + u];
               wv[u] = m.w_rec[idx + u];
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) g += wv[u] * sh.dI[c[u]];
+            for (int u = 0; u < 16; ++u) g += wv[u] * sh.dI[c[u]];
           }
           for (; idx < e1; ++idx) g += m.w_rec[idx] * sh.dI[m.indices[idx]];
           dz += g;
