@@ -37,8 +37,9 @@ def log(*a):
 C2_BLOCK = 2048
 
 
-def c2_desc(bp, n=400_000, seed=0):
-    return bp.net_desc(n, n_exc=int(0.8 * n), p=80.0 / n, conn=bp.CONN_JIT, block=C2_BLOCK, seed=seed)
+def c2_desc(bp, n=400_000, seed=0, block=None):
+    return bp.net_desc(n, n_exc=int(0.8 * n), p=80.0 / n, conn=bp.CONN_JIT, block=C2_BLOCK if block is None else block,
+                       seed=seed)
 
 
 def kernel_source_hash(name):
@@ -69,11 +70,11 @@ def counters_traffic(kernel_file, key, per_launch_units):
 LAUNCH_STEPS = 1000  # steps per persistent-kernel launch (0.1 s simulated)
 
 
-def bench_network(bp, torch, steps, warmup):
+def bench_network(bp, torch, steps, warmup, block=None):
     """W warm-up steps, then K timed steps of the same net, both in launches
     of LAUNCH_STEPS (state stays on the device between launches).  Each timed
     launch is bracketed by HIP events on the stream it runs on."""
-    d = c2_desc(bp)
+    d = c2_desc(bp, block=block)
     net = bp.Net(d)
     left = warmup
     while left > 0:
@@ -317,6 +318,12 @@ def main():
                 spikes_per_step=r["spikes"] / steps, mean_rate_hz=r["spikes"] / steps / r["n"] / (r["dt_ms"] * 1e-3),
                 events_per_step=r["events"] / steps, roofline=roofline, cpu_baseline=cpu)
     if not args.no_extra:
+        w = bench_network(bp, torch, 2000, 1000, block=0)
+        line["c2_whole_rows"] = dict(
+            workload="the same 400k net with the connectivity of one block per row (the paper's per-row gap "
+                     "sequence), spikes exchanged as their targets; 1000 warm-up + 2000 timed steps",
+            workgroups=w["n_wg"], us_per_step=w["wall"] * 1e6 / 2000, synaptic_events_per_s=w["events"] / w["wall"],
+            sim_s_per_wall_s=2000 * w["dt_ms"] * 1e-3 / w["wall"])
         line["c0"] = bench_c0(bp, torch)
         line["operator_sweep"] = bench_ops(bp, torch, calls=args.calls)
         line["snn_training"] = bench_snn(bp, torch)

@@ -26,6 +26,14 @@
 // traffic low), then loads the ids that share its 128-byte line; longer lists
 // are completed from the writer's own record.  A one-workgroup
 // net keeps its own list in LDS between steps.
+// JIT nets of one post block (the paper's per-row sequence) invert the
+// exchange: the writer generates the whole row of each of its spikes (a wave
+// per spike draws 256 gaps at once, one Philox call per lane, and places them
+// by a wave prefix sum), sorts the targets by owning workgroup, and pushes
+// them, two 13-bit (local id, inhibitory) entries per slot, into the owners'
+// inbox lines; the header carries the spike count and the target count
+// (31: too many for the line, the reader regenerates them from the record).
+// Readers add the targets to their counters directly.
 // Several nets run in one launch (continuous batching): the grid is the
 // concatenation of their workgroup ranges and each net exchanges records only
 // among its own workgroups.
@@ -47,6 +55,7 @@ constexpr int kIdBatch = 4096;                 // firing rows staged per pass
 constexpr int kMaxWgPerNet = 512;  // one gathering thread per source
 constexpr int kInbox = 16;         // slots per (destination, source) inbox: header + 15 ids
 constexpr int kHeld = kInbox - 1;  // ids a gathering thread holds in registers (one 128-byte inbox line)
+constexpr int kTgtLine = 2 * (kInbox - 1);  // targets an inbox line carries (two per slot)
 constexpr int kMaxBatch = 48;
 constexpr uint32_t kSpinLimit = 1u << 22;
 
@@ -98,6 +107,11 @@ struct NetShared {
   int scan[2 * (kNetWaves + 1)];
   int ocnt[2];  // own spikes of the step, by step parity
   int abort_flag;
+  // several workgroups: targets of the own spikes by destination workgroup
+  uint16_t lst[kMaxWgPerNet][kTgtLine];  // local target id | 0x1000 if the source is inhibitory
+  int dcnt[kMaxWgPerNet];
+  int fb_src[kMaxWgPerNet];  // sources whose targets did not fit their inbox line
+  int fb_cnt, fb_c, acnt;
   // neuron and synapse constants of the update, read from LDS there (as
   // scalars they would crowd the scalar registers of the whole step loop)
   float kc[12];
@@ -107,6 +121,12 @@ enum { kcWe, kcWi, kcDe, kcDi, kcIext, kcEe, kcEi, kcA, kcVrest, kcR, kcVth, kcV
 
 __device__ __forceinline__ uint64_t pack(uint32_t tag, uint32_t v) { return ((uint64_t)tag << 32) | v; }
 __device__ __forceinline__ uint32_t tag_of(uint64_t s) { return (uint32_t)(s >> 32); }
+
+// Inbox header payload: targets in the line (0..30; 31: more, the reader
+// regenerates them from the source's spike record) | spikes of the source << 5.
+__device__ __forceinline__ uint32_t hdr_word(int spikes, int targets) {
+  return ((uint32_t)spikes << 5) | (uint32_t)(targets > kTgtLine ? 31 : targets);
+}
 
 __device__ __forceinline__ uint64_t* record(const NetDev& N, int par, int w) {
   return N.rec + ((size_t)par * N.n_wg + w) * (size_t)(N.range + 1);
@@ -254,7 +274,12 @@ __device__ __forceinline__ int gather_and_process(const NetDev& N, int self, int
 
 // One workgroup's run of L.n_steps steps of net N (CONN: stored CSR = 0,
 // JIT = 1; specialised so each path keeps its own values in registers).
-template <int CONN>
+// PUSH (JIT nets of one post block, i.e. the paper's per-row sequence, with
+// several workgroups): the writer generates the targets of its own spikes
+// and pushes them to the inbox of the workgroup that owns them; otherwise
+// the spike ids themselves are pushed and every reader regenerates (or
+// streams) the part of each firing row inside its own range.
+template <int CONN, bool PUSH>
 __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, int w, uint32_t spin_limit,
                                          NetShared& sh) {
   const int tid = threadIdx.x, wave = tid / kWave;
@@ -283,6 +308,8 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
   if (tid == 0) {
     sh.abort_flag = 0;
     sh.ocnt[0] = sh.ocnt[1] = 0;
+    sh.fb_cnt = 0;
+    sh.acnt = 0;
     sh.kc[kcWe] = N.w_exc;
     sh.kc[kcWi] = N.w_inh;
     sh.kc[kcDe] = N.de;
@@ -302,6 +329,8 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
   const int32_t b_lo = B > 0 ? lo / B : 0;
   const int32_t b_hi = B > 0 ? (hi - 1) / B : 0;
   const int32_t nbt = b_hi - b_lo + 1;
+  const uint64_t seed = N.seed;
+  const uint32_t K = (uint32_t)N.K;
   unsigned long long ev_local = 0;
 
   // accumulate the targets of the staged firing rows sh.ids[0, nact)
@@ -312,6 +341,7 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
         const int ai = it / nbt;
         const uint32_t b = (uint32_t)(b_lo + it % nbt);
         const uint32_t j = (uint32_t)sh.ids[ai];
+        if (j >= (uint32_t)N.n) continue;
         uint32_t* cnt = ((int32_t)j < N.n_exc) ? sh.cE : sh.cI;
         gen_block(N.seed, (uint32_t)N.K, N.n, B, j, b, lo, hi, [&](int32_t pos, uint32_t) {
           atomicAdd(&cnt[pos - lo], 1u);
@@ -323,7 +353,7 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
       for (int base = 0; base < nact; base += kNetThreads) {
         const int i = base + tid;
         int st = 0, len = 0;
-        if (i < nact) {
+        if (i < nact && (uint32_t)sh.ids[i] < (uint32_t)N.n) {
           const int32_t j = sh.ids[i];
           if (N.n_wg == 1) {
             st = as_global(N.indptr)[j];
@@ -381,13 +411,181 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
     __syncthreads();
   };
 
+  // ---- several workgroups: spikes travel as their targets ----
+  // Reader: thread src polls the header of source src's inbox line, then
+  // loads its target slots and adds them to the LDS counters at once; a
+  // source with more targets than the line holds is handled afterwards from
+  // its spike record (propagate over the own range).  Returns the spikes of
+  // the previous step over all sources, -1 if a wait gave up.
+  auto push_gather = [&](int par, uint32_t tag) -> int {
+    if (tid < N.n_wg) {
+      const uint64_t* r = inbox(N, par, w, tid);
+      uint64_t h = 0;
+      uint32_t spins = 0;
+      while (true) {
+        h = ld_coh64(&r[0]);
+        if (tag_of(h) == tag) break;
+        if (++spins > spin_limit) {
+          atomicOr(N.error, 1u);
+          sh.abort_flag = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      if (tag_of(h) == tag) {
+        const uint32_t hd = (uint32_t)h;
+        const int tc = (int)(hd & 31u);
+        atomicAdd(&sh.acnt, (int)((hd >> 5) & 0x1FFFu));
+        if (tc == 31) {
+          sh.fb_src[atomicAdd(&sh.fb_cnt, 1)] = tid;
+        } else if (tc > 0) {
+          const int ns = (tc + 1) >> 1;
+          uint64_t u[kInbox - 1];
+#pragma unroll
+          for (int q = 0; q < kInbox - 1; ++q) u[q] = q < ns ? ld_coh64(&r[1 + q]) : 0;
+#pragma unroll
+          for (int q = 0; q < kInbox - 1; ++q) {
+            if (q < ns) {
+              const uint64_t x = wait_slot(r, 1 + q, tag, u[q], spin_limit, N, sh);
+              if (tag_of(x) == tag) {
+                const uint32_t v = (uint32_t)x;
+#pragma unroll
+                for (int hw = 0; hw < 2; ++hw) {
+                  const uint32_t e = (v >> (16 * hw)) & 0xFFFFu;
+                  const int32_t k = (int32_t)(e & 0xFFFu);
+                  if (2 * q + hw < tc && k < R) {
+                    atomicAdd((e & 0x1000u) ? &sh.cI[k] : &sh.cE[k], 1u);
+                    ++ev_local;
+                  }
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (sh.abort_flag) return -1;
+    const int A = sh.acnt;
+    const int fb = sh.fb_cnt;
+    for (int f = 0; f < fb; ++f) {
+      const int src = sh.fb_src[f];
+      const uint64_t* rr = record(N, par, src);
+      if (tid == 0) {
+        const uint64_t hh = wait_slot(rr, 0, tag, ld_coh64(&rr[0]), spin_limit, N, sh);
+        sh.fb_c = tag_of(hh) == tag ? min((int)(uint32_t)hh, N.range) : 0;
+      }
+      __syncthreads();
+      if (sh.abort_flag) return -1;
+      const int c = sh.fb_c;
+      for (int q0 = 0; q0 < c; q0 += kIdBatch) {
+        const int n = min(kIdBatch, c - q0);
+        for (int q = tid; q < n; q += kNetThreads) {
+          const uint64_t x = wait_slot(rr, 1 + q0 + q, tag, ld_coh64(&rr[1 + q0 + q]), spin_limit, N, sh);
+          sh.ids[q] = tag_of(x) == tag ? (int)(uint32_t)x : -1;
+        }
+        __syncthreads();
+        if (sh.abort_flag) return -1;
+        propagate(n);
+      }
+      __syncthreads();
+    }
+    return A;
+  };
+
+  // Writer: the targets of the own spikes sh.own[0, total), sorted into
+  // per-destination lists (LDS).  JIT rows are generated whole: with one
+  // block (the paper's sequence) one wave per spike draws 256 gaps per pass
+  // (a Philox call per lane) and places them by a wave prefix sum; with post
+  // blocks one lane per (spike, block).  Stored rows are streamed by a wave.
+  const float inv_range = 1.0f / (float)N.range;
+  auto emit = [&](int32_t pos, uint32_t inh) {
+    if ((uint32_t)pos >= (uint32_t)N.n) return;
+    int d = (int)((float)pos * inv_range);
+    if (d * N.range > pos) --d;
+    else if ((d + 1) * N.range <= pos) ++d;
+    const int slot = atomicAdd(&sh.dcnt[d], 1);
+    if (slot < kTgtLine) sh.lst[d][slot] = (uint16_t)((uint32_t)(pos - d * N.range) | inh);
+  };
+  auto push_generate = [&](int total) {
+    const int lane = lane_id();
+    if constexpr (CONN == 1) {
+      if (B == 0) {
+        const uint32_t cap = (uint32_t)N.n;
+        for (int si = wave; si < total; si += kNetWaves) {
+          const uint32_t j = (uint32_t)sh.own[si];
+          const uint32_t inh = (int32_t)j >= N.n_exc ? 0x1000u : 0u;
+          int32_t base = 0;
+          for (uint32_t c = 0;; ++c) {
+            const uint32_t blk = c * kWave + (uint32_t)lane;
+            const Words4 q = philox10(j, 0u, blk, kStreamConn, (uint32_t)seed, (uint32_t)(seed >> 32));
+            // draw 0 is the first position itself, later draws are gaps 1 + U[0, K);
+            // a gap beyond n ends the row, so gaps are clipped to n
+            const uint32_t g0 = min(below(q.x, K) + (blk != 0u ? 1u : 0u), cap);
+            const uint32_t g1 = min(1u + below(q.y, K), cap);
+            const uint32_t g2 = min(1u + below(q.z, K), cap);
+            const uint32_t g3 = min(1u + below(q.w, K), cap);
+            const int s4 = (int)(g0 + g1 + g2 + g3);
+            const int incl = wave_incl_scan(s4);
+            int32_t p = base + incl - s4 + (int32_t)g0;
+            emit(p, inh);
+            p += (int32_t)g1;
+            emit(p, inh);
+            p += (int32_t)g2;
+            emit(p, inh);
+            p += (int32_t)g3;
+            emit(p, inh);
+            base += __builtin_amdgcn_readlane(incl, kWave - 1);
+            if (base >= N.n) break;
+          }
+        }
+      } else {
+        const int items = total * N.nb;
+        for (int it = tid; it < items; it += kNetThreads) {
+          const int si = it / N.nb;
+          const uint32_t b = (uint32_t)(it - si * N.nb);
+          const uint32_t j = (uint32_t)sh.own[si];
+          const uint32_t inh = (int32_t)j >= N.n_exc ? 0x1000u : 0u;
+          gen_block(seed, K, N.n, B, j, b, 0, N.n, [&](int32_t pos, uint32_t) { emit(pos, inh); });
+        }
+      }
+    } else {
+      for (int si = wave; si < total; si += kNetWaves) {
+        const int32_t j = sh.own[si];
+        const uint32_t inh = j >= N.n_exc ? 0x1000u : 0u;
+        const int32_t e0 = as_global(N.indptr)[j], e1 = as_global(N.indptr)[j + 1];
+        for (int32_t e = e0 + lane; e < e1; e += kWave) emit(as_global(N.indices)[e], inh);
+      }
+    }
+  };
+
+  // Writer: the header of every destination's inbox line (the signal its
+  // reader polls), then the target slots (each slot carries the tag too).
+  auto push_publish = [&](int par, uint32_t tag, int total) {
+    for (int d = tid; d < N.n_wg; d += kNetThreads) {
+      uint64_t* ib = inbox(N, par, d, w);
+      const int c = sh.dcnt[d];
+      st_coh64(ib, pack(tag, hdr_word(total, c)));
+      if (c <= kTgtLine)
+        for (int q = 0; 2 * q < c; ++q) {
+          const uint32_t a = sh.lst[d][2 * q];
+          const uint32_t b = 2 * q + 1 < c ? sh.lst[d][2 * q + 1] : 0xFFFFu;
+          st_coh64(ib + 1 + q, pack(tag, a | (b << 16)));
+        }
+    }
+  };
+
   int nloc = -1;  // one workgroup: own spikes of the last step kept in sh.ids, -1 if not
   for (int32_t s = 0; s < L.n_steps; ++s) {
     const int64_t t = L.t0 + s;
     const int pin = (int)((t + 1) & 1);  // parity of step t-1
     const int pout = (int)(t & 1);
     int A;
-    if (nloc >= 0) {
+    if (PUSH && N.n_wg > 1) {
+      A = push_gather(pin, (uint32_t)t);
+      if (A < 0) break;
+      for (int d = tid; d < N.n_wg; d += kNetThreads) sh.dcnt[d] = 0;
+    } else if (nloc >= 0) {
       A = nloc;  // own list of the last step, still in LDS
       if (A > 0) propagate(A);
       else __syncthreads();
@@ -466,8 +664,17 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
     uint64_t* out = record(N, pout, w);
     for (int q = tid; q < total; q += kNetThreads) st_coh64(&out[1 + q], pack(tag, (uint32_t)sh.own[q]));
     if (tid == 0) st_coh64(&out[0], pack(tag, (uint32_t)total));
-    // ... and the header + first ids pushed to every reader's inbox
-    if (N.n_wg > 1) {
+    // ... and the targets, or the header + first ids, pushed to every
+    // reader's inbox
+    if (PUSH && N.n_wg > 1) {
+      if (tid == 0) {  // last read before the barrier above
+        sh.fb_cnt = 0;
+        sh.acnt = 0;
+      }
+      push_generate(total);
+      __syncthreads();
+      push_publish(pout, tag, total);
+    } else if (N.n_wg > 1) {
       const int m = min(total, kInbox - 1) + 1;
       const int items = N.n_wg * m;
       for (int x = tid; x < items; x += kNetThreads) {
@@ -506,7 +713,7 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
     if (tid < N.n_wg) {
       const uint64_t* r = N.n_wg > 1 ? inbox(N, par, 0, tid) : record(N, par, tid);
       const uint64_t hh = wait_slot(r, 0, (uint32_t)t_end, ld_coh64(&r[0]), spin_limit, N, sh);
-      if (tag_of(hh) == (uint32_t)t_end) c = (int)(uint32_t)hh;
+      if (tag_of(hh) == (uint32_t)t_end) c = (PUSH && N.n_wg > 1) ? (int)(((uint32_t)hh >> 5) & 0x1FFFu) : (int)(uint32_t)hh;
     }
     int tot;
     block_excl_scan(c, sh.scan, &tot);
@@ -522,8 +729,12 @@ __global__ void __launch_bounds__(kNetThreads) net_run_k(BatchArgs args) {
   const NetLaunch L = args.e[e];
   const NetDev N = *L.net;
   const int w = (int)blockIdx.x - L.wg_begin;
-  if (N.conn == 1) net_body<1>(L, N, w, args.spin_limit, sh);
-  else net_body<0>(L, N, w, args.spin_limit, sh);
+  if (N.conn == 1) {
+    if (N.block == 0 && N.n_wg > 1) net_body<1, true>(L, N, w, args.spin_limit, sh);
+    else net_body<1, false>(L, N, w, args.spin_limit, sh);
+  } else {
+    net_body<0, false>(L, N, w, args.spin_limit, sh);
+  }
 }
 
 // Initial state: V0 from the hash (FP64 arithmetic, one rounding), zero
@@ -623,7 +834,11 @@ __global__ void __launch_bounds__(kNetThreads) net_set_state_k(const NetDev* __r
   if (threadIdx.x == 0) out[0] = ((uint64_t)step << 32) | (uint32_t)base_s;
   vm_drain();
   __syncthreads();
-  if (N.n_wg > 1) {
+  if (N.n_wg > 1 && N.conn == 1 && N.block == 0) {
+    // target-pushing nets: readers regenerate the targets from the record
+    for (int d = threadIdx.x; d < N.n_wg; d += kNetThreads)
+      inbox(N, par, d, w)[0] = ((uint64_t)step << 32) | hdr_word(base_s, kTgtLine + 1);
+  } else if (N.n_wg > 1) {
     const int m = min(base_s, kInbox - 1) + 1;
     for (int x = threadIdx.x; x < N.n_wg * m; x += kNetThreads) {
       const int d = x / m, q = x - d * m;

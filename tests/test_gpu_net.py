@@ -58,6 +58,8 @@ def first_diff(a, b):
     (O.CONN_CSR, 20000, 80 / 20000, 1024, 16, 400),   # stored rows, block index
     (O.CONN_CSR, 12000, 80 / 12000, 0, 6, 300),       # stored rows, searched segments
     (O.CONN_JIT, 9000, 0.01, 700, 5, 300),            # range not a multiple of the block
+    (O.CONN_JIT, 100000, 80 / 100000, 0, 25, 200),    # whole rows pushed as targets, lines mostly fit
+    (O.CONN_JIT, 20000, 0.02, 0, 8, 200),             # 400 targets per row: lines overflow, regenerated
 ])
 def test_raster_bitwise(bp, conn, n, p, block, max_wgs, T):
     P, net, ip, ix = make(bp, n, p, conn, block, seed=1, max_wgs=max_wgs)
@@ -99,8 +101,9 @@ def test_cuba_and_coba_multi_wg(bp, model):
     assert c_ref.sum() > 0
 
 
-def test_resume_and_checkpoint_roundtrip(bp):
-    P, net, ip, ix = make(bp, 20000, 80 / 20000, O.CONN_JIT, 1024, seed=2, max_wgs=16)
+@pytest.mark.parametrize("block", [1024, 0])
+def test_resume_and_checkpoint_roundtrip(bp, block):
+    P, net, ip, ix = make(bp, 20000, 80 / 20000, O.CONN_JIT, block, seed=2, max_wgs=16)
     st = O.NetState(P)
     rr1, _, _ = O.net_run(P, st, 150)
     r1, _ = net.run(150, raster=True)
@@ -110,7 +113,7 @@ def test_resume_and_checkpoint_roundtrip(bp):
     r2, _ = net.run(100, raster=True)
     np.testing.assert_array_equal(np.concatenate([r1.cpu().numpy(), r2.cpu().numpy()]), np.concatenate([rr1, rr2]))
     # restore the snapshot into a fresh net and replay the 100 steps
-    P2, net2, _, _ = make(bp, 20000, 80 / 20000, O.CONN_JIT, 1024, seed=2, max_wgs=16)
+    P2, net2, _, _ = make(bp, 20000, 80 / 20000, O.CONN_JIT, block, seed=2, max_wgs=16)
     net2.set_state(raw, 150)
     r2b, _ = net2.run(100, raster=True)
     np.testing.assert_array_equal(r2b.cpu().numpy(), rr2)
@@ -134,8 +137,8 @@ def test_step_api_with_external_current(bp):
 def test_run_batch_equals_solo_runs(bp):
     cases = [(4000, 0.02, O.CONN_CSR, 0, 0, 0), (2500, 0.03, O.CONN_JIT, 0, 1, 0),
              (20000, 0.004, O.CONN_JIT, 1024, 0, 16), (12000, 80 / 12000, O.CONN_CSR, 1024, 1, 8),
-             (1000, 0.08, O.CONN_CSR, 0, 0, 0)]
-    steps = [300, 120, 250, 200, 0]
+             (1000, 0.08, O.CONN_CSR, 0, 0, 0), (30000, 80 / 30000, O.CONN_JIT, 0, 0, 12)]
+    steps = [300, 120, 250, 200, 0, 180]
     nets, refs = [], []
     for i, (n, p, conn, blk, model, mw) in enumerate(cases):
         P, net, ip, ix = make(bp, n, p, conn, blk, seed=10 + i, model=model, max_wgs=mw)
@@ -150,11 +153,13 @@ def test_run_batch_equals_solo_runs(bp):
         assert net.info().step == steps[i]
 
 
-def test_large_jit_net_first_steps(bp):
-    # 400k neurons (320k E / 80k I), p = 80/N, blocks of 1024: the first 40
-    # steps bit-identical to the oracle (full-size shape of the scaled net).
+@pytest.mark.parametrize("block", [2048, 0])
+def test_large_jit_net_first_steps(bp, block):
+    # 400k neurons (320k E / 80k I), p = 80/N, post blocks of 2048 (spike ids
+    # exchanged) or whole rows (targets exchanged): the first 40 steps
+    # bit-identical to the oracle (full-size shape of the scaled net).
     n = 400_000
-    P, net, _, _ = make(bp, n, 80 / n, O.CONN_JIT, 1024, seed=0)
+    P, net, _, _ = make(bp, n, 80 / n, O.CONN_JIT, block, seed=0)
     assert net.info().n_wg >= 128
     st = O.NetState(P)
     r_ref, c_ref, ev_ref = O.net_run(P, st, 40)
