@@ -211,7 +211,12 @@ typedef struct {
   int32_t n, n_exc;
   int32_t conn;    /* BP_CONN_CSR or BP_CONN_JIT */
   int32_t max_gap; /* K */
-  int32_t block;   /* generator block width (0 = whole row) */
+  int32_t block;   /* generator block width (0 = whole row, the paper's
+                      sequence).  Results do not depend on it beyond the
+                      connectivity it defines; speed does: with JIT
+                      connectivity and several workgroups, block 0 nets
+                      exchange the targets of each spike, others the spike
+                      ids (each reader regenerates its own blocks). */
   uint64_t seed;
   float w_exc, w_inh;
   float tau_m, tau_e, tau_i, tau_ref;
