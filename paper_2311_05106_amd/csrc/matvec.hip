@@ -104,7 +104,8 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
   const int32_t width = hi - lo;
   const int32_t r_begin = c * a.chunk_rows;
   const int32_t r_end = min(r_begin + a.chunk_rows, a.n_pre);
-  for (int i = threadIdx.x; i < width; i += kMvThreads) acc[i] = (Acc)0;
+  for (int i = threadIdx.x; i < (width + 3) / 4; i += kMvThreads)  // kTileMax is a multiple of 4
+    reinterpret_cast<uint4*>(acc)[i] = make_uint4(0u, 0u, 0u, 0u);
   if (threadIdx.x < 3) sh.cnt[threadIdx.x] = 0;
   __syncthreads();
   const bool vec = ((reinterpret_cast<uintptr_t>(a.events) | (uintptr_t)r_begin) & 15) == 0;
@@ -235,7 +236,17 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
     }
   } else if constexpr (MODE == kCsrHomo || MODE == kJitHomo) {
     uint16_t* part = reinterpret_cast<uint16_t*>(a.out) + (size_t)c * a.n_post;
-    for (int i = threadIdx.x; i < width; i += kMvThreads) part[lo + i] = (uint16_t)acc[i];
+    uint16_t* dst = part + lo;
+    if ((reinterpret_cast<uintptr_t>(dst) & 7) == 0) {  // four counts per 8-byte store
+      const int w4 = width / 4;
+      for (int i = threadIdx.x; i < w4; i += kMvThreads) {
+        const uint4 v = reinterpret_cast<const uint4*>(acc)[i];
+        reinterpret_cast<uint2*>(dst)[i] = make_uint2(v.x | (v.y << 16), v.z | (v.w << 16));
+      }
+      for (int i = 4 * w4 + threadIdx.x; i < width; i += kMvThreads) dst[i] = (uint16_t)acc[i];
+    } else {
+      for (int i = threadIdx.x; i < width; i += kMvThreads) dst[i] = (uint16_t)acc[i];
+    }
   } else {
     float* part = reinterpret_cast<float*>(a.out) + (size_t)c * a.n_post;
     for (int i = threadIdx.x; i < width; i += kMvThreads) part[lo + i] = acc[i];
