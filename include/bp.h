@@ -320,8 +320,8 @@ typedef struct {
 } bp_snn;
 
 /* Checkpoint buffer bytes: ceil(T / ckpt_every) checkpoints of (I, V)
- * float[B, N] and z uint8[B, N] (the state before each segment), the spike
- * counts float[B, N] and the transposed recurrent connectivity.  Written by
+ * float[B, N] and z uint8[B, N] (the state before each segment) and the
+ * spike counts float[B, N].  Written by
  * bp_snn_forward, read by bp_snn_backward. */
 size_t bp_snn_ckpt_bytes(const bp_snn* m);
 /* Scratch of the reverse pass: one segment of (V, z) per sample and

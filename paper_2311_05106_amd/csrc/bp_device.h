@@ -281,6 +281,33 @@ __device__ __forceinline__ uint64_t ld_coh64(const uint64_t* p) {
 __device__ __forceinline__ void st_coh64(uint64_t* p, uint64_t v) {
   __hip_atomic_store(as_global(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// 16-byte device-coherent accesses through a raw buffer resource (one
+// buffer_load/store_dwordx4 with sc1, the same coherence as the 8-byte forms
+// above).  The resource spans `bytes` bytes from `base`; offsets beyond it
+// read zeros and drop the store.  The base is made wave-uniform here (a
+// buffer resource lives in scalar registers).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t coh_rsrc(const void* base, uint32_t bytes) {
+  const uint64_t b = (uint64_t)base;
+  const uint64_t u = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(b >> 32)) << 32) |
+                     (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)b);
+  return __builtin_amdgcn_make_buffer_rsrc((void*)u, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes),
+                                           0x00020000);
+}
+constexpr int kCohSc1 = 16;  // cache-policy operand of the buffer builtins: sc1
+__device__ __forceinline__ void ld_coh128(__amdgpu_buffer_rsrc_t r, uint32_t off, uint64_t* a, uint64_t* b) {
+  const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, kCohSc1);
+  *a = ((uint64_t)v.y << 32) | v.x;
+  *b = ((uint64_t)v.w << 32) | v.z;
+}
+__device__ __forceinline__ void st_coh128(__amdgpu_buffer_rsrc_t r, uint32_t off, uint64_t a, uint64_t b) {
+  u32x4 v;
+  v.x = (uint32_t)a;
+  v.y = (uint32_t)(a >> 32);
+  v.z = (uint32_t)b;
+  v.w = (uint32_t)(b >> 32);
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, kCohSc1);
+}
 // Wait until every vector memory operation this wave issued has completed
 // (s_waitcnt vmcnt(0); stores are counted by vmcnt on gfx9-family targets).
 __device__ __forceinline__ void vm_drain() { __builtin_amdgcn_s_waitcnt(0x0F70); }

@@ -53,9 +53,10 @@ constexpr int kNPT = 4;                        // neurons per thread
 constexpr int kRangeMax = kNetThreads * kNPT;  // neurons per workgroup
 constexpr int kIdBatch = 4096;                 // firing rows staged per pass
 constexpr int kMaxWgPerNet = 512;  // one gathering thread per source
-constexpr int kInbox = 16;         // slots per (destination, source) inbox: header + 15 ids
-constexpr int kHeld = kInbox - 1;  // ids a gathering thread holds in registers (one 128-byte inbox line)
-constexpr int kTgtLine = 2 * (kInbox - 1);  // targets an inbox line carries (two per slot)
+constexpr int kInbox = 16;  // slots per (destination, source) inbox line of the target exchange
+constexpr int kTgtLine = 2 * (kInbox - 1);  // targets such a line carries (two per slot)
+constexpr int kLine = 4;      // words per inbox line of the spike-id exchange (32 bytes)
+constexpr int kLineIds = 15;  // ids such a line carries: 3 in word 0, 4 in each of words 1..3
 constexpr int kMaxBatch = 48;
 constexpr uint32_t kSpinLimit = 1u << 22;
 
@@ -64,6 +65,8 @@ struct NetDev {
   uint64_t seed;
   float w_exc, w_inh, de, di, a, v_rest, v_th, v_reset, e_exc, e_inh, r, i_ext;
   int32_t n_wg, range;
+  int32_t push;  // several workgroups exchange targets (JIT, one post block), else spike ids
+  int32_t ibw;   // words per inbox line: kInbox (targets) or kLine (spike ids)
   float* V;
   float* ge;
   float* gi;
@@ -72,7 +75,7 @@ struct NetDev {
   const int32_t* indices;
   const int32_t* blkptr;  // [n][nb + 1] block index of the stored rows, or null
   uint64_t* rec;          // [2][n_wg][range + 1] spike records by step parity
-  uint64_t* inbox;        // [2][n_wg dst][n_wg src][kInbox] copies pushed to each reader
+  uint64_t* inbox;        // [2][n_wg dst][n_wg src][ibw] lines pushed to each reader
   unsigned long long* events;  // [n_wg] synaptic events delivered
   uint32_t* error;
 };
@@ -133,7 +136,40 @@ __device__ __forceinline__ uint64_t* record(const NetDev& N, int par, int w) {
 }
 
 __device__ __forceinline__ uint64_t* inbox(const NetDev& N, int par, int dst, int src) {
-  return N.inbox + (((size_t)par * N.n_wg + dst) * N.n_wg + src) * kInbox;
+  return N.inbox + (((size_t)par * N.n_wg + dst) * N.n_wg + src) * N.ibw;
+}
+
+// Spike-id inbox line, 4 words of 64 bits, each written and read with its own
+// tag so a reader can take the 16-byte halves as they land:
+//   bits 63..60  tag: (step + 1) mod 16 of the step whose spikes it carries
+//   bits 59..57  ids in this word
+//   word 0: bits 56..44 the writer's spike count, bits 35..0 ids 0..2;
+//   words 1..3: bits 47..0 ids 3..6, 7..10, 11..14
+// Ids are local to the writer's range (12 bits; ranges hold at most 4096
+// neurons) in the order of its record, which holds the ids beyond 15.
+// Four-bit tags suffice: a reader waits for the tag of one step while the
+// line holds that step's value or the one written two steps before.
+__device__ __forceinline__ uint32_t tag4(uint64_t v) { return (uint32_t)(v >> 60); }
+__device__ __forceinline__ int line_n(uint64_t v) { return (int)((v >> 57) & 7u); }
+__device__ __forceinline__ int line_total(uint64_t v) { return (int)((v >> 44) & 0x1FFFu); }
+__device__ __forceinline__ int line_first(int q) { return q == 0 ? 0 : 4 * q - 1; }
+template <class Id>
+__device__ __forceinline__ uint64_t line_word(uint32_t tag, int q, int total, Id&& id) {
+  const int first = line_first(q);
+  const int n = max(0, min(min(total, kLineIds) - first, q == 0 ? 3 : 4));
+  uint64_t v = ((uint64_t)(tag & 15u) << 60) | ((uint64_t)n << 57);
+  if (q == 0) v |= (uint64_t)min(total, 0x1FFF) << 44;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (i < n) v |= (uint64_t)((uint32_t)id(first + i) & 0xFFFu) << (12 * i);
+  return v;
+}
+// byte offset of the half h (words 2h, 2h + 1) of line (par, dst, src)
+__device__ __forceinline__ uint32_t line_off(const NetDev& N, int par, int dst, int src, int h) {
+  return (uint32_t)(((((size_t)par * N.n_wg + dst) * N.n_wg + src) * kLine + 2 * h) * 8);
+}
+__device__ __forceinline__ uint32_t inbox_bytes(const NetDev& N) {
+  return (uint32_t)(2 * (size_t)N.n_wg * N.n_wg * N.ibw * 8);
 }
 
 // Load slot q of a record until it carries `tag` (bounded).
@@ -184,54 +220,59 @@ __device__ __forceinline__ void src_scan2(int a, int b, int nsrc, int* scratch, 
   *tb = sb;
 }
 
-// Gathers the spikes of the previous step (records tagged `tag` of parity
-// `par`) into sh.ids, in passes of kIdBatch; returns the total, calls
-// `process(n)` for every pass of n ids.
+// Gathers the spikes of the previous step (tagged `tag`, parity `par`) into
+// sh.ids, in passes of kIdBatch; returns the total, calls `process(n)` for
+// every pass of n ids.  Several workgroups: two lanes per source poll the
+// two 16-byte halves of the source's line in the own inbox, which carry the
+// spike count and the first 15 ids; longer lists are completed from the
+// source's record.  One workgroup: the ids come from its own record.
 template <class Process>
 __device__ __forceinline__ int gather_and_process(const NetDev& N, int self, int par, uint32_t tag,
                                                   uint32_t spin_limit, NetShared& sh, Process&& process) {
   const int tid = threadIdx.x;
-  const bool src = tid < N.n_wg;
-  // several workgroups: header and first ids from the own inbox; one
-  // workgroup: its own record (a one-workgroup net has no inbox)
-  const uint64_t* r = !src ? nullptr : (N.n_wg > 1 ? inbox(N, par, self, tid) : record(N, par, tid));
-  // poll the header alone (light polling traffic), then load the ids
-  uint64_t h = 0;
-  if (src) {
-    uint32_t spins = 0;
-    while (true) {
-      h = ld_coh64(&r[0]);
-      if (tag_of(h) == tag) break;
-      if (++spins > spin_limit) {
-        atomicOr(N.error, 1u);
-        sh.abort_flag = 1;
-        break;
+  const bool multi = N.n_wg > 1;
+  const int src = multi ? tid >> 1 : 0, half = tid & 1;
+  const bool poller = multi ? tid < 2 * N.n_wg : tid == 0;
+  const bool carrier = poller && (!multi || half == 0);  // the lane that holds the source's count
+  uint64_t wa = 0, wb = 0;
+  int tot = 0;
+  if (multi) {
+    const __amdgpu_buffer_rsrc_t rs = coh_rsrc(N.inbox, inbox_bytes(N));
+    const uint32_t t4 = tag & 15u;
+    if (poller) {
+      const uint32_t off = line_off(N, par, self, src, half);
+      uint32_t spins = 0;
+      while (true) {
+        ld_coh128(rs, off, &wa, &wb);
+        if (tag4(wa) == t4 && tag4(wb) == t4) break;
+        if (++spins > spin_limit) {
+          atomicOr(N.error, 1u);
+          sh.abort_flag = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+        __asm__ volatile("" ::: "memory");  // reload every pass
       }
-      __builtin_amdgcn_s_sleep(2);
+      if (tag4(wa) != t4 || tag4(wb) != t4) wa = wb = 0;
+      if (half == 0) tot = min(line_total(wa), N.range);
     }
+  } else if (poller) {
+    const uint64_t* r = record(N, par, 0);
+    const uint64_t h = wait_slot(r, 0, tag, ld_coh64(&r[0]), spin_limit, N, sh);
+    if (tag_of(h) == tag) tot = min((int)(uint32_t)h, N.range);
   }
-  const int cnt = (src && tag_of(h) == tag) ? min((int)(uint32_t)h, N.range) : 0;
-  // the first kHeld ids (the rest of the header's 128-byte line) into registers
-  int held[kHeld];
-#pragma unroll
-  for (int q = 0; q < kHeld; ++q) held[q] = 0;
-  if (src && cnt > 0) {
-    uint64_t u[kHeld];
-#pragma unroll
-    for (int q = 0; q < kHeld; ++q) u[q] = q < cnt ? ld_coh64(&r[1 + q]) : 0;
-#pragma unroll
-    for (int q = 0; q < kHeld; ++q)
-      if (q < cnt) held[q] = (int)(uint32_t)wait_slot(r, 1 + q, tag, u[q], spin_limit, N, sh);
-  }
-  const int nheld = min(cnt, kHeld);
-  const int extra = cnt - nheld;
+  const int fx = multi ? kLineIds : 0;  // ids a source's line carries
+  const int extra = max(0, tot - fx);
   int cpos, epos, A, E;
-  src_scan2(cnt, extra, N.n_wg, sh.scan, &cpos, &epos, &A, &E);
+  src_scan2(tot, extra, multi ? 2 * N.n_wg : 1, sh.scan, &cpos, &epos, &A, &E);
+  // the second lane of a pair: its prefix includes the first lane's count
+  const int pair_tot = __builtin_amdgcn_update_dpp(0, tot, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  if (multi && half == 1) cpos -= pair_tot;
   if (sh.abort_flag) return -1;
-  if (E > 0) {  // some list is longer than an inbox line: per-source offsets for the record loads
-    if (src) {
-      sh.srcpref[tid] = cpos;
-      sh.expref[tid] = epos;
+  if (E > 0) {  // some list is longer than its line: per-source offsets for the record loads
+    if (carrier) {
+      sh.srcpref[src] = cpos;
+      sh.expref[src] = epos;
     }
     if (tid == 0) {
       sh.srcpref[N.n_wg] = A;
@@ -239,24 +280,27 @@ __device__ __forceinline__ int gather_and_process(const NetDev& N, int self, int
     }
     __syncthreads();
   }
+  const int32_t base = src * N.range;
+  const int qa = half ? 7 : 0, qb = half ? 11 : 3;  // list positions of the lane's two words
+  const int na = line_n(wa), nb = line_n(wb);
   for (int q0 = 0; q0 < A; q0 += kIdBatch) {
     const int n = min(kIdBatch, A - q0);
-    if (src && nheld > 0) {  // waves without sources skip the staging
+    if (na > 0) {  // lanes without ids skip the staging
 #pragma unroll
-      for (int q = 0; q < kHeld; ++q) {
-        const int pos = cpos + q - q0;
-        if (q < nheld && pos >= 0 && pos < n) sh.ids[pos] = held[q];
+      for (int i = 0; i < 4; ++i) {
+        const int pa = cpos + qa + i - q0, pb = cpos + qb + i - q0;
+        if (i < na && pa >= 0 && pa < n) sh.ids[pa] = base + (int32_t)((wa >> (12 * i)) & 0xFFFu);
+        if (i < nb && pb >= 0 && pb < n) sh.ids[pb] = base + (int32_t)((wb >> (12 * i)) & 0xFFFu);
       }
     }
-    // ids beyond the first kHeld of each record (from the record), spread
-    // over the workgroup
+    // ids beyond a source's line (from its record), spread over the workgroup
     for (int e = tid; e < E; e += kNetThreads) {
       int l = 0, hh = N.n_wg;  // largest l with expref[l] <= e
       while (hh - l > 1) {
         const int m = (l + hh) >> 1;
         if (sh.expref[m] <= e) l = m; else hh = m;
       }
-      const int q = kHeld + (e - sh.expref[l]);
+      const int q = fx + (e - sh.expref[l]);
       const int pos = sh.srcpref[l] + q - q0;
       const int cnt_l = sh.srcpref[l + 1] - sh.srcpref[l];
       if (pos >= 0 && pos < n && q < cnt_l && q < N.range) {
@@ -675,13 +719,12 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
       __syncthreads();
       push_publish(pout, tag, total);
     } else if (N.n_wg > 1) {
-      const int m = min(total, kInbox - 1) + 1;
-      const int items = N.n_wg * m;
-      for (int x = tid; x < items; x += kNetThreads) {
-        const int d = x / m, q = x - d * m;
-        const uint64_t v = q == 0 ? pack(tag, (uint32_t)total) : pack(tag, (uint32_t)sh.own[q - 1]);
-        st_coh64(inbox(N, pout, d, w) + q, v);
-      }
+      // the same line to every reader; a thread writes one 16-byte half
+      const __amdgpu_buffer_rsrc_t rs = coh_rsrc(N.inbox, inbox_bytes(N));
+      const int h = tid & 1;
+      auto id = [&](int q) { return sh.own[q] - lo; };
+      const uint64_t wa = line_word(tag, 2 * h, total, id), wb = line_word(tag, 2 * h + 1, total, id);
+      for (int x = tid; x < 2 * N.n_wg; x += kNetThreads) st_coh128(rs, line_off(N, pout, x >> 1, w, h), wa, wb);
     }
   }
 
@@ -711,9 +754,21 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
     const int par = (int)((t_end - 1) & 1);
     int c = 0;
     if (tid < N.n_wg) {
-      const uint64_t* r = N.n_wg > 1 ? inbox(N, par, 0, tid) : record(N, par, tid);
-      const uint64_t hh = wait_slot(r, 0, (uint32_t)t_end, ld_coh64(&r[0]), spin_limit, N, sh);
-      if (tag_of(hh) == (uint32_t)t_end) c = (PUSH && N.n_wg > 1) ? (int)(((uint32_t)hh >> 5) & 0x1FFFu) : (int)(uint32_t)hh;
+      if (N.n_wg > 1 && !PUSH) {  // word 0 of the source's line in workgroup 0's inbox
+        const uint64_t* r = inbox(N, par, 0, tid);
+        const uint32_t t4 = (uint32_t)t_end & 15u;
+        uint64_t hh = ld_coh64(&r[0]);
+        for (uint32_t spins = 0; tag4(hh) != t4 && spins <= spin_limit; ++spins) {
+          __builtin_amdgcn_s_sleep(1);
+          hh = ld_coh64(&r[0]);
+        }
+        if (tag4(hh) == t4) c = line_total(hh);
+        else atomicOr(N.error, 1u);
+      } else {
+        const uint64_t* r = N.n_wg > 1 ? inbox(N, par, 0, tid) : record(N, par, tid);
+        const uint64_t hh = wait_slot(r, 0, (uint32_t)t_end, ld_coh64(&r[0]), spin_limit, N, sh);
+        if (tag_of(hh) == (uint32_t)t_end) c = PUSH ? (int)(((uint32_t)hh >> 5) & 0x1FFFu) : (int)(uint32_t)hh;
+      }
     }
     int tot;
     block_excl_scan(c, sh.scan, &tot);
@@ -730,7 +785,7 @@ __global__ void __launch_bounds__(kNetThreads) net_run_k(BatchArgs args) {
   const NetDev N = *L.net;
   const int w = (int)blockIdx.x - L.wg_begin;
   if (N.conn == 1) {
-    if (N.block == 0 && N.n_wg > 1) net_body<1, true>(L, N, w, args.spin_limit, sh);
+    if (N.push) net_body<1, true>(L, N, w, args.spin_limit, sh);
     else net_body<1, false>(L, N, w, args.spin_limit, sh);
   } else {
     net_body<0, false>(L, N, w, args.spin_limit, sh);
@@ -758,10 +813,11 @@ __global__ void net_init_k(const NetDev* __restrict__ Np, float v0_lo, float v0_
     N.rec[i] = hdr1 ? 0ull : (0xFFFFFFFFull << 32);
   }
   if (N.n_wg > 1) {
-    const int64_t ib = 2 * (int64_t)N.n_wg * N.n_wg * kInbox;
+    const int64_t ib = 2 * (int64_t)N.n_wg * N.n_wg * N.ibw;
     if (i < ib) {
-      const bool hdr1 = (i / ((int64_t)N.n_wg * N.n_wg * kInbox)) == 1 && (i % kInbox) == 0;
-      N.inbox[i] = hdr1 ? 0ull : (0xFFFFFFFFull << 32);
+      const bool par1 = (i / ((int64_t)N.n_wg * N.n_wg * N.ibw)) == 1;
+      if (N.push) N.inbox[i] = (par1 && (i % N.ibw) == 0) ? 0ull : (0xFFFFFFFFull << 32);
+      else N.inbox[i] = par1 ? 0ull : (15ull << 60);  // empty set of step -1; parity 0 as of step -2
     }
   }
   if (i < N.n_wg) N.events[i] = 0ull;
@@ -806,9 +862,9 @@ __global__ void __launch_bounds__(kNetThreads) net_set_state_k(const NetDev* __r
   for (int p = 0; p < 2; ++p) {
     uint64_t* r = N.rec + ((size_t)p * N.n_wg + w) * (size_t)(N.range + 1);
     for (int q = threadIdx.x; q <= N.range; q += kNetThreads) r[q] = 0xFFFFFFFFull << 32;
-    if (N.n_wg > 1)
-      for (int x = threadIdx.x; x < N.n_wg * kInbox; x += kNetThreads)
-        inbox(N, p, x / kInbox, w)[x % kInbox] = 0xFFFFFFFFull << 32;
+    if (N.n_wg > 1)  // the lines read next as of two steps before (spike-id lines), invalid (target lines)
+      for (int x = threadIdx.x; x < N.n_wg * N.ibw; x += kNetThreads)
+        inbox(N, p, x / N.ibw, w)[x % N.ibw] = N.push ? (0xFFFFFFFFull << 32) : ((uint64_t)((step - 1u) & 15u) << 60);
   }
   if (threadIdx.x == 0) base_s = 0;
   vm_drain();  // the invalidations land before the record is rewritten below
@@ -834,16 +890,14 @@ __global__ void __launch_bounds__(kNetThreads) net_set_state_k(const NetDev* __r
   if (threadIdx.x == 0) out[0] = ((uint64_t)step << 32) | (uint32_t)base_s;
   vm_drain();
   __syncthreads();
-  if (N.n_wg > 1 && N.conn == 1 && N.block == 0) {
+  if (N.n_wg > 1 && N.push) {
     // target-pushing nets: readers regenerate the targets from the record
     for (int d = threadIdx.x; d < N.n_wg; d += kNetThreads)
       inbox(N, par, d, w)[0] = ((uint64_t)step << 32) | hdr_word(base_s, kTgtLine + 1);
   } else if (N.n_wg > 1) {
-    const int m = min(base_s, kInbox - 1) + 1;
-    for (int x = threadIdx.x; x < N.n_wg * m; x += kNetThreads) {
-      const int d = x / m, q = x - d * m;
-      inbox(N, par, d, w)[q] = q == 0 ? (((uint64_t)step << 32) | (uint32_t)base_s) : out[q];
-    }
+    auto id = [&](int q) { return (int32_t)(uint32_t)out[1 + q] - lo; };
+    for (int x = threadIdx.x; x < N.n_wg * kLine; x += kNetThreads)
+      inbox(N, par, x / kLine, w)[x % kLine] = line_word(step, x % kLine, base_s, id);
   }
 }
 
@@ -864,7 +918,7 @@ __global__ void net_events_k(const NetDev* __restrict__ Np, unsigned long long* 
 
 // ------------------------------------------------------------------ host side
 struct Layout {
-  int32_t n_wg, range, nb;
+  int32_t n_wg, range, nb, push, ibw;
   int64_t nnz_cap;
   bool blk;
   size_t off_hdr, off_V, off_ge, off_gi, off_ref, off_rec, off_inbox, off_events, off_error,
@@ -922,7 +976,9 @@ static bp_status make_layout(const bp_net_desc* d, Layout* L) {
   L->off_gi = take((size_t)n * 4);
   L->off_ref = take((size_t)n * 4);
   L->off_rec = take((size_t)2 * n_wg * (range + 1) * 8);
-  L->off_inbox = n_wg > 1 ? take((size_t)2 * n_wg * n_wg * kInbox * 8) : 0;
+  L->push = n_wg > 1 && d->conn == BP_CONN_JIT && d->block == 0;
+  L->ibw = L->push ? kInbox : kLine;
+  L->off_inbox = n_wg > 1 ? take((size_t)2 * n_wg * n_wg * L->ibw * 8) : 0;
   L->off_events = take((size_t)n_wg * 8);
   L->off_error = take(4);
   L->off_indptr = d->conn == BP_CONN_CSR ? take((size_t)(n + 1) * 4) : 0;
@@ -1046,6 +1102,8 @@ bp_status bp_create_net(const bp_net_desc* d, void* ws, size_t bytes, bp_stream 
   H.i_ext = d->i_ext;
   H.n_wg = L.n_wg;
   H.range = L.range;
+  H.push = L.push;
+  H.ibw = L.ibw;
   H.V = (float*)(base + L.off_V);
   H.ge = (float*)(base + L.off_ge);
   H.gi = (float*)(base + L.off_gi);
@@ -1071,7 +1129,7 @@ bp_status bp_create_net(const bp_net_desc* d, void* ws, size_t bytes, bp_stream 
   hipError_t e = hipMemcpyAsync(net->dev, &net->host, sizeof(NetDev), hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return fail(set_error(BP_EDEVICE, "header copy failed: %s", hipGetErrorString(e)));
   int64_t slots = 2 * (int64_t)L.n_wg * (L.range + 1);
-  if (L.n_wg > 1 && 2 * (int64_t)L.n_wg * L.n_wg * kInbox > slots) slots = 2 * (int64_t)L.n_wg * L.n_wg * kInbox;
+  if (L.n_wg > 1 && 2 * (int64_t)L.n_wg * L.n_wg * L.ibw > slots) slots = 2 * (int64_t)L.n_wg * L.n_wg * L.ibw;
   const int64_t init_n = d->n > slots ? d->n : slots;
   net_init_k<<<(unsigned)((init_n + 255) / 256), 256, 0, st>>>(net->dev, d->v0_lo, d->v0_hi);
   if ((e = hipGetLastError()) != hipSuccess)
