@@ -204,16 +204,21 @@ __device__ __forceinline__ void src_scan2(int a, int b, int nsrc, int* scratch, 
     }
   }
   __syncthreads();
-  int pa = 0, pb = 0, sa = 0, sb = 0;
-  for (int q = 0; q < nw; ++q) {
-    const int x = scratch[q], y = scratch[kNetWaves + q];
-    if (q < w) {
-      pa += x;
-      pb += y;
-    }
-    sa += x;
-    sb += y;
-  }
+  // the (at most 16) wave sums in the first 16 lanes, scanned there (row
+  // shifts), then read at the lanes of this wave and of the last wave
+  int x = l < nw ? scratch[l] : 0, y = l < nw ? scratch[kNetWaves + l] : 0;
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  y += __builtin_amdgcn_update_dpp(0, y, 0x111, 0xf, 0xf, false);
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  y += __builtin_amdgcn_update_dpp(0, y, 0x112, 0xf, 0xf, false);
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  y += __builtin_amdgcn_update_dpp(0, y, 0x114, 0xf, 0xf, false);
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  y += __builtin_amdgcn_update_dpp(0, y, 0x118, 0xf, 0xf, false);
+  const int wu = __builtin_amdgcn_readfirstlane(w);
+  const int pa = wu > 0 ? __builtin_amdgcn_readlane(x, wu - 1) : 0;
+  const int pb = wu > 0 ? __builtin_amdgcn_readlane(y, wu - 1) : 0;
+  const int sa = __builtin_amdgcn_readlane(x, kNetWaves - 1), sb = __builtin_amdgcn_readlane(y, kNetWaves - 1);
   *ea = pa + ia - a;
   *eb = pb + ib - b;
   *ta = sa;
@@ -625,14 +630,26 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
     const int pin = (int)((t + 1) & 1);  // parity of step t-1
     const int pout = (int)(t & 1);
     int A;
+    if constexpr (!PUSH) {
+      // clear the own counters read by the last update (each thread its own
+      // neurons; the gather below passes a barrier before any accumulation)
+#pragma unroll
+      for (int i = 0; i < kNPT; ++i) {
+        const int k = i * kNetThreads + tid;
+        if (k < R) {
+          sh.cE[k] = 0u;
+          sh.cI[k] = 0u;
+        }
+      }
+    }
     if (PUSH && N.n_wg > 1) {
       A = push_gather(pin, (uint32_t)t);
       if (A < 0) break;
       for (int d = tid; d < N.n_wg; d += kNetThreads) sh.dcnt[d] = 0;
     } else if (nloc >= 0) {
       A = nloc;  // own list of the last step, still in LDS
+      __syncthreads();  // counters cleared
       if (A > 0) propagate(A);
-      else __syncthreads();
     } else {
       A = gather_and_process(N, w, pin, (uint32_t)t, spin_limit, sh, propagate);
       if (A < 0) break;
@@ -649,9 +666,13 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
 #pragma unroll
     for (int i = 0; i < kNPT; ++i) {
       const int k = i * kNetThreads + tid;
-      // read and clear in one LDS exchange
-      ce[i] = k < R ? atomicExch(&sh.cE[k], 0u) : 0u;
-      ci[i] = k < R ? atomicExch(&sh.cI[k], 0u) : 0u;
+      if constexpr (PUSH) {  // read and clear in one LDS exchange (the next gather adds at once)
+        ce[i] = k < R ? atomicExch(&sh.cE[k], 0u) : 0u;
+        ci[i] = k < R ? atomicExch(&sh.cI[k], 0u) : 0u;
+      } else {  // cleared at the start of the next step
+        ce[i] = k < R ? sh.cE[k] : 0u;
+        ci[i] = k < R ? sh.cI[k] : 0u;
+      }
     }
 #pragma unroll
     for (int i = 0; i < kNPT; ++i) {
