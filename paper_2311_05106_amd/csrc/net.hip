@@ -17,23 +17,22 @@
 //      list order carries no meaning) and publish them.
 // Spike records: per workgroup and step parity an array of 64-bit slots,
 // slot 0 = (tag, count), slot 1 + q = (tag, neuron id), tag = step + 1 in the
-// high word.  Each slot is written with one device-coherent 64-bit store, so
-// a reader accepts a slot only when its tag is the step it waits for: the
-// writer never waits for its stores to land.  The writer pushes the header
-// and the first 15 ids into a private inbox of every other workgroup of the
-// net, so each reader polls only its own inbox lines (no line is polled by
-// many workgroups): a reader polls only the header slot (keeping polling
-// traffic low), then loads the ids that share its 128-byte line; longer lists
-// are completed from the writer's own record.  A one-workgroup
-// net keeps its own list in LDS between steps.
-// JIT nets of one post block (the paper's per-row sequence) invert the
-// exchange: the writer generates the whole row of each of its spikes (a wave
-// per spike draws 256 gaps at once, one Philox call per lane, and places them
-// by a wave prefix sum), sorts the targets by owning workgroup, and pushes
-// them, two 13-bit (local id, inhibitory) entries per slot, into the owners'
-// inbox lines; the header carries the spike count and the target count
-// (31: too many for the line, the reader regenerates them from the record).
-// Readers add the targets to their counters directly.
+// high word; they hold the full lists (persistence, long lists).  The
+// exchange itself goes through inboxes: every writer pushes a short line into
+// a private inbox of every reader of the net, each 64-bit word tagged with
+// the step (mod 16), so a reader accepts a word only when it carries the tag
+// it waits for and the writer never waits for its stores to land.  Two lanes
+// of the reader poll the two 16-byte halves of a line's first 32 bytes, so
+// the payload arrives with the poll.  Spike-id lines carry the writer's spike
+// count and its first 15 ids (longer lists are completed from the record).
+// A one-workgroup net keeps its own list in LDS between steps.
+// JIT nets of one post block (the paper's per-row sequence) exchange targets
+// instead: the writer generates the whole row of each of its spikes (a wave
+// per spike draws 256 gaps at once, one Philox call per lane, and places
+// them by a wave prefix sum), sorts the targets by owning workgroup, and
+// pushes up to 30 per line (13-bit entries); a line with more says so and
+// the reader regenerates that writer's targets from its record.  Readers add
+// the targets to their counters directly.
 // Several nets run in one launch (continuous batching): the grid is the
 // concatenation of their workgroup ranges and each net exchanges records only
 // among its own workgroups.
@@ -53,8 +52,8 @@ constexpr int kNPT = 4;                        // neurons per thread
 constexpr int kRangeMax = kNetThreads * kNPT;  // neurons per workgroup
 constexpr int kIdBatch = 4096;                 // firing rows staged per pass
 constexpr int kMaxWgPerNet = 512;  // one gathering thread per source
-constexpr int kInbox = 16;  // slots per (destination, source) inbox line of the target exchange
-constexpr int kTgtLine = 2 * (kInbox - 1);  // targets such a line carries (two per slot)
+constexpr int kTgtLine = 30;  // targets a line of the target exchange carries
+constexpr int kInbox = 8;     // its words: 2 targets in word 0, 4 in each further word
 constexpr int kLine = 4;      // words per inbox line of the spike-id exchange (32 bytes)
 constexpr int kLineIds = 15;  // ids such a line carries: 3 in word 0, 4 in each of words 1..3
 constexpr int kMaxBatch = 48;
@@ -125,11 +124,6 @@ enum { kcWe, kcWi, kcDe, kcDi, kcIext, kcEe, kcEi, kcA, kcVrest, kcR, kcVth, kcV
 __device__ __forceinline__ uint64_t pack(uint32_t tag, uint32_t v) { return ((uint64_t)tag << 32) | v; }
 __device__ __forceinline__ uint32_t tag_of(uint64_t s) { return (uint32_t)(s >> 32); }
 
-// Inbox header payload: targets in the line (0..30; 31: more, the reader
-// regenerates them from the source's spike record) | spikes of the source << 5.
-__device__ __forceinline__ uint32_t hdr_word(int spikes, int targets) {
-  return ((uint32_t)spikes << 5) | (uint32_t)(targets > kTgtLine ? 31 : targets);
-}
 
 __device__ __forceinline__ uint64_t* record(const NetDev& N, int par, int w) {
   return N.rec + ((size_t)par * N.n_wg + w) * (size_t)(N.range + 1);
@@ -153,15 +147,20 @@ __device__ __forceinline__ uint32_t tag4(uint64_t v) { return (uint32_t)(v >> 60
 __device__ __forceinline__ int line_n(uint64_t v) { return (int)((v >> 57) & 7u); }
 __device__ __forceinline__ int line_total(uint64_t v) { return (int)((v >> 44) & 0x1FFFu); }
 __device__ __forceinline__ int line_first(int q) { return q == 0 ? 0 : 4 * q - 1; }
+// Word q of a line; id(i) gives the writer's i-th spike (local id) and is
+// called for every i < 15 whatever the count (it must stay in bounds).
 template <class Id>
 __device__ __forceinline__ uint64_t line_word(uint32_t tag, int q, int total, Id&& id) {
   const int first = line_first(q);
   const int n = max(0, min(min(total, kLineIds) - first, q == 0 ? 3 : 4));
   uint64_t v = ((uint64_t)(tag & 15u) << 60) | ((uint64_t)n << 57);
   if (q == 0) v |= (uint64_t)min(total, 0x1FFF) << 44;
+  uint32_t x[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) x[i] = (uint32_t)id(first + i);  // unconditional: the reads issue together
 #pragma unroll
   for (int i = 0; i < 4; ++i)
-    if (i < n) v |= (uint64_t)((uint32_t)id(first + i) & 0xFFFu) << (12 * i);
+    if (i < n) v |= (uint64_t)(x[i] & 0xFFFu) << (12 * i);
   return v;
 }
 // byte offset of the half h (words 2h, 2h + 1) of line (par, dst, src)
@@ -170,6 +169,36 @@ __device__ __forceinline__ uint32_t line_off(const NetDev& N, int par, int dst, 
 }
 __device__ __forceinline__ uint32_t inbox_bytes(const NetDev& N) {
   return (uint32_t)(2 * (size_t)N.n_wg * N.n_wg * N.ibw * 8);
+}
+
+// Target inbox line (target exchange), 8 words of which the first 4 are
+// always written and polled (two 16-byte halves), the next ones only when
+// the targets need them; every word carries the tag as above:
+//   bits 63..60  tag, bits 59..57  entries in this word
+//   word 0: bits 56..52 targets in the line (0..30; 31: more, the reader
+//           regenerates them from the source's spike record), bits 51..39
+//           the source's spike count, bits 25..0 entries 0..1;
+//   words q >= 1: bits 51..0 entries 4q - 2 .. 4q + 1
+// An entry is 13 bits: local target id | 0x1000 if the source is inhibitory.
+__device__ __forceinline__ int tline_tc(uint64_t v) { return (int)((v >> 52) & 31u); }
+__device__ __forceinline__ int tline_spikes(uint64_t v) { return (int)((v >> 39) & 0x1FFFu); }
+__device__ __forceinline__ int tline_first(int q) { return q == 0 ? 0 : 4 * q - 2; }
+__device__ __forceinline__ int tline_words(int c) { return c <= 2 ? 1 : 1 + (c - 2 + 3) / 4; }
+// Word q for c targets of which the line carries `ce` (c, or 0 if c > 30);
+// ent(i) is called for i < 30 only.
+template <class Ent>
+__device__ __forceinline__ uint64_t tline_word(uint32_t tag, int q, int c, int ce, int spikes, Ent&& ent) {
+  const int first = tline_first(q);
+  const int n = max(0, min(ce - first, q == 0 ? 2 : 4));
+  uint64_t v = ((uint64_t)(tag & 15u) << 60) | ((uint64_t)n << 57);
+  if (q == 0) v |= ((uint64_t)(c > kTgtLine ? 31 : c) << 52) | ((uint64_t)min(spikes, 0x1FFF) << 39);
+  uint32_t x[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) x[i] = ent(min(first + i, kTgtLine - 1));
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (i < n) v |= (uint64_t)(x[i] & 0x1FFFu) << (13 * i);
+  return v;
 }
 
 // Load slot q of a record until it carries `tag` (bounded).
@@ -467,45 +496,64 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
   // its spike record (propagate over the own range).  Returns the spikes of
   // the previous step over all sources, -1 if a wait gave up.
   auto push_gather = [&](int par, uint32_t tag) -> int {
-    if (tid < N.n_wg) {
-      const uint64_t* r = inbox(N, par, w, tid);
-      uint64_t h = 0;
+    const uint32_t t4 = tag & 15u;
+    // add the entries of one target-line word to the counters
+    auto apply = [&](uint64_t v, int nmax) {
+      const int n = min(line_n(v), nmax);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t e = (uint32_t)(v >> (13 * i)) & 0x1FFFu;
+        const int32_t k = (int32_t)(e & 0xFFFu);
+        if (i < n && k < R) {
+          atomicAdd((e & 0x1000u) ? &sh.cI[k] : &sh.cE[k], 1u);
+          ++ev_local;
+        }
+      }
+    };
+    if (tid < 2 * N.n_wg) {
+      // two lanes per source: the two 16-byte halves of the polled words 0..3
+      const int src = tid >> 1, h = tid & 1;
+      const __amdgpu_buffer_rsrc_t rs = coh_rsrc(N.inbox, inbox_bytes(N));
+      const uint32_t off = (uint32_t)(((((size_t)par * N.n_wg + w) * N.n_wg + src) * kInbox + 2 * h) * 8);
+      uint64_t wa = 0, wb = 0;
       uint32_t spins = 0;
       while (true) {
-        h = ld_coh64(&r[0]);
-        if (tag_of(h) == tag) break;
+        ld_coh128(rs, off, &wa, &wb);
+        if (tag4(wa) == t4 && tag4(wb) == t4) break;
         if (++spins > spin_limit) {
           atomicOr(N.error, 1u);
           sh.abort_flag = 1;
           break;
         }
         __builtin_amdgcn_s_sleep(2);
+        __asm__ volatile("" ::: "memory");  // reload every pass
       }
-      if (tag_of(h) == tag) {
-        const uint32_t hd = (uint32_t)h;
-        const int tc = (int)(hd & 31u);
-        atomicAdd(&sh.acnt, (int)((hd >> 5) & 0x1FFFu));
-        if (tc == 31) {
-          sh.fb_src[atomicAdd(&sh.fb_cnt, 1)] = tid;
-        } else if (tc > 0) {
-          const int ns = (tc + 1) >> 1;
-          uint64_t u[kInbox - 1];
+      if (tag4(wa) == t4 && tag4(wb) == t4) {
+        apply(wa, h == 0 ? 2 : 4);
+        apply(wb, 4);
+        if (h == 0) {
+          const int tc = tline_tc(wa);
+          atomicAdd(&sh.acnt, tline_spikes(wa));
+          if (tc == 31) {
+            sh.fb_src[atomicAdd(&sh.fb_cnt, 1)] = src;
+          } else if (tc > 14) {  // words beyond the polled ones
+            const uint64_t* r = inbox(N, par, w, src);
+            const int nw = tline_words(tc);
+            uint64_t u[kInbox - 4];
 #pragma unroll
-          for (int q = 0; q < kInbox - 1; ++q) u[q] = q < ns ? ld_coh64(&r[1 + q]) : 0;
+            for (int q = 0; q < kInbox - 4; ++q) u[q] = 4 + q < nw ? ld_coh64(&r[4 + q]) : 0;
 #pragma unroll
-          for (int q = 0; q < kInbox - 1; ++q) {
-            if (q < ns) {
-              const uint64_t x = wait_slot(r, 1 + q, tag, u[q], spin_limit, N, sh);
-              if (tag_of(x) == tag) {
-                const uint32_t v = (uint32_t)x;
-#pragma unroll
-                for (int hw = 0; hw < 2; ++hw) {
-                  const uint32_t e = (v >> (16 * hw)) & 0xFFFFu;
-                  const int32_t k = (int32_t)(e & 0xFFFu);
-                  if (2 * q + hw < tc && k < R) {
-                    atomicAdd((e & 0x1000u) ? &sh.cI[k] : &sh.cE[k], 1u);
-                    ++ev_local;
-                  }
+            for (int q = 0; q < kInbox - 4; ++q) {
+              if (4 + q < nw) {
+                uint64_t x = u[q];
+                for (uint32_t sp = 0; tag4(x) != t4 && sp <= spin_limit; ++sp) {
+                  __builtin_amdgcn_s_sleep(1);
+                  x = ld_coh64(&r[4 + q]);
+                }
+                if (tag4(x) == t4) apply(x, 4);
+                else {
+                  atomicOr(N.error, 1u);
+                  sh.abort_flag = 1;
                 }
               }
             }
@@ -611,16 +659,20 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
   // Writer: the header of every destination's inbox line (the signal its
   // reader polls), then the target slots (each slot carries the tag too).
   auto push_publish = [&](int par, uint32_t tag, int total) {
-    for (int d = tid; d < N.n_wg; d += kNetThreads) {
-      uint64_t* ib = inbox(N, par, d, w);
+    const __amdgpu_buffer_rsrc_t rs = coh_rsrc(N.inbox, inbox_bytes(N));
+    for (int x = tid; x < 2 * N.n_wg; x += kNetThreads) {
+      const int d = x >> 1, h = x & 1;
       const int c = sh.dcnt[d];
-      st_coh64(ib, pack(tag, hdr_word(total, c)));
-      if (c <= kTgtLine)
-        for (int q = 0; 2 * q < c; ++q) {
-          const uint32_t a = sh.lst[d][2 * q];
-          const uint32_t b = 2 * q + 1 < c ? sh.lst[d][2 * q + 1] : 0xFFFFu;
-          st_coh64(ib + 1 + q, pack(tag, a | (b << 16)));
-        }
+      const int ce = c > kTgtLine ? 0 : c;
+      auto ent = [&](int i) { return (uint32_t)sh.lst[d][i]; };
+      const uint64_t wa = tline_word(tag, 2 * h, c, ce, total, ent);
+      const uint64_t wb = tline_word(tag, 2 * h + 1, c, ce, total, ent);
+      st_coh128(rs, (uint32_t)(((((size_t)par * N.n_wg + d) * N.n_wg + w) * kInbox + 2 * h) * 8), wa, wb);
+      if (h == 0) {
+        uint64_t* ib = inbox(N, par, d, w);
+        const int nw = tline_words(ce);
+        for (int q = 4; q < nw; ++q) st_coh64(ib + q, tline_word(tag, q, c, ce, total, ent));
+      }
     }
   };
 
@@ -775,7 +827,7 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
     const int par = (int)((t_end - 1) & 1);
     int c = 0;
     if (tid < N.n_wg) {
-      if (N.n_wg > 1 && !PUSH) {  // word 0 of the source's line in workgroup 0's inbox
+      if (N.n_wg > 1) {  // word 0 of the source's line in workgroup 0's inbox
         const uint64_t* r = inbox(N, par, 0, tid);
         const uint32_t t4 = (uint32_t)t_end & 15u;
         uint64_t hh = ld_coh64(&r[0]);
@@ -783,12 +835,12 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
           __builtin_amdgcn_s_sleep(1);
           hh = ld_coh64(&r[0]);
         }
-        if (tag4(hh) == t4) c = line_total(hh);
+        if (tag4(hh) == t4) c = PUSH ? tline_spikes(hh) : line_total(hh);
         else atomicOr(N.error, 1u);
       } else {
-        const uint64_t* r = N.n_wg > 1 ? inbox(N, par, 0, tid) : record(N, par, tid);
+        const uint64_t* r = record(N, par, tid);
         const uint64_t hh = wait_slot(r, 0, (uint32_t)t_end, ld_coh64(&r[0]), spin_limit, N, sh);
-        if (tag_of(hh) == (uint32_t)t_end) c = PUSH ? (int)(((uint32_t)hh >> 5) & 0x1FFFu) : (int)(uint32_t)hh;
+        if (tag_of(hh) == (uint32_t)t_end) c = (int)(uint32_t)hh;
       }
     }
     int tot;
@@ -837,8 +889,7 @@ __global__ void net_init_k(const NetDev* __restrict__ Np, float v0_lo, float v0_
     const int64_t ib = 2 * (int64_t)N.n_wg * N.n_wg * N.ibw;
     if (i < ib) {
       const bool par1 = (i / ((int64_t)N.n_wg * N.n_wg * N.ibw)) == 1;
-      if (N.push) N.inbox[i] = (par1 && (i % N.ibw) == 0) ? 0ull : (0xFFFFFFFFull << 32);
-      else N.inbox[i] = par1 ? 0ull : (15ull << 60);  // empty set of step -1; parity 0 as of step -2
+      N.inbox[i] = par1 ? 0ull : (15ull << 60);  // empty set of step -1; parity 0 as of step -2
     }
   }
   if (i < N.n_wg) N.events[i] = 0ull;
@@ -883,9 +934,9 @@ __global__ void __launch_bounds__(kNetThreads) net_set_state_k(const NetDev* __r
   for (int p = 0; p < 2; ++p) {
     uint64_t* r = N.rec + ((size_t)p * N.n_wg + w) * (size_t)(N.range + 1);
     for (int q = threadIdx.x; q <= N.range; q += kNetThreads) r[q] = 0xFFFFFFFFull << 32;
-    if (N.n_wg > 1)  // the lines read next as of two steps before (spike-id lines), invalid (target lines)
+    if (N.n_wg > 1)  // every line as of two steps before
       for (int x = threadIdx.x; x < N.n_wg * N.ibw; x += kNetThreads)
-        inbox(N, p, x / N.ibw, w)[x % N.ibw] = N.push ? (0xFFFFFFFFull << 32) : ((uint64_t)((step - 1u) & 15u) << 60);
+        inbox(N, p, x / N.ibw, w)[x % N.ibw] = (uint64_t)((step - 1u) & 15u) << 60;
   }
   if (threadIdx.x == 0) base_s = 0;
   vm_drain();  // the invalidations land before the record is rewritten below
@@ -912,9 +963,11 @@ __global__ void __launch_bounds__(kNetThreads) net_set_state_k(const NetDev* __r
   vm_drain();
   __syncthreads();
   if (N.n_wg > 1 && N.push) {
-    // target-pushing nets: readers regenerate the targets from the record
-    for (int d = threadIdx.x; d < N.n_wg; d += kNetThreads)
-      inbox(N, par, d, w)[0] = ((uint64_t)step << 32) | hdr_word(base_s, kTgtLine + 1);
+    // target-pushing nets: "more than the line holds", so readers regenerate
+    // the targets from the record
+    auto none = [](int) { return 0u; };
+    for (int x = threadIdx.x; x < N.n_wg * 4; x += kNetThreads)
+      inbox(N, par, x / 4, w)[x % 4] = tline_word(step, x % 4, kTgtLine + 1, 0, base_s, none);
   } else if (N.n_wg > 1) {
     auto id = [&](int q) { return (int32_t)(uint32_t)out[1 + q] - lo; };
     for (int x = threadIdx.x; x < N.n_wg * kLine; x += kNetThreads)
