@@ -74,7 +74,7 @@ struct NetDev {
   const int32_t* indices;
   const int32_t* blkptr;  // [n][nb + 1] block index of the stored rows, or null
   uint64_t* rec;          // [2][n_wg][range + 1] spike records by step parity
-  uint64_t* inbox;        // [2][n_wg dst][n_wg src][ibw] lines pushed to each reader
+  uint64_t* inbox;        // [ibw / 4 planes][2][n_wg dst][n_wg src][4] words of the lines pushed to each reader
   unsigned long long* events;  // [n_wg] synaptic events delivered
   uint32_t* error;
 };
@@ -129,8 +129,12 @@ __device__ __forceinline__ uint64_t* record(const NetDev& N, int par, int w) {
   return N.rec + ((size_t)par * N.n_wg + w) * (size_t)(N.range + 1);
 }
 
-__device__ __forceinline__ uint64_t* inbox(const NetDev& N, int par, int dst, int src) {
-  return N.inbox + (((size_t)par * N.n_wg + dst) * N.n_wg + src) * N.ibw;
+// Word q of inbox line (par, dst, src).  Lines are stored in planes of 4
+// words (words 0..3 of every line, then words 4..7), so the polled first 32
+// bytes of the lines a reader scans are contiguous.
+__device__ __forceinline__ uint64_t* iword(const NetDev& N, int par, int dst, int src, int q) {
+  const size_t plane = (size_t)2 * N.n_wg * N.n_wg * 4;
+  return N.inbox + (size_t)(q >> 2) * plane + ((((size_t)par * N.n_wg + dst) * N.n_wg + src) * 4 + (q & 3));
 }
 
 // Spike-id inbox line, 4 words of 64 bits, each written and read with its own
@@ -163,7 +167,8 @@ __device__ __forceinline__ uint64_t line_word(uint32_t tag, int q, int total, Id
     if (i < n) v |= (uint64_t)(x[i] & 0xFFFu) << (12 * i);
   return v;
 }
-// byte offset of the half h (words 2h, 2h + 1) of line (par, dst, src)
+// byte offset of the half h (words 2h, 2h + 1) of line (par, dst, src) in
+// the first plane
 __device__ __forceinline__ uint32_t line_off(const NetDev& N, int par, int dst, int src, int h) {
   return (uint32_t)(((((size_t)par * N.n_wg + dst) * N.n_wg + src) * kLine + 2 * h) * 8);
 }
@@ -514,7 +519,7 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
       // two lanes per source: the two 16-byte halves of the polled words 0..3
       const int src = tid >> 1, h = tid & 1;
       const __amdgpu_buffer_rsrc_t rs = coh_rsrc(N.inbox, inbox_bytes(N));
-      const uint32_t off = (uint32_t)(((((size_t)par * N.n_wg + w) * N.n_wg + src) * kInbox + 2 * h) * 8);
+      const uint32_t off = line_off(N, par, w, src, h);
       uint64_t wa = 0, wb = 0;
       uint32_t spins = 0;
       while (true) {
@@ -537,18 +542,18 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
           if (tc == 31) {
             sh.fb_src[atomicAdd(&sh.fb_cnt, 1)] = src;
           } else if (tc > 14) {  // words beyond the polled ones
-            const uint64_t* r = inbox(N, par, w, src);
+            const uint64_t* r = iword(N, par, w, src, 4);  // words 4.. (second plane)
             const int nw = tline_words(tc);
             uint64_t u[kInbox - 4];
 #pragma unroll
-            for (int q = 0; q < kInbox - 4; ++q) u[q] = 4 + q < nw ? ld_coh64(&r[4 + q]) : 0;
+            for (int q = 0; q < kInbox - 4; ++q) u[q] = 4 + q < nw ? ld_coh64(&r[q]) : 0;
 #pragma unroll
             for (int q = 0; q < kInbox - 4; ++q) {
               if (4 + q < nw) {
                 uint64_t x = u[q];
                 for (uint32_t sp = 0; tag4(x) != t4 && sp <= spin_limit; ++sp) {
                   __builtin_amdgcn_s_sleep(1);
-                  x = ld_coh64(&r[4 + q]);
+                  x = ld_coh64(&r[q]);
                 }
                 if (tag4(x) == t4) apply(x, 4);
                 else {
@@ -667,11 +672,11 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
       auto ent = [&](int i) { return (uint32_t)sh.lst[d][i]; };
       const uint64_t wa = tline_word(tag, 2 * h, c, ce, total, ent);
       const uint64_t wb = tline_word(tag, 2 * h + 1, c, ce, total, ent);
-      st_coh128(rs, (uint32_t)(((((size_t)par * N.n_wg + d) * N.n_wg + w) * kInbox + 2 * h) * 8), wa, wb);
+      st_coh128(rs, line_off(N, par, d, w, h), wa, wb);
       if (h == 0) {
-        uint64_t* ib = inbox(N, par, d, w);
+        uint64_t* ib = iword(N, par, d, w, 4);
         const int nw = tline_words(ce);
-        for (int q = 4; q < nw; ++q) st_coh64(ib + q, tline_word(tag, q, c, ce, total, ent));
+        for (int q = 4; q < nw; ++q) st_coh64(ib + (q - 4), tline_word(tag, q, c, ce, total, ent));
       }
     }
   };
@@ -828,7 +833,7 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
     int c = 0;
     if (tid < N.n_wg) {
       if (N.n_wg > 1) {  // word 0 of the source's line in workgroup 0's inbox
-        const uint64_t* r = inbox(N, par, 0, tid);
+        const uint64_t* r = iword(N, par, 0, tid, 0);
         const uint32_t t4 = (uint32_t)t_end & 15u;
         uint64_t hh = ld_coh64(&r[0]);
         for (uint32_t spins = 0; tag4(hh) != t4 && spins <= spin_limit; ++spins) {
@@ -887,8 +892,8 @@ __global__ void net_init_k(const NetDev* __restrict__ Np, float v0_lo, float v0_
   }
   if (N.n_wg > 1) {
     const int64_t ib = 2 * (int64_t)N.n_wg * N.n_wg * N.ibw;
-    if (i < ib) {
-      const bool par1 = (i / ((int64_t)N.n_wg * N.n_wg * N.ibw)) == 1;
+    if (i < ib) {  // planes of [2 parities][dst][src][4 words]
+      const bool par1 = ((i / ((int64_t)N.n_wg * N.n_wg * 4)) & 1) == 1;
       N.inbox[i] = par1 ? 0ull : (15ull << 60);  // empty set of step -1; parity 0 as of step -2
     }
   }
@@ -936,7 +941,7 @@ __global__ void __launch_bounds__(kNetThreads) net_set_state_k(const NetDev* __r
     for (int q = threadIdx.x; q <= N.range; q += kNetThreads) r[q] = 0xFFFFFFFFull << 32;
     if (N.n_wg > 1)  // every line as of two steps before
       for (int x = threadIdx.x; x < N.n_wg * N.ibw; x += kNetThreads)
-        inbox(N, p, x / N.ibw, w)[x % N.ibw] = (uint64_t)((step - 1u) & 15u) << 60;
+        *iword(N, p, x / N.ibw, w, x % N.ibw) = (uint64_t)((step - 1u) & 15u) << 60;
   }
   if (threadIdx.x == 0) base_s = 0;
   vm_drain();  // the invalidations land before the record is rewritten below
@@ -967,11 +972,11 @@ __global__ void __launch_bounds__(kNetThreads) net_set_state_k(const NetDev* __r
     // the targets from the record
     auto none = [](int) { return 0u; };
     for (int x = threadIdx.x; x < N.n_wg * 4; x += kNetThreads)
-      inbox(N, par, x / 4, w)[x % 4] = tline_word(step, x % 4, kTgtLine + 1, 0, base_s, none);
+      *iword(N, par, x / 4, w, x % 4) = tline_word(step, x % 4, kTgtLine + 1, 0, base_s, none);
   } else if (N.n_wg > 1) {
     auto id = [&](int q) { return (int32_t)(uint32_t)out[1 + q] - lo; };
     for (int x = threadIdx.x; x < N.n_wg * kLine; x += kNetThreads)
-      inbox(N, par, x / kLine, w)[x % kLine] = line_word(step, x % kLine, base_s, id);
+      *iword(N, par, x / kLine, w, x % kLine) = line_word(step, x % kLine, base_s, id);
   }
 }
 
