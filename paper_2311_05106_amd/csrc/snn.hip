@@ -80,6 +80,8 @@ struct SnnShared {
   uint8_t zprev[kSnnMaxN];
   int ch[kSnnMaxC];
   int sp[kSnnMaxN];     // neurons that fired at the previous step, ascending
+  int rlo[kSnnMaxN];    // their rows in the recurrent CSR: [rlo, rhi)
+  int rhi[kSnnMaxN];
   float acc[kSnnMaxN];  // input current being accumulated
   int scratch[2 * (1024 / kWave + 1)];
   int nch, nsp;
@@ -94,12 +96,20 @@ __device__ __forceinline__ void stage_lists(const SnnDev& m, int b, int t, SnnSh
   if (wv == 0) {
     const uint8_t* xt = m.x + ((size_t)t * m.B + b) * m.C;
     int base = 0;
-    for (int c0 = 0; c0 < m.C; c0 += kWave) {
-      const int c = c0 + l;
-      const bool on = c < m.C && xt[c];
-      const uint64_t msk = __ballot(on);
-      if (on) sh.ch[base + mask_rank(msk)] = c;
-      base += __popcll(msk);
+    for (int c0 = 0; c0 < m.C; c0 += 4 * kWave) {
+      // four 64-channel groups loaded together, then compacted in order
+      bool on[4];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int c = c0 + g * kWave + l;
+        on[g] = c < m.C && xt[c];
+      }
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const uint64_t msk = __ballot(on[g]);
+        if (on[g]) sh.ch[base + mask_rank(msk)] = c0 + g * kWave + l;
+        base += __popcll(msk);
+      }
     }
     if (l == 0) sh.nch = base;
   }
@@ -113,6 +123,12 @@ __device__ __forceinline__ void stage_lists(const SnnDev& m, int b, int t, SnnSh
       base += __popcll(msk);
     }
     if (l == 0) sh.nsp = base;
+    // row bounds of the listed neurons, all loads in flight together
+    for (int r = l; r < base; r += kWave) {
+      const int j = sh.sp[r];
+      sh.rlo[r] = m.indptr[j];
+      sh.rhi[r] = m.indptr[j + 1];
+    }
   }
   __syncthreads();
 }
@@ -121,20 +137,50 @@ __device__ __forceinline__ void stage_lists(const SnnDev& m, int b, int t, SnnSh
 // Contains two barriers (every thread of the block must call it).
 __device__ __forceinline__ bool fwd_step(const SnnDev& m, int k, bool valid, float& I, float& V, SnnShared& sh) {
   if (valid) {
+    // input channels in list order, eight loads in flight at a time
     float acc = m.alpha * I;
-    for (int q = 0; q < sh.nch; ++q) acc = acc + m.W_in[(size_t)sh.ch[q] * m.N + k];
+    const int nch = sh.nch;
+    for (int q0 = 0; q0 < nch; q0 += 8) {
+      float wv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) wv[u] = q0 + u < nch ? m.W_in[(size_t)sh.ch[q0 + u] * m.N + k] : 0.f;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (q0 + u < nch) acc = acc + wv[u];
+    }
     sh.acc[k] = acc;
   }
   __syncthreads();
   // recurrent input: rows of the fired neurons, ascending; wave w adds the
-  // entries of columns [64 w, 64 w + 64)
+  // entries of columns [64 w, 64 w + 64).  The first 64 entries of four rows
+  // are loaded together, then added row by row (the same order per column).
   const int klo = (int)(threadIdx.x / kWave) * kWave, l = lane_id();
-  for (int r = 0; r < sh.nsp; ++r) {
-    const int j = sh.sp[r];
-    const int e1 = m.indptr[j + 1];
-    for (int e = m.indptr[j] + l; e < e1; e += kWave) {
-      const int kk = m.indices[e];
-      if (kk >= klo && kk < klo + kWave && kk < m.N) sh.acc[kk] = sh.acc[kk] + m.w_rec[e];
+  const int nsp = sh.nsp;
+  for (int r0 = 0; r0 < nsp; r0 += 4) {
+    int kk[4];
+    float wr[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      kk[u] = -1;
+      wr[u] = 0.f;
+      if (r0 + u < nsp) {
+        const int e = sh.rlo[r0 + u] + l;
+        if (e < sh.rhi[r0 + u]) {
+          kk[u] = m.indices[e];
+          wr[u] = m.w_rec[e];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (r0 + u < nsp) {
+        if (kk[u] >= klo && kk[u] < klo + kWave && kk[u] < m.N) sh.acc[kk[u]] = sh.acc[kk[u]] + wr[u];
+        const int e1 = sh.rhi[r0 + u];
+        for (int e = sh.rlo[r0 + u] + kWave + l; e < e1; e += kWave) {  // rows longer than 64
+          const int c = m.indices[e];
+          if (c >= klo && c < klo + kWave && c < m.N) sh.acc[c] = sh.acc[c] + m.w_rec[e];
+        }
+      }
     }
   }
   __syncthreads();
@@ -275,20 +321,31 @@ __global__ void __launch_bounds__(1024) snn_backward_k(SnnDev m, const float* dl
         const bool zt = sz[(size_t)(t - t0) * m.N + k] != 0;
         float dz = gd;
         if (!last) {
-          // own row, entries in order; loads issued 16 entries ahead
+          // own row, entries in order; loads issued 32 entries ahead
           float g = 0.f;
           const int e0 = m.indptr[k], e1 = m.indptr[k + 1];
           int idx = e0;
-          for (; idx + 16 <= e1; idx += 16) {
-            int c[16];
-            float wv[16];
+          for (; idx + 32 <= e1; idx += 32) {
+            int c[32];
+            float wv[32];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
+            for (int u = 0; u < 32; ++u) {
               c[u] = m.indices[idx + u];
               wv[u] = m.w_rec[idx + u];
             }
 #pragma unroll
-            for (int u = 0; u < 16; ++u) g += wv[u] * sh.dI[c[u]];
+            for (int u = 0; u < 32; ++u) g += wv[u] * sh.dI[c[u]];
+          }
+          for (; idx + 8 <= e1; idx += 8) {
+            int c[8];
+            float wv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              c[u] = m.indices[idx + u];
+              wv[u] = m.w_rec[idx + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) g += wv[u] * sh.dI[c[u]];
           }
           for (; idx < e1; ++idx) g += m.w_rec[idx] * sh.dI[m.indices[idx]];
           dz += g;
@@ -306,8 +363,18 @@ __global__ void __launch_bounds__(1024) snn_backward_k(SnnDev m, const float* dl
       if (valid) sh.f.zprev[k] = (t > t0) ? sz[(size_t)(t - 1 - t0) * m.N + k] : z_start;
       __syncthreads();
       stage_lists(m, b, t, sh.f);  // ends with a barrier
-      if (valid)
-        for (int q = 0; q < sh.f.nch; ++q) pin_b[(size_t)sh.f.ch[q] * m.N + k] += dI;
+      if (valid) {
+        // the listed channels are distinct: eight read-modify-writes in flight
+        const int nch = sh.f.nch;
+        for (int q0 = 0; q0 < nch; q0 += 8) {
+          float pv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) pv[u] = q0 + u < nch ? pin_b[(size_t)sh.f.ch[q0 + u] * m.N + k] : 0.f;
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (q0 + u < nch) pin_b[(size_t)sh.f.ch[q0 + u] * m.N + k] = pv[u] + dI;
+        }
+      }
       // rows of the neurons that fired at t - 1: wave w takes those of its 64
       // neurons, lanes over the entries (each entry always by the same lane)
       if (t > 0) {
