@@ -324,9 +324,10 @@ typedef struct {
  * spike counts float[B, N].  Written by
  * bp_snn_forward, read by bp_snn_backward. */
 size_t bp_snn_ckpt_bytes(const bp_snn* m);
-/* Scratch of the reverse pass: one segment of (V, z) per sample and
+/* Scratch of the reverse pass: one segment of (V, z) per sample,
  * per-sample gradient partials (reduced in sample order, so the result does
- * not depend on scheduling). */
+ * not depend on scheduling) and a transposed copy of the recurrent rows
+ * (2 x N x N words, rebuilt by every bp_snn_backward call). */
 size_t bp_snn_ws_bytes(const bp_snn* m);
 
 /* Forward pass: logits (device float[B, O]), loss (device float[1]),

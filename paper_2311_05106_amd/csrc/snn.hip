@@ -31,7 +31,7 @@ constexpr int kSnnMaxO = 64;
 struct SnnLayout {
   int32_t nck;
   size_t off_I, off_V, off_z, off_zsum, ck_total;
-  size_t off_segV, off_segz, off_pin, off_prec, off_dlog, ws_total;
+  size_t off_segV, off_segz, off_pin, off_prec, off_dlog, off_elli, off_ellw, ws_total;
 };
 
 static SnnLayout snn_layout(const bp_snn* m) {
@@ -55,6 +55,10 @@ static SnnLayout snn_layout(const bp_snn* m) {
   L.off_pin = take((size_t)m->B * m->C * m->N * 4);
   L.off_prec = take((size_t)m->B * (m->nnz > 0 ? m->nnz : 1) * 4);
   L.off_dlog = take((size_t)m->B * m->O * 4);
+  // the recurrent rows transposed: entry i of row k at [i][k] (rows of at
+  // most N entries)
+  L.off_elli = take((size_t)m->N * m->N * 4);
+  L.off_ellw = take((size_t)m->N * m->N * 4);
   L.ws_total = o;
   return L;
 }
@@ -263,6 +267,19 @@ __device__ __forceinline__ float surrogate(const SnnDev& m, float v) {
   return m.slope * s * (1.f - s);
 }
 
+// Copies the recurrent rows into the transposed layout read by the backward
+// gather (entry i of row k at [i * N + k]: lanes of a wave, one row each,
+// read consecutive words).  One thread per row.
+__global__ void snn_ell_k(SnnDev m, int32_t* elli, float* ellw) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m.N) return;
+  const int e0 = m.indptr[k], len = m.indptr[k + 1] - e0;
+  for (int i = 0; i < len; ++i) {
+    elli[(size_t)i * m.N + k] = m.indices[e0 + i];
+    ellw[(size_t)i * m.N + k] = m.w_rec[e0 + i];
+  }
+}
+
 struct SnnBwdShared {
   SnnShared f;
   float dI[kSnnMaxN];
@@ -270,7 +287,8 @@ struct SnnBwdShared {
 };
 
 __global__ void __launch_bounds__(1024) snn_backward_k(SnnDev m, const float* dlog_all, float* segV, uint8_t* segz,
-                                                       float* pin, float* prec) {
+                                                       float* pin, float* prec, const int32_t* elli,
+                                                       const float* ellw) {
   __shared__ SnnBwdShared sh;
   const int b = blockIdx.x, k = threadIdx.x;
   const bool valid = k < m.N;
@@ -287,6 +305,7 @@ __global__ void __launch_bounds__(1024) snn_backward_k(SnnDev m, const float* dl
     gd = gd / (float)m.T;
   }
   float dVn = 0.f;
+  const int re0 = valid ? m.indptr[k] : 0, re1 = valid ? m.indptr[k + 1] : 0;  // own row
   float* sV = segV + (size_t)b * m.E * m.N;
   uint8_t* sz = segz + (size_t)b * m.E * m.N;
   for (int seg = m.nck - 1; seg >= 0; --seg) {
@@ -312,42 +331,59 @@ __global__ void __launch_bounds__(1024) snn_backward_k(SnnDev m, const float* dl
       }
       __syncthreads();
     }
-    // reverse through the segment
+    // reverse through the segment; V_t and z_{t-1} of the next step are
+    // loaded one step ahead (z_t is the previous step's z_{t-1})
+    float Vn = 0.f;
+    uint8_t zc = 0, zp = 0;
+    if (valid) {
+      const int i = t1 - 1 - t0;
+      Vn = sV[(size_t)i * m.N + k];
+      zc = sz[(size_t)i * m.N + k];
+      zp = i > 0 ? sz[(size_t)(i - 1) * m.N + k] : z_start;
+    }
     for (int t = t1 - 1; t >= t0; --t) {
       const bool last = (t + 1 >= m.T);
+      const float Vt = Vn;
+      const bool zt = zc != 0;
+      const uint8_t zprev_t = zp;
+      uint8_t zp_next = 0;
+      if (valid && t > t0) {
+        const int i = t - 1 - t0;
+        Vn = sV[(size_t)i * m.N + k];
+        zp_next = i > 0 ? sz[(size_t)(i - 1) * m.N + k] : z_start;
+      }
       float dI = 0.f;
       if (valid) {
-        const float Vt = sV[(size_t)(t - t0) * m.N + k];
-        const bool zt = sz[(size_t)(t - t0) * m.N + k] != 0;
         float dz = gd;
         if (!last) {
-          // own row, entries in order; loads issued 32 entries ahead
+          // own row, entries in order
           float g = 0.f;
-          const int e0 = m.indptr[k], e1 = m.indptr[k + 1];
-          int idx = e0;
-          for (; idx + 32 <= e1; idx += 32) {
-            int c[32];
-            float wv[32];
+          // (transposed copy: entry i at [i * N + k], consecutive across lanes)
+          const int len = re1 - re0;
+          int i = 0;
+          for (; i + 16 <= len; i += 16) {
+            int c[16];
+            float wv[16];
 #pragma unroll
-            for (int u = 0; u < 32; ++u) {
-              c[u] = m.indices[idx + u];
-              wv[u] = m.w_rec[idx + u];
+            for (int u = 0; u < 16; ++u) {
+              c[u] = elli[(size_t)(i + u) * m.N + k];
+              wv[u] = ellw[(size_t)(i + u) * m.N + k];
             }
 #pragma unroll
-            for (int u = 0; u < 32; ++u) g += wv[u] * sh.dI[c[u]];
+            for (int u = 0; u < 16; ++u) g += wv[u] * sh.dI[c[u]];
           }
-          for (; idx + 8 <= e1; idx += 8) {
-            int c[8];
-            float wv[8];
+          for (; i + 4 <= len; i += 4) {
+            int c[4];
+            float wv[4];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              c[u] = m.indices[idx + u];
-              wv[u] = m.w_rec[idx + u];
+            for (int u = 0; u < 4; ++u) {
+              c[u] = elli[(size_t)(i + u) * m.N + k];
+              wv[u] = ellw[(size_t)(i + u) * m.N + k];
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) g += wv[u] * sh.dI[c[u]];
+            for (int u = 0; u < 4; ++u) g += wv[u] * sh.dI[c[u]];
           }
-          for (; idx < e1; ++idx) g += m.w_rec[idx] * sh.dI[m.indices[idx]];
+          for (; i < len; ++i) g += ellw[(size_t)i * m.N + k] * sh.dI[elli[(size_t)i * m.N + k]];
           dz += g;
           if (!m.detach) dz += dVn * (-m.beta * Vt);
         }
@@ -358,9 +394,12 @@ __global__ void __launch_bounds__(1024) snn_backward_k(SnnDev m, const float* dl
         dVn = dV;
       }
       __syncthreads();
-      if (valid) sh.dI[k] = dI;
-      // z_{t-1} of this sample: from the segment scratch or the checkpoint
-      if (valid) sh.f.zprev[k] = (t > t0) ? sz[(size_t)(t - 1 - t0) * m.N + k] : z_start;
+      if (valid) {
+        sh.dI[k] = dI;
+        sh.f.zprev[k] = zprev_t;  // z_{t-1}: from the segment scratch or the checkpoint
+      }
+      zc = zprev_t;
+      zp = zp_next;
       __syncthreads();
       stage_lists(m, b, t, sh.f);  // ends with a barrier
       if (valid) {
@@ -375,17 +414,18 @@ __global__ void __launch_bounds__(1024) snn_backward_k(SnnDev m, const float* dl
             if (q0 + u < nch) pin_b[(size_t)sh.f.ch[q0 + u] * m.N + k] = pv[u] + dI;
         }
       }
-      // rows of the neurons that fired at t - 1: wave w takes those of its 64
-      // neurons, lanes over the entries (each entry always by the same lane)
+      // rows of the neurons that fired at t - 1 (the staged list and row
+      // bounds): wave w takes rows w, w + waves, ..., lanes over the entries;
+      // every entry is updated once per step
       if (t > 0) {
-        const int klo = (int)(threadIdx.x / kWave) * kWave, l = lane_id();
-        for (uint64_t fired = __ballot(valid && sh.f.zprev[k]); fired; fired &= fired - 1) {
-          const int j = klo + __builtin_ctzll(fired);
-          const int e1 = m.indptr[j + 1];
-          for (int idx = m.indptr[j] + l; idx < e1; idx += kWave) prec_b[idx] += sh.dI[m.indices[idx]];
+        const int nwv = blockDim.x / kWave, l = lane_id();
+        for (int r = (int)(threadIdx.x / kWave); r < sh.f.nsp; r += nwv) {
+          const int e1 = sh.f.rhi[r];
+          for (int idx = sh.f.rlo[r] + l; idx < e1; idx += kWave) prec_b[idx] += sh.dI[m.indices[idx]];
         }
       }
-      __syncthreads();
+      // (no barrier here: the next step's first barrier orders these reads
+      // of sh before its writes)
     }
   }
 }
@@ -493,8 +533,12 @@ bp_status bp_snn_backward(const bp_snn* m, const void* ckpt, const float* logits
   BP_LAUNCHED("snn_loss_k");
   float* pin = (float*)(w + L.off_pin);
   float* prec = (float*)(w + L.off_prec);
+  int32_t* elli = (int32_t*)(w + L.off_elli);
+  float* ellw = (float*)(w + L.off_ellw);
+  snn_ell_k<<<(m->N + 255) / 256, 256, 0, st>>>(d, elli, ellw);
+  BP_LAUNCHED("snn_ell_k");
   snn_backward_k<<<m->B, snn_threads(m->N), 0, st>>>(d, dlog, (float*)(w + L.off_segV), (uint8_t*)(w + L.off_segz),
-                                                      pin, prec);
+                                                      pin, prec, elli, ellw);
   BP_LAUNCHED("snn_backward_k");
   if (dW_in) {
     const size_t n = (size_t)m->C * m->N;
