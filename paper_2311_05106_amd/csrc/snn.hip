@@ -92,12 +92,45 @@ struct SnnShared {
   float red[kSnnMaxO][1024 / kWave];
 };
 
+// Input bytes of one step held by wave 0 (up to 256 channels), loaded one
+// step ahead of their use.
+struct XPre {
+  int t;
+  bool on[4];
+};
+
 // Ascending lists of the firing input channels of sample b at step t (wave
 // 0) and of the neurons with sh.zprev set (the last wave), by wave ballots;
-// ends with a barrier.
-__device__ __forceinline__ void stage_lists(const SnnDev& m, int b, int t, SnnShared& sh) {
+// ends with a barrier.  Wave 0 also loads the input bytes of step t_next
+// (-1: none) into xp.
+__device__ __forceinline__ void stage_lists(const SnnDev& m, int b, int t, SnnShared& sh, XPre& xp, int t_next) {
   const int wv = threadIdx.x / kWave, l = lane_id(), last = blockDim.x / kWave - 1;
-  if (wv == 0) {
+  if (wv == 0 && m.C <= 4 * kWave) {
+    bool on[4];
+    const uint8_t* xt = m.x + ((size_t)t * m.B + b) * m.C;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int c = g * kWave + l;
+      on[g] = xp.t == t ? xp.on[g] : (c < m.C && xt[c]);
+    }
+    xp.t = t_next;
+    if (t_next >= 0) {
+      const uint8_t* xn = m.x + ((size_t)t_next * m.B + b) * m.C;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int c = g * kWave + l;
+        xp.on[g] = c < m.C && xn[c];
+      }
+    }
+    int base = 0;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const uint64_t msk = __ballot(on[g]);
+      if (on[g]) sh.ch[base + mask_rank(msk)] = g * kWave + l;
+      base += __popcll(msk);
+    }
+    if (l == 0) sh.nch = base;
+  } else if (wv == 0) {
     const uint8_t* xt = m.x + ((size_t)t * m.B + b) * m.C;
     int base = 0;
     for (int c0 = 0; c0 < m.C; c0 += 4 * kWave) {
@@ -200,6 +233,7 @@ __global__ void __launch_bounds__(1024) snn_forward_k(SnnDev m, float* logits, u
   const int b = blockIdx.x, k = threadIdx.x;
   const bool valid = k < m.N;
   float I = 0.f, V = 0.f, zs = 0.f;
+  XPre xp{-1, {false, false, false, false}};
   if (valid) sh.zprev[k] = 0;
   __syncthreads();
   for (int t = 0; t < m.T; ++t) {
@@ -209,7 +243,7 @@ __global__ void __launch_bounds__(1024) snn_forward_k(SnnDev m, float* logits, u
       m.ckV[o] = V;
       m.ckz[o] = sh.zprev[k];
     }
-    stage_lists(m, b, t, sh);
+    stage_lists(m, b, t, sh, xp, t + 1 < m.T ? t + 1 : -1);
     const bool z = fwd_step(m, k, valid, I, V, sh);
     if (valid) {
       sh.zprev[k] = z ? 1 : 0;
@@ -305,6 +339,7 @@ __global__ void __launch_bounds__(1024) snn_backward_k(SnnDev m, const float* dl
     gd = gd / (float)m.T;
   }
   float dVn = 0.f;
+  XPre xp{-1, {false, false, false, false}};
   const int re0 = valid ? m.indptr[k] : 0, re1 = valid ? m.indptr[k + 1] : 0;  // own row
   float* sV = segV + (size_t)b * m.E * m.N;
   uint8_t* sz = segz + (size_t)b * m.E * m.N;
@@ -322,7 +357,7 @@ __global__ void __launch_bounds__(1024) snn_backward_k(SnnDev m, const float* dl
     }
     __syncthreads();
     for (int t = t0; t < t1; ++t) {
-      stage_lists(m, b, t, sh.f);
+      stage_lists(m, b, t, sh.f, xp, t + 1 < t1 ? t + 1 : -1);
       const bool z = fwd_step(m, k, valid, I, V, sh.f);
       if (valid) {
         sh.f.zprev[k] = z ? 1 : 0;
@@ -401,7 +436,7 @@ __global__ void __launch_bounds__(1024) snn_backward_k(SnnDev m, const float* dl
       zc = zprev_t;
       zp = zp_next;
       __syncthreads();
-      stage_lists(m, b, t, sh.f);  // ends with a barrier
+      stage_lists(m, b, t, sh.f, xp, t > t0 ? t - 1 : -1);  // ends with a barrier
       if (valid) {
         // the listed channels are distinct: eight read-modify-writes in flight
         const int nch = sh.f.nch;
@@ -433,8 +468,17 @@ __global__ void __launch_bounds__(1024) snn_backward_k(SnnDev m, const float* dl
 __global__ void snn_reduce_k(const float* part, int B, size_t n, float* out) {
   const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
+  // samples in order, eight loads in flight
   float s = 0.f;
-  for (int b = 0; b < B; ++b) s += part[(size_t)b * n + i];
+  int b = 0;
+  for (; b + 8 <= B; b += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(b + u) * n + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; b < B; ++b) s += part[(size_t)b * n + i];
   out[i] = s;
 }
 
@@ -444,7 +488,18 @@ __global__ void snn_readout_grad_k(SnnDev m, const float* dlog, float* dW_out, f
   if (dW_out && i < m.N * m.O) {
     const int k = i / m.O, o = i % m.O;
     float s = 0.f;
-    for (int b = 0; b < m.B; ++b) s += m.zsum[(size_t)b * m.N + k] / (float)m.T * dlog[(size_t)b * m.O + o];
+    int b = 0;
+    for (; b + 8 <= m.B; b += 8) {  // samples in order, eight loads in flight
+      float zv[8], dv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        zv[u] = m.zsum[(size_t)(b + u) * m.N + k];
+        dv[u] = dlog[(size_t)(b + u) * m.O + o];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += zv[u] / (float)m.T * dv[u];
+    }
+    for (; b < m.B; ++b) s += m.zsum[(size_t)b * m.N + k] / (float)m.T * dlog[(size_t)b * m.O + o];
     dW_out[i] = s;
   }
   if (db_out && i < m.O) {
