@@ -123,6 +123,30 @@ def test_resume_and_checkpoint_roundtrip(bp, block):
     np.testing.assert_array_equal(r2c.cpu().numpy(), rr2)
 
 
+@pytest.mark.parametrize("block", [1024, 0])
+@pytest.mark.parametrize("at", [15, 16, 17, 31])
+def test_resume_at_tag_wrap_steps(bp, block, at):
+    """Inbox words carry the step modulo 16: restoring at steps around a wrap
+    of that tag (fresh net and rewind of a net that ran further) replays the
+    oracle's raster exactly."""
+    P, net, _, _ = make(bp, 20000, 80 / 20000, O.CONN_JIT, block, seed=5, max_wgs=16)
+    st = O.NetState(P)
+    O.net_run(P, st, at)
+    net.run(at)
+    raw = net.get_state()["raw"].clone()
+    rr, _, _ = O.net_run(P, st, 40)
+    r, _ = net.run(40, raster=True)
+    np.testing.assert_array_equal(r.cpu().numpy(), rr)
+    P2, net2, _, _ = make(bp, 20000, 80 / 20000, O.CONN_JIT, block, seed=5, max_wgs=16)
+    net2.set_state(raw, at)
+    r2, _ = net2.run(40, raster=True)
+    np.testing.assert_array_equal(r2.cpu().numpy(), rr)
+    net.run(7)  # the lines now hold later steps' tags
+    net.set_state(raw, at)
+    r3, _ = net.run(40, raster=True)
+    np.testing.assert_array_equal(r3.cpu().numpy(), rr)
+
+
 def test_step_api_with_external_current(bp):
     P, net, ip, ix = make(bp, 3000, 0.02, O.CONN_CSR, 0, seed=6, i_ext=0.0)
     st = O.NetState(P)
