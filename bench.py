@@ -2,7 +2,7 @@
 
 Headline workload: the COBA E/I LIF network scaled to 400,000 neurons
 (320,000 excitatory / 80,000 inhibitory), fixed-probability connectivity
-p = 80/N regenerated every step from the seed (JIT, post blocks of 2048),
+p = 80/N regenerated every step from the seed (JIT, post blocks of 2560),
 w_e = 0.6, w_i = 6.7, tau_e = 5 ms, tau_i = 10 ms, V_rest = -60 mV,
 V_th = -50 mV, refractory 5 ms, V0 ~ U(-60, -50) mV, I_ext = 20, dt = 0.1 ms,
 FP32 state.  One bench step = one simulation time step; the default K =
@@ -34,7 +34,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-C2_BLOCK = 2048
+C2_BLOCK = 2560
 
 
 def c2_desc(bp, n=400_000, seed=0, block=None):
@@ -50,9 +50,9 @@ def kernel_source_hash(name):
     return h.hexdigest()[:16]
 
 
-def counters_traffic(kernel_file, key, per_launch_units):
+def counters_traffic(kernel_file, key, per_launch_units, block=None):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if the
-    kernel source still matches the one they were taken on."""
+    kernel source and the block width still match the ones they were taken on."""
     path = os.path.join(ROOT, "profiles", "counters.json")
     if not os.path.exists(path):
         return None
@@ -61,6 +61,8 @@ def counters_traffic(kernel_file, key, per_launch_units):
             data = json.load(f)
         ent = data.get(key)
         if not ent or ent.get("source_hash") != kernel_source_hash(kernel_file):
+            return None
+        if block is not None and ent.get("block") != block:
             return None
         return ent["bytes_per_unit"] * per_launch_units
     except Exception:
@@ -300,7 +302,7 @@ def main():
     alg_bytes = (28.0 * r["n"] * steps + 8.0 * r["spikes"]) / launches  # per launch
     launch_s = sum(r["launch_ms"]) / launches * 1e-3  # average launch duration
     achieved = alg_bytes / launch_s / 1e9
-    traffic = counters_traffic("net.hip", "net_run_k_coba400k_jit", steps / launches)
+    traffic = counters_traffic("net.hip", "net_run_k_coba400k_jit", steps / launches, block=C2_BLOCK)
     roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
                     traffic=traffic, kernel="net_run_k", alg_bytes_per_launch=alg_bytes,
                     launch_ms=launch_s * 1e3, launches=launches, steps_per_launch=LAUNCH_STEPS)

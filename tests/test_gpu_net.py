@@ -60,6 +60,8 @@ def first_diff(a, b):
     (O.CONN_JIT, 9000, 0.01, 700, 5, 300),            # range not a multiple of the block
     (O.CONN_JIT, 100000, 80 / 100000, 0, 25, 200),    # whole rows pushed as targets, lines mostly fit
     (O.CONN_JIT, 20000, 0.02, 0, 8, 200),             # 400 targets per row: lines overflow, regenerated
+    (O.CONN_JIT, 20000, 80 / 20000, 2560, 8, 300),    # ranges of 2560: three neurons on some threads
+    (O.CONN_JIT, 30000, 80 / 30000, 0, 8, 200),       # whole rows, ranges of 3750
 ])
 def test_raster_bitwise(bp, conn, n, p, block, max_wgs, T):
     P, net, ip, ix = make(bp, n, p, conn, block, seed=1, max_wgs=max_wgs)
@@ -177,9 +179,9 @@ def test_run_batch_equals_solo_runs(bp):
         assert net.info().step == steps[i]
 
 
-@pytest.mark.parametrize("block", [2048, 0])
+@pytest.mark.parametrize("block", [2560, 0])
 def test_large_jit_net_first_steps(bp, block):
-    # 400k neurons (320k E / 80k I), p = 80/N, post blocks of 2048 (spike ids
+    # 400k neurons (320k E / 80k I), p = 80/N, post blocks of 2560 (spike ids
     # exchanged) or whole rows (targets exchanged): the first 40 steps
     # bit-identical to the oracle (full-size shape of the scaled net).
     n = 400_000
