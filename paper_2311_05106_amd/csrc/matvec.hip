@@ -17,9 +17,11 @@
 //   group at once (40 loads in flight per lane for counts, the next rows'
 //   bounds fetched ahead), so a wave reads four segments per instruction,
 //   coalesced.
-//   JIT rows are regenerated per (row, block) by one lane each; the tile is
-//   one block, so no lane generates targets outside its tile, and with
-//   enough blocks to cover the chip no row chunks (and no partials) are used.
+//   JIT rows are regenerated per (row, block) by one lane each, or by four
+//   lanes (one generator call each, positions by a quad prefix sum) when a
+//   pass lists at most 256 rows; the tile is one block, so no lane generates
+//   targets outside its tile, and with enough blocks to cover the chip no
+//   row chunks (and no partials) are used.
 #include "bp_device.h"
 #include "bp_host.h"
 
@@ -209,6 +211,73 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
       const uint32_t K = (uint32_t)a.jit.max_gap;
       const int32_t wkind = a.jit.wkind, n_post = a.n_post;
       const float w0 = a.jit.w0, w1 = a.jit.w1;
+      if (B > 0 && nbt == 1 && items * 4 <= kMvThreads) {
+        // Few rows in the pass: four lanes per row.  In pass P lane q draws
+        // generator block 4P + q (draws 16P + 4q .. 16P + 4q + 3); a prefix
+        // of the lanes' gap sums over the quad places the targets, so a row
+        // of up to 14 targets takes one generator call per lane instead of
+        // a sequential walk.  Positions and target indices are those of
+        // the walk (target m >= 1 at the previous one plus 1 + draw m + 1).
+        const int ai = (int)threadIdx.x >> 2, q = (int)threadIdx.x & 3;
+        const int qb = lane_id() & ~3;
+        const bool act = ai < items;
+        const uint32_t b = (uint32_t)b_lo;
+        const int64_t end = hi;
+        const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+        const uint32_t j = act ? (uint32_t)sh.ids[ai] : 0u;
+        DrawSeq wd(seed, kStreamW, j, b);
+        auto shfl64 = [](int64_t v, int src) {
+          const uint32_t lo32 = (uint32_t)__shfl((int)(uint32_t)v, src, kWave);
+          const uint32_t hi32 = (uint32_t)__shfl((int)(uint32_t)((uint64_t)v >> 32), src, kWave);
+          return (int64_t)(((uint64_t)hi32 << 32) | lo32);
+        };
+        bool live = act;
+        int64_t prev = 0;  // last position of the previous pass
+        for (uint32_t pass = 0;; ++pass) {
+          const uint32_t blk = 4 * pass + (uint32_t)q;
+          const Words4 w = philox10(j, b, blk, kStreamConn, k0, k1);
+          int64_t g[4];
+          g[0] = 1 + (int64_t)below(w.x, K);
+          g[1] = 1 + (int64_t)below(w.y, K);
+          g[2] = 1 + (int64_t)below(w.z, K);
+          g[3] = 1 + (int64_t)below(w.w, K);
+          int64_t first = 0;
+          if (blk == 0) {  // draws 0 and 1 give the first target, not gaps
+            const uint32_t ra = below(w.x, K), rb = below(w.y, K + 1u);
+            first = (int64_t)b * B + (int64_t)(ra < rb ? ra : rb);
+            g[0] = 0;
+            g[1] = 0;
+          }
+          const int64_t sum = g[0] + g[1] + g[2] + g[3];
+          const int64_t s0 = shfl64(sum, qb), s1 = shfl64(sum, qb + 1), s2 = shfl64(sum, qb + 2);
+          const int64_t b0 = pass == 0 ? shfl64(first, qb) : prev;
+          const int64_t excl = (q > 0 ? s0 : 0) + (q > 1 ? s1 : 0) + (q > 2 ? s2 : 0);
+          int64_t pos = b0 + excl;
+          if (live && blk == 0 && pos < end) {  // target 0
+            if constexpr (MODE == kJitHomo) {
+              atomicAdd(&acc[pos - lo], 1u);
+            } else {
+              float unit;
+              lds_add_f32(&acc[pos - lo], jit_weight(wd, wkind, w0, w1, 0u, &unit));
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            pos += g[u];
+            if (live && g[u] > 0 && pos < end) {
+              if constexpr (MODE == kJitHomo) {
+                atomicAdd(&acc[pos - lo], 1u);
+              } else {
+                float unit;
+                lds_add_f32(&acc[pos - lo], jit_weight(wd, wkind, w0, w1, 4u * blk - 1u + (uint32_t)u, &unit));
+              }
+            }
+          }
+          prev = shfl64(pos, qb + 3);  // the pass's last position
+          live = live && prev < end;
+          if (__ballot(live) == 0) break;
+        }
+      } else
       for (int it = threadIdx.x; it < items; it += kMvThreads) {
         const int ai = nbt == 1 ? it : it / nbt;
         const uint32_t b = (uint32_t)(b_lo + (nbt == 1 ? 0 : it % nbt));
