@@ -322,14 +322,26 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
   }
 }
 
+// First of the two columns of this thread in the reductions: workgroup b
+// takes 512 columns of tile b mod n_tiles, the same tile-to-workgroup order
+// as the scatter, so with a multiple of 8 tiles the partials of a tile are
+// read on the XCD that wrote them (workgroups are dealt to the 8 XCDs in
+// turn).  With an odd tile width the second column may be the next tile's
+// first, which that tile's thread also writes, with the same value.
+__device__ __forceinline__ int32_t reduce_col(int32_t tile, int32_t n_tiles) {
+  const int32_t t = (int32_t)blockIdx.x % n_tiles, sl = (int32_t)blockIdx.x / n_tiles;
+  const int32_t k = sl * 512 + (int32_t)threadIdx.x * 2;
+  return k < tile ? t * tile + k : INT32_MAX;
+}
+
 // y[k] = w * sum_c counts[c][k]  (integer sum, one FP32 rounding); two
 // consecutive columns per thread, eight chunk loads in flight.
 __global__ void mv_reduce_counts_k(const uint16_t* __restrict__ part, int32_t chunks, int32_t n_post, float w,
-                                   float* __restrict__ y) {
-  const int32_t k = (blockIdx.x * blockDim.x + threadIdx.x) * 2;
+                                   float* __restrict__ y, int32_t tile, int32_t n_tiles) {
+  const int32_t k = reduce_col(tile, n_tiles);
   if (k >= n_post) return;
   const bool vec = ((reinterpret_cast<uintptr_t>(part) | reinterpret_cast<uintptr_t>(y)) & 7) == 0;
-  if (vec && k + 2 <= n_post && (n_post & 1) == 0) {
+  if (vec && (tile & 1) == 0 && k + 2 <= n_post && (n_post & 1) == 0) {
     uint32_t s0 = 0, s1 = 0;
 #pragma unroll 8
     for (int c = 0; c < chunks; ++c) {
@@ -349,11 +361,12 @@ __global__ void mv_reduce_counts_k(const uint16_t* __restrict__ part, int32_t ch
 }
 // y[k] = sum_c part[c][k] in chunk order; two consecutive columns per thread,
 // eight chunk loads in flight.
-__global__ void mv_reduce_f32_k(const float* __restrict__ part, int32_t chunks, int32_t n_post, float* __restrict__ y) {
-  const int32_t k = (blockIdx.x * blockDim.x + threadIdx.x) * 2;
+__global__ void mv_reduce_f32_k(const float* __restrict__ part, int32_t chunks, int32_t n_post, float* __restrict__ y,
+                                int32_t tile, int32_t n_tiles) {
+  const int32_t k = reduce_col(tile, n_tiles);
   if (k >= n_post) return;
   const bool vec = ((reinterpret_cast<uintptr_t>(part) | reinterpret_cast<uintptr_t>(y)) & 7) == 0;
-  if (vec && k + 2 <= n_post && (n_post & 1) == 0) {
+  if (vec && (tile & 1) == 0 && k + 2 <= n_post && (n_post & 1) == 0) {
     float s0 = 0.f, s1 = 0.f;
 #pragma unroll 8
     for (int c = 0; c < chunks; ++c) {
@@ -542,9 +555,9 @@ static bp_status launch_scatter(const MvArgs& a, const MvPlan& p, hipStream_t st
 static bp_status finish_partials(const MvPlan& p, bool homo, void* ws, int32_t n_post, float w, float* y,
                                  hipStream_t st) {
   if (p.chunks <= 1 || n_post == 0) return BP_OK;
-  const int g = (n_post + 511) / 512;
-  if (homo) mv_reduce_counts_k<<<g, 256, 0, st>>>((const uint16_t*)ws, p.chunks, n_post, w, y);
-  else mv_reduce_f32_k<<<g, 256, 0, st>>>((const float*)ws, p.chunks, n_post, y);
+  const int g = p.n_tiles * ((p.tile + 511) / 512);
+  if (homo) mv_reduce_counts_k<<<g, 256, 0, st>>>((const uint16_t*)ws, p.chunks, n_post, w, y, p.tile, p.n_tiles);
+  else mv_reduce_f32_k<<<g, 256, 0, st>>>((const float*)ws, p.chunks, n_post, y, p.tile, p.n_tiles);
   BP_LAUNCHED("mv_reduce_k");
   return BP_OK;
 }

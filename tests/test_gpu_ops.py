@@ -107,7 +107,9 @@ def _to(x, dtype=None):
 @pytest.mark.parametrize("n_pre,n_post,p,frac,tiled", [
     (4000, 4000, 0.02, 0.003, False),     # single tile, single chunk
     (60000, 9000, 0.01, 0.1, False),      # many chunks -> partial sums
+    (60000, 9001, 0.01, 0.1, False),      # odd tile width with partial sums
     (20000, 50000, 0.002, 0.05, True),    # several tiles with the tile index
+    (20000, 50000, 0.002, 0.05, 8191),    # odd tile width, several tiles, partial sums
     (20000, 50000, 0.002, 0.05, False),   # several tiles, no index -> atomic kernel
     (3000, 20000, 0.01, 1.0, True),       # every row fires
     (3000, 20000, 0.01, 0.0, True),       # no row fires
@@ -119,7 +121,8 @@ def test_event_csr_homogeneous_bitwise(bp, n_pre, n_post, p, frac, tiled):
     w = np.float32(0.6)
     ref = (cnt.astype(np.float32) * w).astype(np.float32)
     ipt, ixt, et = _to(ip), _to(ix), _to(e)
-    tp, tw = (bp.csr_tile_index(ipt, ixt, n_post, 8192), 8192) if tiled else (None, 0)
+    width = 8192 if tiled is True else int(tiled)
+    tp, tw = (bp.csr_tile_index(ipt, ixt, n_post, width), width) if tiled else (None, 0)
     y = bp.event_csr_matvec(ipt, ixt, None, float(w), n_post, et, tile_ptr=tp, tile_width=tw)
     np.testing.assert_array_equal(y.cpu().numpy(), ref)
     # repeated calls give the same bits
@@ -131,6 +134,7 @@ def test_event_csr_homogeneous_bitwise(bp, n_pre, n_post, p, frac, tiled):
     (4000, 4000, 0.02, 0.01, False),
     (60000, 9000, 0.01, 0.1, False),
     (20000, 50000, 0.002, 0.05, True),
+    (20000, 50000, 0.002, 0.05, 8191),
     (20000, 50000, 0.002, 0.05, False),
 ])
 def test_event_csr_heterogeneous(bp, n_pre, n_post, p, frac, tiled):
@@ -140,7 +144,8 @@ def test_event_csr_heterogeneous(bp, n_pre, n_post, p, frac, tiled):
     ref = O.event_csr_matvec(ip, ix, data, 0.0, n_post, e)
     scale = O.event_csr_matvec(ip, ix, np.abs(data), 0.0, n_post, e)
     ipt, ixt = _to(ip), _to(ix)
-    tp, tw = (bp.csr_tile_index(ipt, ixt, n_post, 8192), 8192) if tiled else (None, 0)
+    width = 8192 if tiled is True else int(tiled)
+    tp, tw = (bp.csr_tile_index(ipt, ixt, n_post, width), width) if tiled else (None, 0)
     y = bp.event_csr_matvec(ipt, ixt, _to(data), 0.0, n_post, _to(e), tile_ptr=tp, tile_width=tw)
     _tol_check(y.cpu().numpy(), ref, scale, name="hetero")
 
