@@ -141,7 +141,7 @@ def bench_c0(bp, torch, reps=5):
                 us_per_step=t * 1e3, sim_s_per_wall_s=0.1 / t, synaptic_events_per_s=ev / t)
 
 
-def bench_ops(bp, torch, calls=10000):
+def bench_ops(bp, torch, calls=10000, fracs=(0.001, 0.01, 0.1)):
     """Operator sweep: n_pre = n_post = 1e5, p = 0.01; each point runs `calls`
     products cycling 64 event vectors, replayed from a HIP graph."""
     import numpy as np
@@ -155,7 +155,7 @@ def bench_ops(bp, torch, calls=10000):
     data = torch.from_numpy(S.hetero_data(nnz, 1)).to(dev)
     rowlen = (ip[1:] - ip[:-1]).to(torch.int64)
     out = []
-    for frac in (0.001, 0.01, 0.1):
+    for frac in fracs:
         ev = torch.from_numpy(S.events(n, frac, 5, count=64)).to(dev)
         ev_f = ev.to(torch.int64)
         nnz_a = float((ev_f * rowlen[None, :]).sum(1).double().mean().item())
@@ -266,6 +266,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--block", type=int, default=C2_BLOCK, help="post-block width of the JIT connectivity")
     ap.add_argument("--calls", type=int, default=10000, help="products per point of the operator sweep")
+    ap.add_argument("--ops-frac", type=float, default=None,
+                    help="run the operator sweep at this firing fraction only (for profiling)")
     ap.add_argument("--section", choices=["c0", "ops", "snn", "serving"],
                     help="run only this secondary workload and print its JSON (for profiling)")
     args = ap.parse_args()
@@ -282,7 +284,8 @@ def main():
 
     if args.section:
         if args.section == "ops":
-            res = bench_ops(bp, torch, calls=args.calls)
+            res = bench_ops(bp, torch, calls=args.calls,
+                            **({} if args.ops_frac is None else {"fracs": (args.ops_frac,)}))
         else:
             res = dict(c0=bench_c0, snn=bench_snn, serving=bench_serving)[args.section](bp, torch)
         print(json.dumps({args.section: res}), flush=True)
