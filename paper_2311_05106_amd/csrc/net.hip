@@ -723,12 +723,15 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
 #pragma unroll
     for (int i = 0; i < kNPT; ++i) {
       const int k = i * kNetThreads + tid;
+      // k < kRangeMax: always inside the arrays, so the accesses need no
+      // guard (a guarded access is a branch and a wait of its own); values
+      // for k >= R are never used
       if constexpr (PUSH) {  // read and clear in one LDS exchange (the next gather adds at once)
-        ce[i] = k < R ? atomicExch(&sh.cE[k], 0u) : 0u;
-        ci[i] = k < R ? atomicExch(&sh.cI[k], 0u) : 0u;
+        ce[i] = atomicExch(&sh.cE[k], 0u);
+        ci[i] = atomicExch(&sh.cI[k], 0u);
       } else {  // cleared at the start of the next step
-        ce[i] = k < R ? sh.cE[k] : 0u;
-        ci[i] = k < R ? sh.cI[k] : 0u;
+        ce[i] = sh.cE[k];
+        ci[i] = sh.cI[k];
       }
     }
 #pragma unroll
