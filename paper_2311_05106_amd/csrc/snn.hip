@@ -196,24 +196,27 @@ __device__ __forceinline__ bool fwd_step(const SnnDev& m, int k, bool valid, flo
   for (int r0 = 0; r0 < nsp; r0 += 4) {
     int kk[4];
     float wr[4];
+    int rl[4], rh[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {  // r0 + u < kSnnMaxN: unguarded LDS reads, masked below
+      rl[u] = sh.rlo[r0 + u];
+      rh[u] = sh.rhi[r0 + u];
+    }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       kk[u] = -1;
       wr[u] = 0.f;
-      if (r0 + u < nsp) {
-        const int e = sh.rlo[r0 + u] + l;
-        if (e < sh.rhi[r0 + u]) {
-          kk[u] = m.indices[e];
-          wr[u] = m.w_rec[e];
-        }
+      const int e = rl[u] + l;
+      if (r0 + u < nsp && e < rh[u]) {
+        kk[u] = m.indices[e];
+        wr[u] = m.w_rec[e];
       }
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       if (r0 + u < nsp) {
         if (kk[u] >= klo && kk[u] < klo + kWave && kk[u] < m.N) sh.acc[kk[u]] = sh.acc[kk[u]] + wr[u];
-        const int e1 = sh.rhi[r0 + u];
-        for (int e = sh.rlo[r0 + u] + kWave + l; e < e1; e += kWave) {  // rows longer than 64
+        for (int e = rl[u] + kWave + l; e < rh[u]; e += kWave) {  // rows longer than 64
           const int c = m.indices[e];
           if (c >= klo && c < klo + kWave && c < m.N) sh.acc[c] = sh.acc[c] + m.w_rec[e];
         }
