@@ -273,7 +273,7 @@ def main():
     args = ap.parse_args()
     globals()["C2_BLOCK"] = args.block
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
+        print(f"bench.py: the implementation runs on one GPU only (got --gpus {args.gpus}); "
               "the multi-GPU design is described but not built", file=sys.stderr)
         sys.exit(2)
     import torch

@@ -42,7 +42,7 @@ typedef int32_t bp_status;
 #define BP_ENOMEM (-2)       /* caller's workspace too small */
 #define BP_EDEVICE (-3)      /* HIP runtime error (message holds hipGetErrorString) */
 #define BP_ESTATE (-4)       /* object used in a wrong state (destroyed net, stalled kernel) */
-#define BP_EUNSUPPORTED (-5) /* valid request this build does not support */
+#define BP_EUNSUPPORTED (-5) /* valid request the library does not support */
 
 typedef void* bp_stream; /* hipStream_t */
 
