@@ -141,6 +141,11 @@ def bench_c0(bp, torch, reps=5):
                 us_per_step=t * 1e3, sim_s_per_wall_s=0.1 / t, synaptic_events_per_s=ev / t)
 
 
+# JIT operator blocks of 782 columns: 128 column tiles x 2 row chunks make 256
+# workgroups, one per compute unit (blocks of 1024 left 60 idle)
+JIT_OP_BLOCK = 782
+
+
 def bench_ops(bp, torch, calls=10000, fracs=(0.001, 0.01, 0.1)):
     """Operator sweep: n_pre = n_post = 1e5, p = 0.01; each point runs `calls`
     products cycling 64 event vectors, replayed from a HIP graph."""
@@ -160,8 +165,8 @@ def bench_ops(bp, torch, calls=10000, fracs=(0.001, 0.01, 0.1)):
         ev_f = ev.to(torch.int64)
         nnz_a = float((ev_f * rowlen[None, :]).sum(1).double().mean().item())
         act = float(ev_f.sum(1).double().mean().item())
-        jc = bp.JitConn(n, n, K=K, block=1024, seed=0, w0=0.5)
-        jn = bp.JitConn(n, n, K=K, block=1024, seed=0, wkind=bp.W_NORMAL, w0=0.5, w1=0.1)
+        jc = bp.JitConn(n, n, K=K, block=JIT_OP_BLOCK, seed=0, w0=0.5)
+        jn = bp.JitConn(n, n, K=K, block=JIT_OP_BLOCK, seed=0, wkind=bp.W_NORMAL, w0=0.5, w1=0.1)
         y = torch.empty(n, dtype=torch.float32, device=dev)
         cases = [
             ("event_csr_homo", lambda e: bp.event_csr_matvec(ip, ix, None, 0.5, n, e, tp, tw, out=y, ws=ws_c),
