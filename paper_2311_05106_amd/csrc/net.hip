@@ -163,8 +163,8 @@ __device__ __forceinline__ uint64_t line_word(uint32_t tag, int q, int total, Id
 #pragma unroll
   for (int i = 0; i < 4; ++i) x[i] = (uint32_t)id(first + i);  // unconditional: the reads issue together
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-    if (i < n) v |= (uint64_t)(x[i] & 0xFFFu) << (12 * i);
+  for (int i = 0; i < 4; ++i)  // masked arithmetically, so no read moves into a branch
+    v |= (uint64_t)(x[i] & (i < n ? 0xFFFu : 0u)) << (12 * i);
   return v;
 }
 // byte offset of the half h (words 2h, 2h + 1) of line (par, dst, src) in
@@ -201,8 +201,7 @@ __device__ __forceinline__ uint64_t tline_word(uint32_t tag, int q, int c, int c
 #pragma unroll
   for (int i = 0; i < 4; ++i) x[i] = ent(min(first + i, kTgtLine - 1));
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-    if (i < n) v |= (uint64_t)(x[i] & 0x1FFFu) << (13 * i);
+  for (int i = 0; i < 4; ++i) v |= (uint64_t)(x[i] & (i < n ? 0x1FFFu : 0u)) << (13 * i);
   return v;
 }
 
