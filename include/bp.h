@@ -223,8 +223,8 @@ typedef struct {
   float v_rest, v_th, v_reset, e_exc, e_inh, r, i_ext, dt;
   float v0_lo, v0_hi;
   int32_t max_wgs; /* upper bound on the workgroups the net runs on
-                      (0 = one per compute unit); fewer lets more nets share
-                      the GPU in bp_run_batch */
+                      (0 = default: one per compute unit, at most 160);
+                      fewer lets more nets share the GPU in bp_run_batch */
 } bp_net_desc;
 
 typedef struct bp_net_s* bp_net;
