@@ -82,6 +82,8 @@ def lib():
         L.or_jit_matvec.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                     C.c_int32, C.c_int32, _u8p, _f64p]
         L.or_jit_counts.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _u8p, _i64p]
+        L.or_jit_matvec_dense.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                          C.c_int32, C.c_int32, _f64p, _f64p]
         L.or_jit_vjp.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                  C.c_int32, C.c_int32, _u8p, _f64p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.or_net_v0.argtypes = [C.POINTER(NetParams), _f32p]
@@ -212,6 +214,15 @@ def jit_matvec(seed, K, B, wkind, w0, w1, n_post, events):
     ev = np.ascontiguousarray(events, np.uint8)
     y = np.empty(n_post, np.float64)
     lib().or_jit_matvec(seed, K, B, wkind, float(w0), float(w1), ev.shape[0], n_post, ev, y)
+    return y
+
+
+def jit_matvec_dense(seed, K, B, wkind, w0, w1, n_post, v):
+    """y = J v for a float vector v (Section 5.2's JIT operator on a dense
+    vector); FP64."""
+    vv = np.ascontiguousarray(v, np.float64)
+    y = np.empty(n_post, np.float64)
+    lib().or_jit_matvec_dense(seed, K, B, wkind, float(w0), float(w1), vv.shape[0], n_post, vv, y)
     return y
 
 

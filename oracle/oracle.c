@@ -319,6 +319,24 @@ void or_jit_matvec(uint64_t seed, int32_t K, int32_t B, int32_t wkind, double w0
   free(buf);
 }
 
+/* Float-vector JIT product (Section 5.2: y = J v with J given by its
+ * probability, weight distribution and seed; every row j contributes its
+ * weights times v[j]; rows with v[j] == 0 contribute nothing). */
+void or_jit_matvec_dense(uint64_t seed, int32_t K, int32_t B, int32_t wkind, double w0, double w1,
+                         int32_t n_pre, int32_t n_post, const double* v, double* y) {
+  int32_t* buf = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_post > 0 ? n_post : 1));
+  int32_t nb = n_blocks(n_post, B);
+  for (int32_t k = 0; k < n_post; ++k) y[k] = 0.0;
+  for (int32_t j = 0; j < n_pre; ++j) {
+    if (v[j] == 0.0) continue;
+    for (int32_t b = 0; b < nb; ++b) {
+      int64_t c = or_row_block(seed, K, n_post, B, j, b, buf);
+      for (int64_t m = 0; m < c; ++m) y[buf[m]] += or_jit_weight(seed, wkind, w0, w1, j, b, m, NULL) * v[j];
+    }
+  }
+  free(buf);
+}
+
 void or_jit_counts(uint64_t seed, int32_t K, int32_t B, int32_t n_pre, int32_t n_post,
                    const uint8_t* ev, int64_t* cnt) {
   int32_t* buf = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_post > 0 ? n_post : 1));

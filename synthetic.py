@@ -37,6 +37,14 @@ def cotangent(n, seed):
     return rng.standard_normal(n)
 
 
+def dense_vector(n, seed, zero_frac=0.0):
+    """A dense FP32 input vector ~ N(0, 1) with a fraction of exact zeros."""
+    rng = np.random.default_rng([seed, 12])
+    v = rng.standard_normal(n).astype(np.float32)
+    v[rng.random(n) < zero_frac] = 0.0
+    return v
+
+
 def poisson_inputs(T, B, C, dt_ms, seed, lo_hz=5.0, hi_hz=50.0):
     """x[t, b, c] ~ Bernoulli(r_bc dt), r_bc ~ U(lo, hi) Hz.  uint8 [T, B, C]."""
     rng = np.random.default_rng([seed, 4])

@@ -103,6 +103,45 @@ def test_jit_weighted_bruteforce(wkind):
     np.testing.assert_allclose(y, D.T @ e, rtol=1e-12, atol=1e-12)
 
 
+@pytest.mark.parametrize("wkind", [O.W_HOMO, O.W_NORMAL, O.W_UNIFORM])
+def test_jit_dense_vector_bruteforce(wkind):
+    # Section 5.2's JIT operator on a float vector: y = sum_j v[j] J[j, :],
+    # the dense matrix assembled entry by entry and multiplied by numpy.
+    seed, K, n_pre, n_post, B = 8, 7, 45, 70, 16
+    w0, w1 = {O.W_HOMO: (0.3, 0.0), O.W_NORMAL: (0.5, 0.1), O.W_UNIFORM: (-1.0, 2.0)}[wkind]
+    D = np.zeros((n_pre, n_post))
+    for j in range(n_pre):
+        for b in range(-(-n_post // B)):
+            for m, k in enumerate(O.row_block(seed, K, n_post, B, j, b)):
+                D[j, k] += O.jit_weight(seed, wkind, w0, w1, j, b, m)[0]
+    v = S.dense_vector(n_pre, 2, zero_frac=0.3).astype(np.float64)
+    y = O.jit_matvec_dense(seed, K, B, wkind, w0, w1, n_post, v)
+    np.testing.assert_allclose(y, D.T @ v, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("B", [0, 64])
+def test_jit_dense_vector_special_cases(B):
+    # On a 0/1 vector the float product is the event product; a stored CSR of
+    # the same seed gives the same homogeneous product through scipy; the
+    # product is linear in v; v = 0 gives 0.
+    seed, K, n_pre, n_post = 31, 23, 300, 410
+    e = S.events(n_pre, 0.2, 4)
+    for wk, w0, w1 in [(O.W_HOMO, 0.7, 0.0), (O.W_NORMAL, 0.5, 0.1)]:
+        np.testing.assert_array_equal(O.jit_matvec_dense(seed, K, B, wk, w0, w1, n_post, e.astype(np.float64)),
+                                      O.jit_matvec(seed, K, B, wk, w0, w1, n_post, e))
+    ip, ix = O.csr_build(seed, K, n_pre, n_post, B)
+    M = sp.csr_matrix((np.ones(ix.size), ix, ip), shape=(n_pre, n_post))
+    v1 = S.dense_vector(n_pre, 5).astype(np.float64)
+    v2 = S.dense_vector(n_pre, 6, zero_frac=0.5).astype(np.float64)
+    y1 = O.jit_matvec_dense(seed, K, B, O.W_HOMO, 1.5, 0.0, n_post, v1)
+    np.testing.assert_allclose(y1, 1.5 * (M.T @ v1), rtol=1e-12, atol=1e-12)
+    y2 = O.jit_matvec_dense(seed, K, B, O.W_UNIFORM, -0.5, 1.0, n_post, v2)
+    y12 = O.jit_matvec_dense(seed, K, B, O.W_UNIFORM, -0.5, 1.0, n_post, 2.0 * v1 - 3.0 * v2)
+    y1u = O.jit_matvec_dense(seed, K, B, O.W_UNIFORM, -0.5, 1.0, n_post, v1)
+    np.testing.assert_allclose(y12, 2.0 * y1u - 3.0 * y2, rtol=1e-11, atol=1e-11)
+    assert not O.jit_matvec_dense(seed, K, B, O.W_NORMAL, 0.5, 0.1, n_post, np.zeros(n_pre)).any()
+
+
 def test_jit_normal_weights_are_normal():
     z = np.array([O.jit_weight(3, O.W_NORMAL, 0.0, 1.0, j, 0, m)[1] for j in range(400) for m in range(50)])
     assert abs(z.mean()) < 5 / math.sqrt(z.size)
