@@ -210,6 +210,53 @@ def bench_ops(bp, torch, calls=10000, fracs=(0.001, 0.01, 0.1)):
     return out
 
 
+def bench_dense(bp, torch, calls=640):
+    """JIT product on dense float vectors (Section 5.2's operator y = J^T v):
+    n_pre = n_post = 1e5, p = 0.01, blocks of JIT_OP_BLOCK columns, v ~ N(0, 1)
+    with no zeros (every row contributes); `calls` products cycling 8
+    vectors, replayed from a HIP graph."""
+    import synthetic as S
+    n, K = 100_000, bp.max_gap(0.01)
+    dev = "cuda"
+    vs = [torch.from_numpy(S.dense_vector(n, 30 + i)).to(dev) for i in range(8)]
+    y = torch.empty(n, dtype=torch.float32, device=dev)
+    out = []
+    for name, wk, w0, w1 in [("homo", bp.W_HOMO, 0.5, 0.0), ("uniform", bp.W_UNIFORM, -1.0, 1.0),
+                             ("normal", bp.W_NORMAL, 0.5, 0.1)]:
+        conn = bp.JitConn(n, n, K=K, block=JIT_OP_BLOCK, seed=0, wkind=wk, w0=w0, w1=w1)
+        ws = torch.empty(max(bp.jit_dense_ws(conn), 1), dtype=torch.uint8, device=dev)
+        # synapses per product: the row lengths of the same seed (every row is listed)
+        ip, _ = bp.csr_build(conn)
+        nnz = float(ip[-1].item())
+        fn = lambda v: bp.jit_conn_matvec_dense(conn, v, out=y, ws=ws)
+        for v in vs:
+            fn(v)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                for v in vs:
+                    fn(v)
+        torch.cuda.synchronize()
+        reps = max(1, calls // 8)
+        g.replay()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            g.replay()
+        b.record()
+        torch.cuda.synchronize()
+        us = a.elapsed_time(b) * 1e3 / (reps * 8)
+        # CSR-equivalent bytes: what a stored matrix would stream (4 B index + 4 B weight per synapse)
+        gbs = 8.0 * nnz / (us * 1e-6) / 1e9
+        out.append(dict(op=f"jit_dense_{name}", us_per_call=us, synapses=nnz, synapses_per_s=nnz / (us * 1e-6),
+                        csr_equiv_GBps=gbs, csr_equiv_frac=gbs / HBM_PEAK_GBS))
+        del g
+    return out
+
+
 def bench_snn(bp, torch, reps=5):
     """Differentiable recurrent LIF network: batch 256, 128 Poisson inputs
     (5-50 Hz), 512 neurons with p = 0.1 recurrent CSR, 10 classes, 250 steps
@@ -273,7 +320,7 @@ def main():
     ap.add_argument("--calls", type=int, default=10000, help="products per point of the operator sweep")
     ap.add_argument("--ops-frac", type=float, default=None,
                     help="run the operator sweep at this firing fraction only (for profiling)")
-    ap.add_argument("--section", choices=["c0", "ops", "snn", "serving"],
+    ap.add_argument("--section", choices=["c0", "ops", "dense", "snn", "serving"],
                     help="run only this secondary workload and print its JSON (for profiling)")
     args = ap.parse_args()
     globals()["C2_BLOCK"] = args.block
@@ -292,7 +339,7 @@ def main():
             res = bench_ops(bp, torch, calls=args.calls,
                             **({} if args.ops_frac is None else {"fracs": (args.ops_frac,)}))
         else:
-            res = dict(c0=bench_c0, snn=bench_snn, serving=bench_serving)[args.section](bp, torch)
+            res = dict(c0=bench_c0, dense=bench_dense, snn=bench_snn, serving=bench_serving)[args.section](bp, torch)
         print(json.dumps({args.section: res}), flush=True)
         return
 
@@ -336,6 +383,7 @@ def main():
             sim_s_per_wall_s=2000 * w["dt_ms"] * 1e-3 / w["wall"])
         line["c0"] = bench_c0(bp, torch)
         line["operator_sweep"] = bench_ops(bp, torch, calls=args.calls)
+        line["jit_dense_vector"] = bench_dense(bp, torch)
         line["snn_training"] = bench_snn(bp, torch)
         line["serving"] = bench_serving(bp, torch)
     print(json.dumps(line), flush=True)

@@ -174,6 +174,21 @@ size_t bp_jit_ws_bytes(const bp_jit_conn* c);
 bp_status bp_jit_conn_matvec(const bp_jit_conn* c, const uint8_t* events, float* y, void* ws, size_t ws_bytes,
                              bp_stream stream);
 
+/* Float-vector form of the JIT product (Section 5.2's operator on a dense
+ * vector): y (device float[n_post], overwritten) = J^T v, y[k] = sum over
+ * rows j of v[j] * w_jk, for v a device float[n_pre] (16-byte aligned for the
+ * vector loads; any alignment is accepted).  Rows with v[j] == 0 (either
+ * sign) are skipped; NaN and infinities propagate.  The connectivity and
+ * weights are those of bp_jit_conn_matvec for the same descriptor, so on a
+ * 0/1 vector the two agree up to FP32 summation order.  Every product
+ * v[j] * w_jk is rounded to FP32 and summed in FP32 in an unspecified order.
+ * ws: bp_jit_dense_ws_bytes(c) bytes of device scratch (0 when one row chunk
+ * covers the matrix).  Errors: BP_EINVAL on a null y, a null v with
+ * n_pre > 0, a bad descriptor or a short workspace; nothing is launched. */
+size_t bp_jit_dense_ws_bytes(const bp_jit_conn* c);
+bp_status bp_jit_conn_matvec_dense(const bp_jit_conn* c, const float* v, float* y, void* ws, size_t ws_bytes,
+                                   bp_stream stream);
+
 /* Reverse mode: d_events[j] = sum over row j of w_jk dy[k] (every row);
  * d_w (device float[2], nullable) = derivatives with respect to (w0, w1)
  * summed over firing rows: homogeneous (sum dy, 0); normal (sum dy, sum z dy);

@@ -133,6 +133,25 @@ def jit_conn_matvec(conn: JitConn, events, out=None, ws=None):
     return y
 
 
+def jit_conn_matvec_dense(conn: JitConn, v, out=None, ws=None):
+    """y = J^T v for a dense FP32 vector v with J regenerated from the seed
+    (Section 5.2's JIT operator; rows with v[j] == 0 are skipped)."""
+    c = conn.c
+    _dev(v, torch.float32, "v")
+    if v.numel() != c.n_pre or not v.is_contiguous():
+        raise ValueError(f"v must be a contiguous float32 vector of {c.n_pre} entries")
+    y = out if out is not None else torch.empty(c.n_post, dtype=torch.float32, device=v.device)
+    wsb = int(lib().bp_jit_dense_ws_bytes(C.byref(c)))
+    if ws is None or ws.numel() < wsb:
+        ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=v.device)
+    check(lib().bp_jit_conn_matvec_dense(C.byref(c), _p(v), _p(y), _p(ws), wsb, _stream()))
+    return y
+
+
+def jit_dense_ws(conn: JitConn):
+    return int(lib().bp_jit_dense_ws_bytes(C.byref(conn.c)))
+
+
 def jit_ws(conn: JitConn):
     return int(lib().bp_jit_ws_bytes(C.byref(conn.c)))
 

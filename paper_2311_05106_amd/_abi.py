@@ -66,6 +66,8 @@ SIGNATURES = {
     "bp_event_csr_backward": (_i32, [C.POINTER(Csr), _vp, _vp, _vp, _vp, _vp, _vp]),
     "bp_jit_ws_bytes": (_sz, [C.POINTER(JitConn)]),
     "bp_jit_conn_matvec": (_i32, [C.POINTER(JitConn), _vp, _vp, _vp, _sz, _vp]),
+    "bp_jit_dense_ws_bytes": (_sz, [C.POINTER(JitConn)]),
+    "bp_jit_conn_matvec_dense": (_i32, [C.POINTER(JitConn), _vp, _vp, _vp, _sz, _vp]),
     "bp_jit_conn_backward": (_i32, [C.POINTER(JitConn), _vp, _vp, _vp, _vp, _vp]),
     "bp_backward": (_i32, [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "bp_net_bytes": (_i32, [C.POINTER(NetDesc), C.POINTER(_sz)]),

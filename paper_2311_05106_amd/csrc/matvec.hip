@@ -1,5 +1,8 @@
 // Event-driven CSR matvec (Appendix B), JIT-connectivity matvec (Appendix C,
-// Section 5.2) and their reverse modes (Section 4.1).
+// Section 5.2) on spike vectors and on dense float vectors, and their reverse
+// modes (Section 4.1).  The float-vector product lists the rows with
+// v[j] != 0 (64 bytes of v per lane and sweep) in place of the firing rows
+// and scales each generated weight by v[j]; it always sums in FP32.
 //
 // Forward layout: the postsynaptic range is cut into tiles of P columns that
 // fit in LDS, the presynaptic range into C chunks of rows.  Workgroup
@@ -35,7 +38,7 @@ constexpr int kTileMax = 16384;                    // LDS tile columns (64 KB)
 constexpr int kGroup = 16;                         // lanes streaming one CSR segment
 constexpr int kSegLoads = 10;                      // loads per lane and segment pass (160 entries)
 
-enum MvMode { kCsrHomo = 0, kCsrData = 1, kJitHomo = 2, kJitWeighted = 3 };
+enum MvMode { kCsrHomo = 0, kCsrData = 1, kJitHomo = 2, kJitWeighted = 3, kJitVec = 4 };
 
 struct MvArgs {
   const int32_t* indptr;
@@ -43,6 +46,7 @@ struct MvArgs {
   const float* data;
   const int32_t* tile_ptr;  // [n_pre][n_tiles + 1] or null (single tile)
   const uint8_t* events;
+  const float* vec;         // kJitVec: dense input vector (rows with v[j] != 0 are listed)
   void* out;                // y (chunks == 1) or partials [chunks][n_post]
   bp_jit_conn jit;
   float w;
@@ -72,6 +76,26 @@ __device__ __forceinline__ uint32_t spike_bits16(const uint8_t* __restrict__ ev,
   uint32_t b = 0;
   for (int q = 0; q < kRowsPerLane; ++q)
     if (r + q < r_end && ev[r + q]) b |= 1u << q;
+  return b;
+}
+
+// Bit q set iff row r + q < r_end has v[r + q] != 0 (sign bit ignored, so
+// -0 is zero and NaN is not).
+__device__ __forceinline__ uint32_t nonzero_floats16(const float* __restrict__ v, int32_t r, int32_t r_end,
+                                                     bool vec) {
+  uint32_t b = 0;
+  if (vec && r + kRowsPerLane <= r_end) {
+    const uint4* p = reinterpret_cast<const uint4*>(v + r);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint4 x = p[i];
+      b |= (uint32_t)((x.x << 1) != 0u) << (4 * i) | (uint32_t)((x.y << 1) != 0u) << (4 * i + 1) |
+           (uint32_t)((x.z << 1) != 0u) << (4 * i + 2) | (uint32_t)((x.w << 1) != 0u) << (4 * i + 3);
+    }
+    return b;
+  }
+  for (int q = 0; q < kRowsPerLane; ++q)
+    if (r + q < r_end && v[r + q] != 0.f) b |= 1u << q;
   return b;
 }
 
@@ -110,13 +134,16 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
     reinterpret_cast<uint4*>(acc)[i] = make_uint4(0u, 0u, 0u, 0u);
   if (threadIdx.x < 3) sh.cnt[threadIdx.x] = 0;
   __syncthreads();
-  const bool vec = ((reinterpret_cast<uintptr_t>(a.events) | (uintptr_t)r_begin) & 15) == 0;
+  const uintptr_t src = MODE == kJitVec ? reinterpret_cast<uintptr_t>(a.vec) : reinterpret_cast<uintptr_t>(a.events);
+  const bool vec = ((src | (uintptr_t)r_begin) & 15) == 0;
 
   int total = 0;  // listed rows, equal in every lane
   int s = 0;
   for (int32_t r0 = r_begin; r0 < r_end; r0 += kSweep, ++s) {
     const int32_t r = r0 + (int32_t)threadIdx.x * kRowsPerLane;
-    const uint32_t bits = r < r_end ? spike_bits16(a.events, r, r_end, vec) : 0u;
+    uint32_t bits = 0u;
+    if (r < r_end)
+      bits = MODE == kJitVec ? nonzero_floats16(a.vec, r, r_end, vec) : spike_bits16(a.events, r, r_end, vec);
     // the counter of the next sweep was last read before the previous barrier
     if (threadIdx.x == 0) sh.cnt[(s + 1) % 3] = 0;
     append_rows(bits, r, total, &sh.cnt[s % 3], sh.ids);
@@ -225,6 +252,7 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
         const int64_t end = hi;
         const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
         const uint32_t j = act ? (uint32_t)sh.ids[ai] : 0u;
+        const float vj = MODE == kJitVec ? a.vec[j] : 1.f;  // row 0 exists whenever a pass runs
         DrawSeq wd(seed, kStreamW, j, b);
         auto shfl64 = [](int64_t v, int src) {
           const uint32_t lo32 = (uint32_t)__shfl((int)(uint32_t)v, src, kWave);
@@ -258,7 +286,7 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
               atomicAdd(&acc[pos - lo], 1u);
             } else {
               float unit;
-              lds_add_f32(&acc[pos - lo], jit_weight(wd, wkind, w0, w1, 0u, &unit));
+              lds_add_f32(&acc[pos - lo], jit_weight(wd, wkind, w0, w1, 0u, &unit) * vj);
             }
           }
 #pragma unroll
@@ -269,7 +297,7 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
                 atomicAdd(&acc[pos - lo], 1u);
               } else {
                 float unit;
-                lds_add_f32(&acc[pos - lo], jit_weight(wd, wkind, w0, w1, 4u * blk - 1u + (uint32_t)u, &unit));
+                lds_add_f32(&acc[pos - lo], jit_weight(wd, wkind, w0, w1, 4u * blk - 1u + (uint32_t)u, &unit) * vj);
               }
             }
           }
@@ -282,13 +310,14 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
         const int ai = nbt == 1 ? it : it / nbt;
         const uint32_t b = (uint32_t)(b_lo + (nbt == 1 ? 0 : it % nbt));
         const uint32_t j = (uint32_t)sh.ids[ai];
+        const float vj = MODE == kJitVec ? a.vec[j] : 1.f;
         DrawSeq wd(seed, kStreamW, j, b);
         gen_block(seed, K, n_post, B, j, b, lo, hi, [&](int32_t pos, uint32_t m) {
           if constexpr (MODE == kJitHomo) {
             atomicAdd(&acc[pos - lo], 1u);
           } else {
             float unit;
-            lds_add_f32(&acc[pos - lo], jit_weight(wd, wkind, w0, w1, m, &unit));
+            lds_add_f32(&acc[pos - lo], jit_weight(wd, wkind, w0, w1, m, &unit) * vj);
           }
         });
       }
@@ -523,7 +552,8 @@ static MvPlan plan_csr(const bp_csr* m) {
   return p;
 }
 
-static MvPlan plan_jit(const bp_jit_conn* c) {
+// counts: homogeneous weights summed as integer counts (event input only).
+static MvPlan plan_jit(const bp_jit_conn* c, bool counts) {
   MvPlan p{};
   if (c->block > 0 && c->block <= kTileMax && c->n_post > c->block) {
     p.tile = c->block;  // one block per tile: every generated target lands in the tile
@@ -534,7 +564,7 @@ static MvPlan plan_jit(const bp_jit_conn* c) {
   }
   p.n_tiles = (int32_t)(((int64_t)c->n_post + p.tile - 1) / p.tile);
   if (p.n_tiles < 1) p.n_tiles = 1;
-  set_chunks(p, c->n_pre, c->wkind == kWHomo, c->n_post);
+  set_chunks(p, c->n_pre, counts, c->n_post);
   return p;
 }
 
@@ -629,7 +659,7 @@ bp_status bp_event_csr_matvec(const bp_csr* m, const uint8_t* events, float* y, 
 
 size_t bp_jit_ws_bytes(const bp_jit_conn* c) {
   if (!c) return 0;
-  return plan_jit(c).ws;
+  return plan_jit(c, c->wkind == kWHomo).ws;
 }
 
 bp_status bp_jit_conn_matvec(const bp_jit_conn* c, const uint8_t* events, float* y, void* ws, size_t ws_bytes,
@@ -640,9 +670,9 @@ bp_status bp_jit_conn_matvec(const bp_jit_conn* c, const uint8_t* events, float*
   BP_REQUIRE(y != nullptr, "null y");
   BP_REQUIRE(c->n_pre == 0 || events != nullptr, "null events");
   hipStream_t st = as_stream(stream);
-  const MvPlan p = plan_jit(c);
-  BP_REQUIRE(ws_bytes >= p.ws && (p.ws == 0 || ws != nullptr), "workspace too small (%zu < %zu)", ws_bytes, p.ws);
   const bool homo = c->wkind == kWHomo;
+  const MvPlan p = plan_jit(c, homo);
+  BP_REQUIRE(ws_bytes >= p.ws && (p.ws == 0 || ws != nullptr), "workspace too small (%zu < %zu)", ws_bytes, p.ws);
   MvArgs a{};
   a.jit = *c; a.events = events; a.out = p.chunks > 1 ? ws : (void*)y; a.w = c->w0;
   a.n_pre = c->n_pre; a.n_post = c->n_post; a.tile = p.tile; a.n_tiles = p.n_tiles;
@@ -650,6 +680,30 @@ bp_status bp_jit_conn_matvec(const bp_jit_conn* c, const uint8_t* events, float*
   s = homo ? launch_scatter<kJitHomo>(a, p, st) : launch_scatter<kJitWeighted>(a, p, st);
   if (s) return s;
   return finish_partials(p, homo, ws, c->n_post, c->w0, y, st);
+}
+
+size_t bp_jit_dense_ws_bytes(const bp_jit_conn* c) {
+  if (!c) return 0;
+  return plan_jit(c, false).ws;
+}
+
+bp_status bp_jit_conn_matvec_dense(const bp_jit_conn* c, const float* v, float* y, void* ws, size_t ws_bytes,
+                                   bp_stream stream) {
+  bp_status s = check_conn(c, true);
+  if (s) return s;
+  if (c->n_post == 0) return BP_OK;
+  BP_REQUIRE(y != nullptr, "null y");
+  BP_REQUIRE(c->n_pre == 0 || v != nullptr, "null v");
+  hipStream_t st = as_stream(stream);
+  const MvPlan p = plan_jit(c, false);
+  BP_REQUIRE(ws_bytes >= p.ws && (p.ws == 0 || ws != nullptr), "workspace too small (%zu < %zu)", ws_bytes, p.ws);
+  MvArgs a{};
+  a.jit = *c; a.vec = v; a.out = p.chunks > 1 ? ws : (void*)y; a.w = c->w0;
+  a.n_pre = c->n_pre; a.n_post = c->n_post; a.tile = p.tile; a.n_tiles = p.n_tiles;
+  a.chunks = p.chunks; a.chunk_rows = p.chunk_rows;
+  s = launch_scatter<kJitVec>(a, p, st);
+  if (s) return s;
+  return finish_partials(p, false, ws, c->n_post, c->w0, y, st);
 }
 
 bp_status bp_event_csr_backward(const bp_csr* m, const uint8_t* events, const float* dy, float* d_events,

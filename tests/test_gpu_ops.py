@@ -228,6 +228,82 @@ def test_jit_full_operator_size(bp, frac):
     np.testing.assert_array_equal(y.cpu().numpy(), cnt.astype(np.float32) * np.float32(0.5))
 
 
+# ------------------------------------------------- JIT product on a float vector
+_WMAX = {0: lambda w0, w1: abs(w0), 1: lambda w0, w1: abs(w0) + 6 * abs(w1), 2: lambda w0, w1: max(abs(w0), abs(w1))}
+
+
+def _dense_check(bp, n_pre, n_post, K, B, wkind, w0, w1, v, seed, v_dev=None):
+    w0f, w1f = float(np.float32(w0)), float(np.float32(w1))
+    vd = v.astype(np.float64)
+    ref = O.jit_matvec_dense(seed, K, B, wkind, w0f, w1f, n_post, vd)
+    # scale: sum over connected rows of |v_j| times the weight bound
+    absv = O.jit_matvec_dense(seed, K, B, O.W_HOMO, 1.0, 0.0, n_post, np.abs(vd))
+    conn = bp.JitConn(n_pre, n_post, K=K, block=B, seed=seed, wkind=wkind, w0=w0, w1=w1)
+    y = bp.jit_conn_matvec_dense(conn, v_dev if v_dev is not None else _to(v))
+    yg = y.cpu().numpy()
+    _tol_check(yg, ref, absv * _WMAX[wkind](w0f, w1f), name=f"dense wkind={wkind} B={B}")
+    return yg
+
+
+@pytest.mark.parametrize("wkind,w0,w1", [(0, 0.7, 0.0), (1, 0.5, 0.1), (2, -1.0, 2.0)])
+@pytest.mark.parametrize("n_pre,n_post,p,B,zero_frac", [
+    (3000, 20000, 0.01, 512, 0.5),      # blocks of 512 columns, generic lanes
+    (3000, 20000, 0.01, 512, 0.97),     # few rows per pass: quad lanes
+    (3000, 20000, 0.01, 0, 0.3),        # two tiles, whole-row regeneration
+    (50000, 3000, 0.02, 256, 0.0),      # many row chunks, FP32 partials
+    (3001, 9001, 0.05, 1000, 0.2),      # ragged rows, columns and last block
+])
+def test_jit_dense_vector(bp, wkind, w0, w1, n_pre, n_post, p, B, zero_frac):
+    v = S.dense_vector(n_pre, 21, zero_frac=zero_frac)
+    _dense_check(bp, n_pre, n_post, O.max_gap(p), B, wkind, w0, w1, v, seed=17)
+
+
+def test_jit_dense_vector_edge_cases(bp):
+    n_pre, n_post, K, B = 2000, 5000, O.max_gap(0.02), 512
+    # misaligned input (16-byte vector loads off): a view starting one float in
+    big = S.dense_vector(n_pre + 1, 3, zero_frac=0.4)
+    vt = _to(big)[1:]
+    assert vt.data_ptr() % 16 != 0
+    _dense_check(bp, n_pre, n_post, K, B, 1, 0.5, 0.1, big[1:], seed=5, v_dev=vt)
+    # all zeros (either sign) give exact zeros; NaN propagates to its targets only
+    conn = bp.JitConn(n_pre, n_post, K=K, block=B, seed=5, wkind=1, w0=0.5, w1=0.1)
+    z = np.zeros(n_pre, np.float32)
+    z[::3] = -0.0
+    assert not bp.jit_conn_matvec_dense(conn, _to(z)).cpu().numpy().any()
+    nan = np.zeros(n_pre, np.float32)
+    nan[7] = np.nan
+    yn = bp.jit_conn_matvec_dense(conn, _to(nan)).cpu().numpy()
+    e = np.zeros(n_pre, np.uint8)
+    e[7] = 1
+    hit = O.jit_counts(5, K, B, n_post, e) > 0
+    assert np.all(np.isnan(yn[hit])) and np.all(yn[~hit] == 0.0)
+    # one row: y is that row's weights times v[j]
+    one = np.zeros(n_pre, np.float32)
+    one[1999] = 2.5
+    _dense_check(bp, n_pre, n_post, K, B, 2, -1.0, 2.0, one, seed=5)
+    # no rows; then 1 and 17 rows (below and above one 16-row load)
+    conn0 = bp.JitConn(0, n_post, K=K, block=B, seed=5, w0=0.5)
+    assert not bp.jit_conn_matvec_dense(conn0, torch.zeros(0, device=dev)).cpu().numpy().any()
+    for n in (1, 17):
+        _dense_check(bp, n, n_post, K, B, 0, 0.5, 0.0, S.dense_vector(n, 4), seed=5)
+
+
+def test_jit_dense_vector_wrong_input_rejected(bp):
+    conn = bp.JitConn(100, 200, K=O.max_gap(0.1), block=0, seed=1, w0=0.5)
+    with pytest.raises(TypeError):
+        bp.jit_conn_matvec_dense(conn, torch.zeros(100, dtype=torch.uint8, device=dev))
+    with pytest.raises(ValueError):
+        bp.jit_conn_matvec_dense(conn, torch.zeros(99, device=dev))
+
+
+@pytest.mark.parametrize("wkind,w0,w1,zero_frac", [(2, -1.0, 2.0, 0.0), (1, 0.5, 0.1, 0.9)])
+def test_jit_dense_vector_full_operator_size(bp, wkind, w0, w1, zero_frac):
+    # the benchmark's operator: 1e5 x 1e5, p = 0.01, blocks of 1024 columns
+    n = 100_000
+    v = S.dense_vector(n, 9, zero_frac=zero_frac)
+    _dense_check(bp, n, n, O.max_gap(0.01), 1024, wkind, w0, w1, v, seed=0)
+
+
 # ------------------------------------------------------------------ reverse mode
 def test_event_csr_backward(bp):
     n_pre, n_post = 6000, 5000
