@@ -82,6 +82,8 @@ def lib():
         L.or_jit_matvec.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                     C.c_int32, C.c_int32, _u8p, _f64p]
         L.or_jit_counts.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _u8p, _i64p]
+        L.or_jit_matmat_dense.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                          C.c_int32, C.c_int32, C.c_int32, _f64p, _f64p]
         L.or_jit_matvec_dense.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                           C.c_int32, C.c_int32, _f64p, _f64p]
         L.or_jit_vjp.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
@@ -224,6 +226,15 @@ def jit_matvec_dense(seed, K, B, wkind, w0, w1, n_post, v):
     y = np.empty(n_post, np.float64)
     lib().or_jit_matvec_dense(seed, K, B, wkind, float(w0), float(w1), vv.shape[0], n_post, vv, y)
     return y
+
+
+def jit_matmat_dense(seed, K, B, wkind, w0, w1, n_post, X):
+    """Y = J^T X for X [n_pre, m] (m float vectors at once); FP64."""
+    XX = np.ascontiguousarray(X, np.float64)
+    Y = np.empty((n_post, XX.shape[1]), np.float64)
+    lib().or_jit_matmat_dense(seed, K, B, wkind, float(w0), float(w1), XX.shape[0], n_post, XX.shape[1],
+                              XX.reshape(-1), Y.reshape(-1))
+    return Y
 
 
 def jit_counts(seed, K, B, n_post, events):

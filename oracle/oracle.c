@@ -337,6 +337,28 @@ void or_jit_matvec_dense(uint64_t seed, int32_t K, int32_t B, int32_t wkind, dou
   free(buf);
 }
 
+/* Batched form (Section 5.2's operator on m vectors at once): Y = J^T X with
+ * X row-major [n_pre][m] and Y row-major [n_post][m]; column c of Y is the
+ * float-vector product of column c of X, each in the same row order. */
+void or_jit_matmat_dense(uint64_t seed, int32_t K, int32_t B, int32_t wkind, double w0, double w1,
+                         int32_t n_pre, int32_t n_post, int32_t m, const double* X, double* Y) {
+  int32_t* buf = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_post > 0 ? n_post : 1));
+  int32_t nb = n_blocks(n_post, B);
+  for (int64_t i = 0; i < (int64_t)n_post * m; ++i) Y[i] = 0.0;
+  for (int32_t j = 0; j < n_pre; ++j) {
+    const double* x = X + (size_t)j * m;
+    for (int32_t b = 0; b < nb; ++b) {
+      int64_t cnt = or_row_block(seed, K, n_post, B, j, b, buf);
+      for (int64_t t = 0; t < cnt; ++t) {
+        const double w = or_jit_weight(seed, wkind, w0, w1, j, b, t, NULL);
+        for (int32_t c = 0; c < m; ++c)
+          if (x[c] != 0.0) Y[(size_t)buf[t] * m + c] += w * x[c];
+      }
+    }
+  }
+  free(buf);
+}
+
 void or_jit_counts(uint64_t seed, int32_t K, int32_t B, int32_t n_pre, int32_t n_post,
                    const uint8_t* ev, int64_t* cnt) {
   int32_t* buf = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_post > 0 ? n_post : 1));

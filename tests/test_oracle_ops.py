@@ -142,6 +142,26 @@ def test_jit_dense_vector_special_cases(B):
     assert not O.jit_matvec_dense(seed, K, B, O.W_NORMAL, 0.5, 0.1, n_post, np.zeros(n_pre)).any()
 
 
+@pytest.mark.parametrize("wkind", [O.W_HOMO, O.W_NORMAL, O.W_UNIFORM])
+def test_jit_dense_matrix_bruteforce(wkind):
+    # m vectors at once: Y = D^T X with D assembled entry by entry (numpy
+    # product), and column c of Y equal to the single-vector product of
+    # column c of X (same row order, so exactly).
+    seed, K, n_pre, n_post, B, m = 8, 7, 45, 70, 16, 5
+    w0, w1 = {O.W_HOMO: (0.3, 0.0), O.W_NORMAL: (0.5, 0.1), O.W_UNIFORM: (-1.0, 2.0)}[wkind]
+    D = np.zeros((n_pre, n_post))
+    for j in range(n_pre):
+        for b in range(-(-n_post // B)):
+            for t, k in enumerate(O.row_block(seed, K, n_post, B, j, b)):
+                D[j, k] += O.jit_weight(seed, wkind, w0, w1, j, b, t)[0]
+    X = np.stack([S.dense_vector(n_pre, 40 + c, zero_frac=0.3) for c in range(m)], 1).astype(np.float64)
+    X[3] = 0.0
+    Y = O.jit_matmat_dense(seed, K, B, wkind, w0, w1, n_post, X)
+    np.testing.assert_allclose(Y, D.T @ X, rtol=1e-12, atol=1e-12)
+    for c in range(m):
+        np.testing.assert_array_equal(Y[:, c], O.jit_matvec_dense(seed, K, B, wkind, w0, w1, n_post, X[:, c]))
+
+
 def test_jit_normal_weights_are_normal():
     z = np.array([O.jit_weight(3, O.W_NORMAL, 0.0, 1.0, j, 0, m)[1] for j in range(400) for m in range(50)])
     assert abs(z.mean()) < 5 / math.sqrt(z.size)
