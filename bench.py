@@ -214,7 +214,9 @@ def bench_dense(bp, torch, calls=640):
     """JIT product on dense float vectors (Section 5.2's operator y = J^T v):
     n_pre = n_post = 1e5, p = 0.01, blocks of JIT_OP_BLOCK columns, v ~ N(0, 1)
     with no zeros (every row contributes); `calls` products cycling 8
-    vectors, replayed from a HIP graph."""
+    vectors, replayed from a HIP graph; then the batched product on 8 vectors
+    at once (4 distinct X, calls / 8 products)."""
+    import numpy as np
     import synthetic as S
     n, K = 100_000, bp.max_gap(0.01)
     dev = "cuda"
@@ -253,6 +255,40 @@ def bench_dense(bp, torch, calls=640):
         gbs = 8.0 * nnz / (us * 1e-6) / 1e9
         out.append(dict(op=f"jit_dense_{name}", us_per_call=us, synapses=nnz, synapses_per_s=nnz / (us * 1e-6),
                         csr_equiv_GBps=gbs, csr_equiv_frac=gbs / HBM_PEAK_GBS))
+        del g
+    # batched: 8 vectors per product (X [n, 8] row-major), each row generated once per column group
+    m = 8
+    Xs = [torch.from_numpy(np.ascontiguousarray(np.stack([S.dense_vector(n, 60 + 8 * i + c) for c in range(m)], 1)))
+          .to(dev) for i in range(4)]
+    Y = torch.empty((n, m), dtype=torch.float32, device=dev)
+    for name, wk, w0, w1 in [("uniform", bp.W_UNIFORM, -1.0, 1.0), ("normal", bp.W_NORMAL, 0.5, 0.1)]:
+        conn = bp.JitConn(n, n, K=K, block=JIT_OP_BLOCK, seed=0, wkind=wk, w0=w0, w1=w1)
+        ws = torch.empty(max(bp.jit_matmat_ws(conn, m), 1), dtype=torch.uint8, device=dev)
+        ip, _ = bp.csr_build(conn)
+        nnz = float(ip[-1].item())
+        fn = lambda X: bp.jit_conn_matmat_dense(conn, X, out=Y, ws=ws)
+        for X in Xs:
+            fn(X)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                for X in Xs:
+                    fn(X)
+        torch.cuda.synchronize()
+        reps = max(1, calls // 32)
+        g.replay()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            g.replay()
+        b.record()
+        torch.cuda.synchronize()
+        us = a.elapsed_time(b) * 1e3 / (reps * 4)
+        out.append(dict(op=f"jit_dense_matmat{m}_{name}", us_per_call=us, synapses=nnz, columns=m,
+                        synapse_columns_per_s=nnz * m / (us * 1e-6)))
         del g
     return out
 

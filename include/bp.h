@@ -189,6 +189,19 @@ size_t bp_jit_dense_ws_bytes(const bp_jit_conn* c);
 bp_status bp_jit_conn_matvec_dense(const bp_jit_conn* c, const float* v, float* y, void* ws, size_t ws_bytes,
                                    bp_stream stream);
 
+/* Batched float-vector JIT product (Section 5.2's operator on m vectors at
+ * once): Y = J^T X with X a device float[n_pre][m] and Y a device
+ * float[n_post][m] (both row-major, Y overwritten); column c of Y is
+ * bp_jit_conn_matvec_dense of column c of X up to FP32 summation order.
+ * Every row is used (zero entries add zero); up to 8 columns of X share one
+ * generation of each row.  n_post * m must fit in int32.  ws:
+ * bp_jit_matmat_ws_bytes(c, m) bytes of device scratch.  Errors: BP_EINVAL
+ * on a null Y, a null X with n_pre > 0, m < 0, a bad descriptor or a short
+ * workspace; m == 0 launches nothing. */
+size_t bp_jit_matmat_ws_bytes(const bp_jit_conn* c, int32_t m);
+bp_status bp_jit_conn_matmat_dense(const bp_jit_conn* c, const float* X, int32_t m, float* Y, void* ws,
+                                   size_t ws_bytes, bp_stream stream);
+
 /* Reverse mode: d_events[j] = sum over row j of w_jk dy[k] (every row);
  * d_w (device float[2], nullable) = derivatives with respect to (w0, w1)
  * summed over firing rows: homogeneous (sum dy, 0); normal (sum dy, sum z dy);

@@ -16,7 +16,7 @@ from ._abi import (COBA, CONN_CSR, CONN_JIT, CUBA, STREAM_CONN, STREAM_V0, STREA
 
 __all__ = [
     "lib", "BpError", "max_gap", "hash_words", "csr_build", "csr_tile_index", "compact", "event_csr_matvec",
-    "jit_conn_matvec", "event_csr_backward", "jit_conn_backward", "Net", "run_batch", "JitConn",
+    "jit_conn_matvec", "jit_conn_matvec_dense", "jit_conn_matmat_dense", "event_csr_backward", "jit_conn_backward", "Net", "run_batch", "JitConn",
     "COBA", "CUBA", "CONN_CSR", "CONN_JIT", "W_HOMO", "W_NORMAL", "W_UNIFORM",
 ]
 
@@ -146,6 +146,26 @@ def jit_conn_matvec_dense(conn: JitConn, v, out=None, ws=None):
         ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=v.device)
     check(lib().bp_jit_conn_matvec_dense(C.byref(c), _p(v), _p(y), _p(ws), wsb, _stream()))
     return y
+
+
+def jit_conn_matmat_dense(conn: JitConn, X, out=None, ws=None):
+    """Y = J^T X for a contiguous FP32 matrix X [n_pre, m] (m float vectors
+    at once); Y is [n_post, m]."""
+    c = conn.c
+    _dev(X, torch.float32, "X")
+    if X.dim() != 2 or X.shape[0] != c.n_pre or not X.is_contiguous():
+        raise ValueError(f"X must be a contiguous float32 matrix with {c.n_pre} rows")
+    m = int(X.shape[1])
+    Y = out if out is not None else torch.empty((c.n_post, m), dtype=torch.float32, device=X.device)
+    wsb = int(lib().bp_jit_matmat_ws_bytes(C.byref(c), m))
+    if ws is None or ws.numel() < wsb:
+        ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=X.device)
+    check(lib().bp_jit_conn_matmat_dense(C.byref(c), _p(X), m, _p(Y), _p(ws), wsb, _stream()))
+    return Y
+
+
+def jit_matmat_ws(conn: JitConn, m):
+    return int(lib().bp_jit_matmat_ws_bytes(C.byref(conn.c), m))
 
 
 def jit_dense_ws(conn: JitConn):

@@ -68,6 +68,8 @@ SIGNATURES = {
     "bp_jit_conn_matvec": (_i32, [C.POINTER(JitConn), _vp, _vp, _vp, _sz, _vp]),
     "bp_jit_dense_ws_bytes": (_sz, [C.POINTER(JitConn)]),
     "bp_jit_conn_matvec_dense": (_i32, [C.POINTER(JitConn), _vp, _vp, _vp, _sz, _vp]),
+    "bp_jit_matmat_ws_bytes": (_sz, [C.POINTER(JitConn), _i32]),
+    "bp_jit_conn_matmat_dense": (_i32, [C.POINTER(JitConn), _vp, _i32, _vp, _vp, _sz, _vp]),
     "bp_jit_conn_backward": (_i32, [C.POINTER(JitConn), _vp, _vp, _vp, _vp, _vp]),
     "bp_backward": (_i32, [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "bp_net_bytes": (_i32, [C.POINTER(NetDesc), C.POINTER(_sz)]),

@@ -38,7 +38,8 @@ constexpr int kTileMax = 16384;                    // LDS tile columns (64 KB)
 constexpr int kGroup = 16;                         // lanes streaming one CSR segment
 constexpr int kSegLoads = 10;                      // loads per lane and segment pass (160 entries)
 
-enum MvMode { kCsrHomo = 0, kCsrData = 1, kJitHomo = 2, kJitWeighted = 3, kJitVec = 4 };
+enum MvMode { kCsrHomo = 0, kCsrData = 1, kJitHomo = 2, kJitWeighted = 3, kJitVec = 4, kJitMat = 5 };
+constexpr int kMatCols = 8;  // kJitMat: columns of X per workgroup (blockIdx.y = column group)
 
 struct MvArgs {
   const int32_t* indptr;
@@ -47,6 +48,8 @@ struct MvArgs {
   const int32_t* tile_ptr;  // [n_pre][n_tiles + 1] or null (single tile)
   const uint8_t* events;
   const float* vec;         // kJitVec: dense input vector (rows with v[j] != 0 are listed)
+  const float* x;           // kJitMat: X row-major [n_pre][m] (every row is listed)
+  int32_t m, mg;            // kJitMat: columns of X, columns per group
   void* out;                // y (chunks == 1) or partials [chunks][n_post]
   bp_jit_conn jit;
   float w;
@@ -118,6 +121,34 @@ __device__ __forceinline__ void append_rows(uint32_t bits, int32_t r, int total,
   }
 }
 
+// The factor(s) of one listed row: v[j] for kJitVec, X[j][c0 .. c0 + mg)
+// for kJitMat (clamped loads, masked adds), 1 for kJitWeighted.
+template <int MODE>
+struct RowScale {
+  float v[MODE == kJitMat ? kMatCols : 1];
+  __device__ __forceinline__ void load(const MvArgs& a, uint32_t j, int c0, int mg) {
+    if constexpr (MODE == kJitMat) {
+      const float* row = a.x + (size_t)j * a.m + c0;
+#pragma unroll
+      for (int cc = 0; cc < kMatCols; ++cc) v[cc] = row[cc < mg ? cc : mg - 1];
+    } else if constexpr (MODE == kJitVec) {
+      v[0] = a.vec[j];
+    } else {
+      v[0] = 1.f;
+    }
+  }
+  // acc holds mg floats per column of the tile (one for the other modes)
+  __device__ __forceinline__ void add(float* acc, int off, float w, int mg) const {
+    if constexpr (MODE == kJitMat) {
+#pragma unroll
+      for (int cc = 0; cc < kMatCols; ++cc)
+        if (cc < mg) lds_add_f32(&acc[off * mg + cc], w * v[cc]);
+    } else {
+      lds_add_f32(&acc[off], w * v[0]);
+    }
+  }
+};
+
 template <int MODE>
 __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
   using Acc = typename std::conditional<(MODE == kCsrHomo || MODE == kJitHomo), uint32_t, float>::type;
@@ -130,7 +161,9 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
   const int32_t width = hi - lo;
   const int32_t r_begin = c * a.chunk_rows;
   const int32_t r_end = min(r_begin + a.chunk_rows, a.n_pre);
-  for (int i = threadIdx.x; i < (width + 3) / 4; i += kMvThreads)  // kTileMax is a multiple of 4
+  const int c0 = MODE == kJitMat ? (int)blockIdx.y * a.mg : 0;
+  const int mg = MODE == kJitMat ? min(a.mg, a.m - c0) : 1;  // width * mg <= kTileMax (host plan)
+  for (int i = threadIdx.x; i < (width * mg + 3) / 4; i += kMvThreads)  // kTileMax is a multiple of 4
     reinterpret_cast<uint4*>(acc)[i] = make_uint4(0u, 0u, 0u, 0u);
   if (threadIdx.x < 3) sh.cnt[threadIdx.x] = 0;
   __syncthreads();
@@ -142,8 +175,11 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
   for (int32_t r0 = r_begin; r0 < r_end; r0 += kSweep, ++s) {
     const int32_t r = r0 + (int32_t)threadIdx.x * kRowsPerLane;
     uint32_t bits = 0u;
-    if (r < r_end)
-      bits = MODE == kJitVec ? nonzero_floats16(a.vec, r, r_end, vec) : spike_bits16(a.events, r, r_end, vec);
+    if (r < r_end) {
+      if constexpr (MODE == kJitMat) bits = r + kRowsPerLane <= r_end ? 0xFFFFu : (1u << (r_end - r)) - 1u;
+      else if constexpr (MODE == kJitVec) bits = nonzero_floats16(a.vec, r, r_end, vec);
+      else bits = spike_bits16(a.events, r, r_end, vec);
+    }
     // the counter of the next sweep was last read before the previous barrier
     if (threadIdx.x == 0) sh.cnt[(s + 1) % 3] = 0;
     append_rows(bits, r, total, &sh.cnt[s % 3], sh.ids);
@@ -252,7 +288,8 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
         const int64_t end = hi;
         const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
         const uint32_t j = act ? (uint32_t)sh.ids[ai] : 0u;
-        const float vj = MODE == kJitVec ? a.vec[j] : 1.f;  // row 0 exists whenever a pass runs
+        RowScale<MODE> sc;
+        sc.load(a, j, c0, mg);  // row 0 exists whenever a pass runs
         DrawSeq wd(seed, kStreamW, j, b);
         auto shfl64 = [](int64_t v, int src) {
           const uint32_t lo32 = (uint32_t)__shfl((int)(uint32_t)v, src, kWave);
@@ -286,7 +323,7 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
               atomicAdd(&acc[pos - lo], 1u);
             } else {
               float unit;
-              lds_add_f32(&acc[pos - lo], jit_weight(wd, wkind, w0, w1, 0u, &unit) * vj);
+              sc.add(acc, (int)(pos - lo), jit_weight(wd, wkind, w0, w1, 0u, &unit), mg);
             }
           }
 #pragma unroll
@@ -297,7 +334,7 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
                 atomicAdd(&acc[pos - lo], 1u);
               } else {
                 float unit;
-                lds_add_f32(&acc[pos - lo], jit_weight(wd, wkind, w0, w1, 4u * blk - 1u + (uint32_t)u, &unit) * vj);
+                sc.add(acc, (int)(pos - lo), jit_weight(wd, wkind, w0, w1, 4u * blk - 1u + (uint32_t)u, &unit), mg);
               }
             }
           }
@@ -310,14 +347,15 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
         const int ai = nbt == 1 ? it : it / nbt;
         const uint32_t b = (uint32_t)(b_lo + (nbt == 1 ? 0 : it % nbt));
         const uint32_t j = (uint32_t)sh.ids[ai];
-        const float vj = MODE == kJitVec ? a.vec[j] : 1.f;
+        RowScale<MODE> sc;
+        sc.load(a, j, c0, mg);
         DrawSeq wd(seed, kStreamW, j, b);
         gen_block(seed, K, n_post, B, j, b, lo, hi, [&](int32_t pos, uint32_t m) {
           if constexpr (MODE == kJitHomo) {
             atomicAdd(&acc[pos - lo], 1u);
           } else {
             float unit;
-            lds_add_f32(&acc[pos - lo], jit_weight(wd, wkind, w0, w1, m, &unit) * vj);
+            sc.add(acc, pos - lo, jit_weight(wd, wkind, w0, w1, m, &unit), mg);
           }
         });
       }
@@ -326,6 +364,15 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
     total = 0;
   }
   __syncthreads();
+  if constexpr (MODE == kJitMat) {
+    // acc[i * mg + cc] is Y[lo + i][c0 + cc]; Y (or the chunk's partial) is [n_post][m]
+    float* dst = reinterpret_cast<float*>(a.out) + (size_t)c * a.n_post * a.m;
+    for (int i2 = threadIdx.x; i2 < width * mg; i2 += kMvThreads) {
+      const int i = i2 / mg, cc = i2 - i * mg;
+      dst[(size_t)(lo + i) * a.m + c0 + cc] = acc[i2];
+    }
+    return;
+  }
   if (a.chunks == 1) {
     float* y = reinterpret_cast<float*>(a.out);
     for (int i = threadIdx.x; i < width; i += kMvThreads) {
@@ -568,6 +615,21 @@ static MvPlan plan_jit(const bp_jit_conn* c, bool counts) {
   return p;
 }
 
+// Batched product: the single-vector plan, kMatCols columns of X per
+// workgroup while the LDS tile holds them (tile * mg <= kTileMax), column
+// groups on blockIdx.y, row chunks sized for tiles x groups workgroups.
+static MvPlan plan_jit_mat(const bp_jit_conn* c, int32_t m, int32_t* mg, int32_t* groups) {
+  MvPlan p = plan_jit(c, false);
+  *mg = max(1, min(min(kMatCols, kTileMax / p.tile), m));
+  *groups = (m + *mg - 1) / *mg;
+  const int32_t nt = p.n_tiles;
+  p.n_tiles = nt * *groups;
+  set_chunks(p, c->n_pre, false, c->n_post);
+  p.n_tiles = nt;
+  p.ws = p.chunks > 1 ? (size_t)p.chunks * c->n_post * m * sizeof(float) : 0;
+  return p;
+}
+
 static bp_status check_csr(const bp_csr* m) {
   BP_REQUIRE(m != nullptr, "null CSR descriptor");
   BP_REQUIRE(m->n_pre >= 0 && m->n_post >= 0, "negative size");
@@ -704,6 +766,37 @@ bp_status bp_jit_conn_matvec_dense(const bp_jit_conn* c, const float* v, float* 
   s = launch_scatter<kJitVec>(a, p, st);
   if (s) return s;
   return finish_partials(p, false, ws, c->n_post, c->w0, y, st);
+}
+
+size_t bp_jit_matmat_ws_bytes(const bp_jit_conn* c, int32_t m) {
+  if (!c || m <= 0) return 0;
+  int32_t mg, groups;
+  return plan_jit_mat(c, m, &mg, &groups).ws;
+}
+
+bp_status bp_jit_conn_matmat_dense(const bp_jit_conn* c, const float* X, int32_t m, float* Y, void* ws,
+                                   size_t ws_bytes, bp_stream stream) {
+  bp_status s = check_conn(c, true);
+  if (s) return s;
+  BP_REQUIRE(m >= 0, "negative m");
+  if (c->n_post == 0 || m == 0) return BP_OK;
+  BP_REQUIRE((int64_t)c->n_post * m <= INT32_MAX, "n_post * m exceeds 2^31 - 1");
+  BP_REQUIRE(Y != nullptr, "null Y");
+  BP_REQUIRE(c->n_pre == 0 || X != nullptr, "null X");
+  hipStream_t st = as_stream(stream);
+  int32_t mg, groups;
+  const MvPlan p = plan_jit_mat(c, m, &mg, &groups);
+  BP_REQUIRE(groups <= 65535, "too many column groups (%d)", groups);
+  BP_REQUIRE(ws_bytes >= p.ws && (p.ws == 0 || ws != nullptr), "workspace too small (%zu < %zu)", ws_bytes, p.ws);
+  MvArgs a{};
+  a.jit = *c; a.x = X; a.m = m; a.mg = mg; a.out = p.chunks > 1 ? ws : (void*)Y;
+  a.n_pre = c->n_pre; a.n_post = c->n_post; a.tile = p.tile; a.n_tiles = p.n_tiles;
+  a.chunks = p.chunks; a.chunk_rows = p.chunk_rows;
+  mv_scatter_k<kJitMat><<<dim3(p.n_tiles * p.chunks, groups), kMvThreads, 0, st>>>(a);
+  BP_LAUNCHED("mv_scatter_k");
+  MvPlan flat = p;  // the partials are [chunk][n_post * m]: tiles of tile * m floats
+  flat.tile = p.tile * m;
+  return finish_partials(flat, false, ws, c->n_post * m, c->w0, Y, st);
 }
 
 bp_status bp_event_csr_backward(const bp_csr* m, const uint8_t* events, const float* dy, float* d_events,

@@ -304,6 +304,68 @@ def test_jit_dense_vector_full_operator_size(bp, wkind, w0, w1, zero_frac):
     _dense_check(bp, n, n, O.max_gap(0.01), 1024, wkind, w0, w1, v, seed=0)
 
 
+def _mat_check(bp, n_pre, n_post, K, B, wkind, w0, w1, X, seed):
+    w0f, w1f = float(np.float32(w0)), float(np.float32(w1))
+    Xd = X.astype(np.float64)
+    ref = O.jit_matmat_dense(seed, K, B, wkind, w0f, w1f, n_post, Xd)
+    absx = O.jit_matmat_dense(seed, K, B, O.W_HOMO, 1.0, 0.0, n_post, np.abs(Xd))
+    conn = bp.JitConn(n_pre, n_post, K=K, block=B, seed=seed, wkind=wkind, w0=w0, w1=w1)
+    Y = bp.jit_conn_matmat_dense(conn, _to(X)).cpu().numpy()
+    assert Y.shape == (n_post, X.shape[1])
+    _tol_check(Y.reshape(-1), ref.reshape(-1), absx.reshape(-1) * _WMAX[wkind](w0f, w1f),
+               name=f"matmat wkind={wkind} B={B} m={X.shape[1]}")
+    return Y, conn
+
+
+def _mat(n_pre, m, seed, zero_frac=0.0):
+    return np.ascontiguousarray(np.stack([S.dense_vector(n_pre, seed + c, zero_frac) for c in range(m)], 1))
+
+
+@pytest.mark.parametrize("wkind,w0,w1", [(0, 0.7, 0.0), (1, 0.5, 0.1), (2, -1.0, 2.0)])
+@pytest.mark.parametrize("n_pre,n_post,p,B,m", [
+    (3000, 20000, 0.01, 512, 8),      # one column group, generic lanes
+    (3000, 20000, 0.01, 512, 13),     # two groups, the second ragged
+    (200, 20000, 0.01, 512, 3),       # few rows per pass: quad lanes
+    (3000, 20000, 0.01, 0, 3),        # whole rows, tile of 16384: one column per group
+    (50000, 3000, 0.02, 256, 5),      # row chunks, partials reduced as [n_post * m]
+    (3001, 9001, 0.05, 1000, 1),      # ragged sizes, one column
+])
+def test_jit_dense_matrix(bp, wkind, w0, w1, n_pre, n_post, p, B, m):
+    X = _mat(n_pre, m, 50, zero_frac=0.2)
+    Y, conn = _mat_check(bp, n_pre, n_post, O.max_gap(p), B, wkind, w0, w1, X, seed=19)
+    # column c agrees with the single-vector product of column c
+    for c in (0, m - 1):
+        yc = bp.jit_conn_matvec_dense(conn, _to(np.ascontiguousarray(X[:, c]))).cpu().numpy()
+        absx = O.jit_matvec_dense(19, O.max_gap(p), B, O.W_HOMO, 1.0, 0.0, n_post, np.abs(X[:, c]).astype(np.float64))
+        _tol_check(yc, Y[:, c].astype(np.float64), 2 * absx * _WMAX[wkind](float(np.float32(w0)), float(np.float32(w1))))
+
+
+def test_jit_dense_matrix_edge_cases(bp):
+    n_pre, n_post, K, B = 500, 3000, O.max_gap(0.02), 512
+    conn = bp.JitConn(n_pre, n_post, K=K, block=B, seed=3, wkind=1, w0=0.5, w1=0.1)
+    assert bp.jit_conn_matmat_dense(conn, torch.zeros((n_pre, 0), device=dev)).shape == (n_post, 0)
+    assert not bp.jit_conn_matmat_dense(conn, torch.zeros((n_pre, 4), device=dev)).cpu().numpy().any()
+    conn0 = bp.JitConn(0, n_post, K=K, block=B, seed=3, w0=0.5)
+    assert not bp.jit_conn_matmat_dense(conn0, torch.zeros((0, 6), device=dev)).cpu().numpy().any()
+    with pytest.raises(ValueError):
+        bp.jit_conn_matmat_dense(conn, torch.zeros((n_pre, 4), device=dev).t())
+    # two calls in a row on one workspace, the second with fewer columns
+    ws = torch.empty(max(bp.jit_matmat_ws(conn, 9), 1), dtype=torch.uint8, device=dev)
+    for m in (9, 2):
+        X = _mat(n_pre, m, 70)
+        Y = bp.jit_conn_matmat_dense(conn, _to(X), ws=ws).cpu().numpy()
+        ref = O.jit_matmat_dense(3, K, B, 1, float(np.float32(0.5)), float(np.float32(0.1)), n_post, X.astype(np.float64))
+        absx = O.jit_matmat_dense(3, K, B, 0, 1.0, 0.0, n_post, np.abs(X).astype(np.float64))
+        _tol_check(Y.reshape(-1), ref.reshape(-1), absx.reshape(-1) * (0.5 + 0.6))
+
+
+def test_jit_dense_matrix_full_operator_size(bp):
+    # the benchmark's operator with 8 vectors: 1e5 x 1e5, p = 0.01, blocks of 782
+    n = 100_000
+    X = _mat(n, 8, 80, zero_frac=0.9)
+    _mat_check(bp, n, n, O.max_gap(0.01), 782, 2, -1.0, 1.0, X, seed=0)
+
+
 # ------------------------------------------------------------------ reverse mode
 def test_event_csr_backward(bp):
     n_pre, n_post = 6000, 5000
