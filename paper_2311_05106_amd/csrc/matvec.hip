@@ -137,12 +137,14 @@ struct RowScale {
       v[0] = 1.f;
     }
   }
-  // acc holds mg floats per column of the tile (one for the other modes)
-  __device__ __forceinline__ void add(float* acc, int off, float w, int mg) const {
+  // kJitMat: acc holds column cc of the group at acc[cc * width .. + width)
+  // (column-major, so the lanes of one add hit banks spread by their random
+  // offsets; a row-major [width][8] tile put all 64 on 4 of the banks)
+  __device__ __forceinline__ void add(float* acc, int off, float w, int mg, int width) const {
     if constexpr (MODE == kJitMat) {
 #pragma unroll
       for (int cc = 0; cc < kMatCols; ++cc)
-        if (cc < mg) lds_add_f32(&acc[off * mg + cc], w * v[cc]);
+        if (cc < mg) lds_add_f32(&acc[cc * width + off], w * v[cc]);
     } else {
       lds_add_f32(&acc[off], w * v[0]);
     }
@@ -323,7 +325,7 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
               atomicAdd(&acc[pos - lo], 1u);
             } else {
               float unit;
-              sc.add(acc, (int)(pos - lo), jit_weight(wd, wkind, w0, w1, 0u, &unit), mg);
+              sc.add(acc, (int)(pos - lo), jit_weight(wd, wkind, w0, w1, 0u, &unit), mg, width);
             }
           }
 #pragma unroll
@@ -334,7 +336,7 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
                 atomicAdd(&acc[pos - lo], 1u);
               } else {
                 float unit;
-                sc.add(acc, (int)(pos - lo), jit_weight(wd, wkind, w0, w1, 4u * blk - 1u + (uint32_t)u, &unit), mg);
+                sc.add(acc, (int)(pos - lo), jit_weight(wd, wkind, w0, w1, 4u * blk - 1u + (uint32_t)u, &unit), mg, width);
               }
             }
           }
@@ -355,7 +357,7 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
             atomicAdd(&acc[pos - lo], 1u);
           } else {
             float unit;
-            sc.add(acc, pos - lo, jit_weight(wd, wkind, w0, w1, m, &unit), mg);
+            sc.add(acc, pos - lo, jit_weight(wd, wkind, w0, w1, m, &unit), mg, width);
           }
         });
       }
@@ -365,11 +367,11 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
   }
   __syncthreads();
   if constexpr (MODE == kJitMat) {
-    // acc[i * mg + cc] is Y[lo + i][c0 + cc]; Y (or the chunk's partial) is [n_post][m]
+    // acc[cc * width + i] is Y[lo + i][c0 + cc]; Y (or the chunk's partial) is [n_post][m]
     float* dst = reinterpret_cast<float*>(a.out) + (size_t)c * a.n_post * a.m;
     for (int i2 = threadIdx.x; i2 < width * mg; i2 += kMvThreads) {
       const int i = i2 / mg, cc = i2 - i * mg;
-      dst[(size_t)(lo + i) * a.m + c0 + cc] = acc[i2];
+      dst[(size_t)(lo + i) * a.m + c0 + cc] = acc[cc * width + i];
     }
     return;
   }
