@@ -7,7 +7,7 @@ import torch
 
 from . import _abi
 from . import JitConn, _p, _stream, check, event_csr_backward, event_csr_matvec, jit_conn_backward, \
-    jit_conn_matvec, lib
+    jit_conn_matvec, jit_conn_matvec_dense, lib
 
 
 class EventCSRMatvec(torch.autograd.Function):
@@ -48,6 +48,27 @@ class JitConnMatvec(torch.autograd.Function):
         (ev,) = ctx.saved_tensors
         d_ev, d_w = jit_conn_backward(ctx.conn, ev, dy.contiguous())
         return d_ev, d_w, None
+
+
+class JitConnMatvecDense(torch.autograd.Function):
+    """y = J^T v for a dense float vector v (Section 5.2's JIT operator);
+    gradient for v: dv[j] = sum over row j of w_jk dy[k], the row-wise
+    product of the reverse mode, for every row.  The weights' parameters
+    get no gradient here."""
+
+    @staticmethod
+    def forward(ctx, v, conn: JitConn):
+        ctx.conn = conn
+        return jit_conn_matvec_dense(conn, v.contiguous())
+
+    @staticmethod
+    def backward(ctx, dy):
+        c = ctx.conn.c
+        # the row-wise products do not depend on the spike vector; an all-zero
+        # one also skips the (w0, w1) sums
+        ev = torch.zeros(max(c.n_pre, 1), dtype=torch.uint8, device=dy.device)
+        d_v, _ = jit_conn_backward(ctx.conn, ev, dy.contiguous(), want_w=False)
+        return d_v, None
 
 
 class SNN:

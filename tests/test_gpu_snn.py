@@ -146,3 +146,11 @@ def test_operator_autograd_functions(mods):
                           dy.astype(np.float64))
     gw = w01.grad.cpu().numpy()
     assert abs(gw[0] - g0) <= 1e-4 * max(1.0, abs(g0)) and abs(gw[1] - g1) <= 1e-4 * max(1.0, abs(g1))
+    # JIT product on a dense vector: gradient of v is the row-wise product J dy
+    cu = bp.JitConn(n_pre, n_post, K=O.max_gap(0.01), block=512, seed=3, wkind=bp.W_UNIFORM, w0=-1.0, w1=2.0)
+    v = t(S.dense_vector(n_pre, 7, zero_frac=0.3)).requires_grad_(True)
+    A.JitConnMatvecDense.apply(v, cu).backward(t(dy))
+    d_ev, _, _ = O.jit_vjp(3, O.max_gap(0.01), 512, 2, -1.0, 2.0, n_post, e, dy.astype(np.float64))
+    row_abs, _, _ = O.jit_vjp(3, O.max_gap(0.01), 512, 0, 2.0, 0.0, n_post, e, np.abs(dy).astype(np.float64))
+    err = np.abs(v.grad.cpu().numpy().astype(np.float64) - d_ev)
+    assert np.all(err <= 1e-5 * row_abs + 1e-30), err.max()
