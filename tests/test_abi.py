@@ -63,6 +63,28 @@ def test_argument_errors_are_reported_before_launch():
     assert L.bp_run(None, 1, None, None, None, None) == _abi.BP_ESTATE
 
 
+def test_dense_vector_products_check_arguments_before_launch():
+    import ctypes as C
+    from paper_2311_05106_amd import _abi
+    L = _abi.lib()
+    bad = _abi.JitConn(10, 10, 0, 0, 1, 0, 1.0, 0.0)  # K = 0
+    ok = _abi.JitConn(10, 20, 5, 0, 1, 0, 1.0, 0.0)
+    p = C.c_void_p(0x1000)
+    assert L.bp_jit_conn_matvec_dense(C.byref(bad), p, p, None, 0, None) == _abi.BP_EINVAL
+    assert L.bp_jit_conn_matvec_dense(C.byref(ok), p, None, None, 0, None) == _abi.BP_EINVAL
+    assert L.bp_jit_conn_matvec_dense(C.byref(ok), None, p, None, 0, None) == _abi.BP_EINVAL
+    assert L.bp_jit_conn_matmat_dense(C.byref(bad), p, 4, p, None, 0, None) == _abi.BP_EINVAL
+    assert L.bp_jit_conn_matmat_dense(C.byref(ok), p, -1, p, None, 0, None) == _abi.BP_EINVAL
+    assert L.bp_jit_conn_matmat_dense(C.byref(ok), p, 4, None, None, 0, None) == _abi.BP_EINVAL
+    assert L.bp_jit_conn_matmat_dense(C.byref(ok), None, 4, p, None, 0, None) == _abi.BP_EINVAL
+    big = _abi.JitConn(10, 1 << 20, 5, 0, 1, 0, 1.0, 0.0)
+    assert L.bp_jit_conn_matmat_dense(C.byref(big), p, 1 << 12, p, None, 0, None) == _abi.BP_EINVAL
+    assert b"2^31" in L.bp_last_error()
+    # nothing to compute: success without a launch
+    assert L.bp_jit_conn_matmat_dense(C.byref(ok), p, 0, p, None, 0, None) == _abi.BP_OK
+    assert L.bp_jit_matmat_ws_bytes(C.byref(ok), 0) == 0
+
+
 def test_net_bytes_scales_linearly_for_jit():
     # JIT connectivity stores no synapses (Section 5.2): at a fixed workgroup
     # count (fixed exchange buffers) each extra neuron costs only its state
