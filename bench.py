@@ -144,6 +144,15 @@ def bench_c0(bp, torch, reps=5):
 # JIT operator blocks of 782 columns: 128 column tiles x 2 row chunks make 256
 # workgroups, one per compute unit (blocks of 1024 left 60 idle)
 JIT_OP_BLOCK = 782
+# Dense-vector products list every row, so each workgroup walks many more
+# (row, block) pairs: longer blocks cut the per-pair start-up draws and even
+# out the walks of a wave.  Measured sweep (us, homogeneous / U / N, one
+# vector): 782: 288 / 359 / 424; 1564: 229 / 291 / 348; 3125: 197 / 254 / 306;
+# 6250: 179 / 231 / 282; 12500: 215 / 281 / 342.  The 8-vector product keeps
+# 8 columns in the LDS tile only up to 2048 columns: 1564: 903 / 933 us
+# (U / N), 782: 1062 / 1107, 4096 (5 columns per group): 1008 / 1078.
+DENSE_OP_BLOCK = 6250  # 16 column tiles x 16 row chunks
+DENSE_MAT_BLOCK = 1564  # 64 column tiles x 4 row chunks
 
 
 def bench_ops(bp, torch, calls=10000, fracs=(0.001, 0.01, 0.1)):
@@ -212,10 +221,10 @@ def bench_ops(bp, torch, calls=10000, fracs=(0.001, 0.01, 0.1)):
 
 def bench_dense(bp, torch, calls=640):
     """JIT product on dense float vectors (Section 5.2's operator y = J^T v):
-    n_pre = n_post = 1e5, p = 0.01, blocks of JIT_OP_BLOCK columns, v ~ N(0, 1)
+    n_pre = n_post = 1e5, p = 0.01, blocks of DENSE_OP_BLOCK columns, v ~ N(0, 1)
     with no zeros (every row contributes); `calls` products cycling 8
     vectors, replayed from a HIP graph; then the batched product on 8 vectors
-    at once (4 distinct X, calls / 8 products)."""
+    at once (blocks of DENSE_MAT_BLOCK, 4 distinct X, calls / 8 products)."""
     import numpy as np
     import synthetic as S
     n, K = 100_000, bp.max_gap(0.01)
@@ -225,7 +234,7 @@ def bench_dense(bp, torch, calls=640):
     out = []
     for name, wk, w0, w1 in [("homo", bp.W_HOMO, 0.5, 0.0), ("uniform", bp.W_UNIFORM, -1.0, 1.0),
                              ("normal", bp.W_NORMAL, 0.5, 0.1)]:
-        conn = bp.JitConn(n, n, K=K, block=JIT_OP_BLOCK, seed=0, wkind=wk, w0=w0, w1=w1)
+        conn = bp.JitConn(n, n, K=K, block=DENSE_OP_BLOCK, seed=0, wkind=wk, w0=w0, w1=w1)
         ws = torch.empty(max(bp.jit_dense_ws(conn), 1), dtype=torch.uint8, device=dev)
         # synapses per product: the row lengths of the same seed (every row is listed)
         ip, _ = bp.csr_build(conn)
@@ -253,7 +262,8 @@ def bench_dense(bp, torch, calls=640):
         us = a.elapsed_time(b) * 1e3 / (reps * 8)
         # CSR-equivalent bytes: what a stored matrix would stream (4 B index + 4 B weight per synapse)
         gbs = 8.0 * nnz / (us * 1e-6) / 1e9
-        out.append(dict(op=f"jit_dense_{name}", us_per_call=us, synapses=nnz, synapses_per_s=nnz / (us * 1e-6),
+        out.append(dict(op=f"jit_dense_{name}", block=DENSE_OP_BLOCK, us_per_call=us, synapses=nnz,
+                        synapses_per_s=nnz / (us * 1e-6),
                         csr_equiv_GBps=gbs, csr_equiv_frac=gbs / HBM_PEAK_GBS))
         del g
     # batched: 8 vectors per product (X [n, 8] row-major), each row generated once per column group
@@ -262,7 +272,7 @@ def bench_dense(bp, torch, calls=640):
           .to(dev) for i in range(4)]
     Y = torch.empty((n, m), dtype=torch.float32, device=dev)
     for name, wk, w0, w1 in [("uniform", bp.W_UNIFORM, -1.0, 1.0), ("normal", bp.W_NORMAL, 0.5, 0.1)]:
-        conn = bp.JitConn(n, n, K=K, block=JIT_OP_BLOCK, seed=0, wkind=wk, w0=w0, w1=w1)
+        conn = bp.JitConn(n, n, K=K, block=DENSE_MAT_BLOCK, seed=0, wkind=wk, w0=w0, w1=w1)
         ws = torch.empty(max(bp.jit_matmat_ws(conn, m), 1), dtype=torch.uint8, device=dev)
         ip, _ = bp.csr_build(conn)
         nnz = float(ip[-1].item())
@@ -287,7 +297,8 @@ def bench_dense(bp, torch, calls=640):
         b.record()
         torch.cuda.synchronize()
         us = a.elapsed_time(b) * 1e3 / (reps * 4)
-        out.append(dict(op=f"jit_dense_matmat{m}_{name}", us_per_call=us, synapses=nnz, columns=m,
+        out.append(dict(op=f"jit_dense_matmat{m}_{name}", block=DENSE_MAT_BLOCK, us_per_call=us, synapses=nnz,
+                        columns=m,
                         synapse_columns_per_s=nnz * m / (us * 1e-6)))
         del g
     return out

@@ -297,11 +297,13 @@ def test_jit_dense_vector_wrong_input_rejected(bp):
 
 
 @pytest.mark.parametrize("wkind,w0,w1,zero_frac", [(2, -1.0, 2.0, 0.0), (1, 0.5, 0.1, 0.9)])
-def test_jit_dense_vector_full_operator_size(bp, wkind, w0, w1, zero_frac):
-    # the benchmark's operator: 1e5 x 1e5, p = 0.01, blocks of 1024 columns
+@pytest.mark.parametrize("B", [1024, 6250])
+def test_jit_dense_vector_full_operator_size(bp, wkind, w0, w1, zero_frac, B):
+    # the benchmark's operator: 1e5 x 1e5, p = 0.01, blocks of 6250 columns
+    # (16 tiles x 16 row chunks), and 1024
     n = 100_000
     v = S.dense_vector(n, 9, zero_frac=zero_frac)
-    _dense_check(bp, n, n, O.max_gap(0.01), 1024, wkind, w0, w1, v, seed=0)
+    _dense_check(bp, n, n, O.max_gap(0.01), B, wkind, w0, w1, v, seed=0)
 
 
 def _mat_check(bp, n_pre, n_post, K, B, wkind, w0, w1, X, seed):
@@ -360,10 +362,11 @@ def test_jit_dense_matrix_edge_cases(bp):
 
 
 def test_jit_dense_matrix_full_operator_size(bp):
-    # the benchmark's operator with 8 vectors: 1e5 x 1e5, p = 0.01, blocks of 782
+    # the benchmark's operator with 8 vectors: 1e5 x 1e5, p = 0.01, blocks of
+    # 1564 (64 tiles x 4 row chunks)
     n = 100_000
     X = _mat(n, 8, 80, zero_frac=0.9)
-    _mat_check(bp, n, n, O.max_gap(0.01), 782, 2, -1.0, 1.0, X, seed=0)
+    _mat_check(bp, n, n, O.max_gap(0.01), 1564, 2, -1.0, 1.0, X, seed=0)
 
 
 # ------------------------------------------------------------------ reverse mode
