@@ -141,9 +141,14 @@ def bench_c0(bp, torch, reps=5):
                 us_per_step=t * 1e3, sim_s_per_wall_s=0.1 / t, synaptic_events_per_s=ev / t)
 
 
-# JIT operator blocks of 782 columns: 128 column tiles x 2 row chunks make 256
-# workgroups, one per compute unit (blocks of 1024 left 60 idle)
-JIT_OP_BLOCK = 782
+# JIT operator blocks of 3125 columns: 32 column tiles x 8 row chunks make 256
+# workgroups, one per compute unit.  Measured sweep (us, homogeneous / normal
+# weights at 0.1 %, 1 %, 10 % firing): 782 (128 tiles x 2 chunks): 9.8/11.3,
+# 11.7/17.4, 25.5/54.3; 1564: 8.6/11.1, 10.8/18.1, 19.6/42.7; 3125: 7.9/11.6,
+# 8.8/13.5, 17.6/43.3; 6250: 8.7/14.8, 9.3/16.5, 19.2/48.2.  Longer blocks
+# mean longer walks per (row, block): fewer start-up draws per target and
+# less spread between the walks of a wave.
+JIT_OP_BLOCK = 3125
 # Dense-vector products list every row, so each workgroup walks many more
 # (row, block) pairs: longer blocks cut the per-pair start-up draws and even
 # out the walks of a wave.  Measured sweep (us, homogeneous / U / N, one

@@ -220,12 +220,26 @@ def test_jit_weighted(bp, wkind, w0, w1, B):
 
 
 @pytest.mark.parametrize("frac", [0.01, 0.1])
-def test_jit_full_operator_size(bp, frac):
-    n, K, B = 100_000, O.max_gap(0.01), 1024
+@pytest.mark.parametrize("B", [1024, 3125])  # 3125: the operator sweep's blocks
+def test_jit_full_operator_size(bp, frac, B):
+    n, K = 100_000, O.max_gap(0.01)
     e = S.events(n, frac, 8)
     cnt = O.jit_counts(0, K, B, n, e)
     y = bp.jit_conn_matvec(bp.JitConn(n, n, K=K, block=B, seed=0, w0=0.5), _to(e))
     np.testing.assert_array_equal(y.cpu().numpy(), cnt.astype(np.float32) * np.float32(0.5))
+
+
+def test_jit_normal_full_operator_size(bp):
+    # the operator sweep's weighted point: 1e5 x 1e5, p = 0.01, blocks of 3125,
+    # N(0.5, 0.1) weights, 10 % firing
+    n, K, B = 100_000, O.max_gap(0.01), 3125
+    e = S.events(n, 0.1, 8)
+    ref = O.jit_matvec(0, K, B, 1, np.float32(0.5), np.float32(0.1), n, e)
+    cnt = O.jit_counts(0, K, B, n, e)
+    y = bp.jit_conn_matvec(bp.JitConn(n, n, K=K, block=B, seed=0, wkind=1, w0=0.5, w1=0.1), _to(e)).cpu().numpy()
+    err = np.abs(y - ref)
+    assert np.all(err <= 1e-5 * cnt * (0.5 + 6 * 0.1) + 1e-7 * (cnt > 0)), err.max()
+    assert np.all(y[cnt == 0] == 0.0)
 
 
 # ------------------------------------------------- JIT product on a float vector
