@@ -283,14 +283,19 @@ static double u_open1(uint32_t word) { return (double)(word >> 8) * (1.0 / 16777
 
 /* Weight of connection m (0-based, in generation order) of row j, block b.
  * Homogeneous: w0.  Uniform: w0 + (w1 - w0) u.  Normal: w0 + w1 z with z from
- * Box-Muller on draws 2m and 2m+1 of stream W.  Also returns the unit draw
+ * Box-Muller on draws 2q and 2q+1 of stream W, q = m / 2 (cosine half for
+ * even m, sine half for odd m).  Also returns the unit draw
  * (u, or z) in *unit for the reverse mode. */
 double or_jit_weight(uint64_t seed, int32_t wkind, double w0, double w1, int32_t j, int32_t b,
                      int64_t m, double* unit) {
   if (wkind == OR_W_NORMAL) {
-    double u1 = u_open0(or_hash(seed, OR_STREAM_W, (uint32_t)j, (uint32_t)b, (uint32_t)(2 * m)));
-    double u2 = u_open1(or_hash(seed, OR_STREAM_W, (uint32_t)j, (uint32_t)b, (uint32_t)(2 * m + 1)));
-    double z = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+    /* Box-Muller, both halves of each pair: targets 2q and 2q + 1 share the
+     * draws 2q, 2q + 1 and take r cos(2 pi u2) and r sin(2 pi u2). */
+    const int64_t q = m >> 1;
+    double u1 = u_open0(or_hash(seed, OR_STREAM_W, (uint32_t)j, (uint32_t)b, (uint32_t)(2 * q)));
+    double u2 = u_open1(or_hash(seed, OR_STREAM_W, (uint32_t)j, (uint32_t)b, (uint32_t)(2 * q + 1)));
+    double r = sqrt(-2.0 * log(u1));
+    double z = (m & 1) ? r * sin(2.0 * M_PI * u2) : r * cos(2.0 * M_PI * u2);
     if (unit) *unit = z;
     return w0 + w1 * z;
   }

@@ -118,14 +118,19 @@ __device__ __forceinline__ void gen_block(uint64_t seed, uint32_t K, int32_t n_p
 
 // Weight of connection m of (j, b) for the JIT weight kinds, read from the
 // W sub-stream of (j, b) through `wd` (connections are visited in increasing
-// m, so one Philox call serves two normal or four uniform weights); *unit
+// m, so one Philox call serves four normal or four uniform weights); *unit
 // receives the unit draw (z or u) for the reverse mode.
 __device__ __forceinline__ float jit_weight(DrawSeq& wd, int wkind, float w0, float w1, uint32_t m, float* unit) {
   if (wkind == kWNormal) {
-    // Box-Muller with the hardware log2 / sqrt / cos(2 pi x) instructions
-    const uint32_t wa = wd(2u * m), wb = wd(2u * m + 1u);
+    // Box-Muller with the hardware log2 / sqrt / cos(2 pi x) instructions;
+    // connections 2q and 2q + 1 share draws 2q, 2q + 1 and take the cosine
+    // and the sine half (sin(2 pi x) = cos(2 pi (x - 1/4)); x - 1/4 is exact
+    // for x on the 2^-24 grid)
+    const uint32_t q = m >> 1;
+    const uint32_t wa = wd(2u * q), wb = wd(2u * q + 1u);
     const float u1 = u_open0(wa), u2 = u_open1(wb);
-    const float z = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1)) * __builtin_amdgcn_cosf(u2);
+    const float x = u2 - ((m & 1u) ? 0.25f : 0.0f);
+    const float z = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1)) * __builtin_amdgcn_cosf(x);
     *unit = z;
     return w0 + w1 * z;
   }

@@ -171,6 +171,26 @@ def test_jit_normal_weights_are_normal():
     assert abs(w.mean() - 0.5) < 5 * 0.1 / math.sqrt(w.size)
 
 
+def test_jit_normal_weight_pairs():
+    # connections 2q and 2q + 1 are the two halves of one Box-Muller pair:
+    # uncorrelated N(0, 1) values whose squares sum to a chi-square with two
+    # degrees of freedom (the shared radius), and the pair's angle is uniform
+    z = np.array([[O.jit_weight(6, O.W_NORMAL, 0.0, 1.0, j, 2, m)[1] for m in (2 * q, 2 * q + 1)]
+                  for j in range(300) for q in range(10)])
+    assert abs(np.corrcoef(z[:, 0], z[:, 1])[0, 1]) < 5 / math.sqrt(len(z))
+    assert stats.kstest(z[:, 0] ** 2 + z[:, 1] ** 2, "chi2", args=(2,)).pvalue > 1e-3
+    ang = np.arctan2(z[:, 1], z[:, 0]) / (2 * math.pi) % 1.0
+    assert stats.kstest(ang, "uniform").pvalue > 1e-3
+    # and the pair is built from the words 2q, 2q + 1 of the weight stream
+    for j, b, q in [(0, 0, 0), (7, 3, 5), (123, 1, 17)]:
+        u1 = ((O.hash_word(6, O.STREAM_W, j, b, 2 * q) >> 8) + 1) / 2.0 ** 24
+        u2 = (O.hash_word(6, O.STREAM_W, j, b, 2 * q + 1) >> 8) / 2.0 ** 24
+        z0 = O.jit_weight(6, O.W_NORMAL, 0.0, 1.0, j, b, 2 * q)[1]
+        z1 = O.jit_weight(6, O.W_NORMAL, 0.0, 1.0, j, b, 2 * q + 1)[1]
+        assert z0 ** 2 + z1 ** 2 == pytest.approx(-2.0 * math.log(u1), rel=1e-12)
+        assert math.atan2(z1, z0) / (2 * math.pi) % 1.0 == pytest.approx(u2, abs=1e-12)
+
+
 def test_jit_uniform_weights_are_uniform():
     u = np.array([O.jit_weight(4, O.W_UNIFORM, 0.0, 1.0, j, 1, m)[0] for j in range(400) for m in range(50)])
     assert stats.kstest(u, "uniform").pvalue > 1e-3
