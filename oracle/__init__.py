@@ -99,8 +99,9 @@ def lib():
                                      C.c_void_p]
         L.or_snn_grad.restype = C.c_int
         L.or_snn_grad.argtypes = [C.POINTER(SnnParams), _u8p, _i32p, _f64p, _i32p, _i32p, _f64p, _f64p, _f64p,
-                                  C.c_void_p, C.POINTER(C.c_double), _f64p, C.c_void_p, C.c_void_p,
-                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+                                  C.c_void_p, C.c_void_p, C.POINTER(C.c_double), _f64p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_snn_spike_fns.argtypes = [C.POINTER(SnnParams), _f64p, C.c_int64, C.c_void_p, C.c_void_p]
         _lib = L
     return _lib
 
@@ -312,8 +313,22 @@ def snn_params(B, C_, N, O, T, alpha, beta, theta=1.0, slope=4.0, surrogate=0, s
                      relu_width)
 
 
+def snn_spike_fns(P, v):
+    """(S(v), S'(v)): the smooth spike function of smooth mode and the
+    surrogate derivative used by the reverse pass, at membrane values v."""
+    vv = np.ascontiguousarray(v, np.float64).reshape(-1)
+    s = np.empty_like(vv)
+    ds = np.empty_like(vv)
+    lib().or_snn_spike_fns(C.byref(P), vv, vv.size, _ptr(s), _ptr(ds))
+    return s, ds
+
+
 def snn_grad(P, x, labels, W_in, indptr, indices, w_rec, W_out, b_out, z_force=None, want_z=False,
-             want_margin=False):
+             want_margin=False, reset_in=None, want_zval=False):
+    """Loss, logits and BPTT gradients of the recurrent LIF network (FP64).
+    z_force: spikes [T, B, N] to use instead of the threshold; reset_in:
+    frozen reset factors [T, B, N] (entry t multiplies V_{t-1} at step t);
+    want_zval: also return the spike values z_t (fractional in smooth mode)."""
     B, N, O, T, Cc = P.B, P.N, P.O, P.T, P.C
     loss = C.c_double(0.0)
     logits = np.empty((B, O), np.float64)
@@ -325,12 +340,14 @@ def snn_grad(P, x, labels, W_in, indptr, indices, w_rec, W_out, b_out, z_force=N
     dW_out = np.empty((N, O), np.float64)
     db_out = np.empty(O, np.float64)
     zf = None if z_force is None else np.ascontiguousarray(z_force, np.uint8)
+    rf = None if reset_in is None else np.ascontiguousarray(reset_in, np.float64)
+    zv = np.empty((T, B, N), np.float64) if want_zval else None
     rc = lib().or_snn_grad(C.byref(P), np.ascontiguousarray(x, np.uint8), np.ascontiguousarray(labels, np.int32),
                            np.ascontiguousarray(W_in, np.float64), np.ascontiguousarray(indptr, np.int32),
                            np.ascontiguousarray(indices, np.int32), np.ascontiguousarray(w_rec, np.float64),
                            np.ascontiguousarray(W_out, np.float64), np.ascontiguousarray(b_out, np.float64),
-                           _ptr(zf), C.byref(loss), logits, _ptr(z_out), _ptr(vm), _ptr(dW_in), _ptr(dw_rec),
-                           _ptr(dW_out), _ptr(db_out))
+                           _ptr(zf), _ptr(rf), C.byref(loss), logits, _ptr(z_out), _ptr(vm), _ptr(zv), _ptr(dW_in),
+                           _ptr(dw_rec), _ptr(dW_out), _ptr(db_out))
     assert rc == 0
-    return dict(loss=loss.value, logits=logits, z=z_out, vmargin=vm, dW_in=dW_in, dw_rec=dw_rec[:nnz],
+    return dict(loss=loss.value, logits=logits, z=z_out, vmargin=vm, zval=zv, dW_in=dW_in, dw_rec=dw_rec[:nnz],
                 dW_out=dW_out, db_out=db_out)
