@@ -49,61 +49,83 @@ class SnnParams(C.Structure):
 
 
 def lib():
+    """The oracle built as plain C (loops run as written, one thread)."""
     global _lib
     if _lib is None:
-        path = _build.LIB
-        if not os.path.exists(path):
+        if not os.path.exists(_build.LIB):
             _build.build()
-        L = C.CDLL(path)
-        L.or_hash.restype = C.c_uint32
-        L.or_hash.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]
-        L.or_hash_many.argtypes = [C.c_uint64, C.c_uint32, _u32p, _u32p, _u32p, _u32p, C.c_int64]
-        L.or_philox.argtypes = [_u32p, C.c_uint32, C.c_uint32, _u32p]
-        L.or_philox_many.argtypes = [_u32p, _u32p, _u32p, C.c_int64]
-        L.or_max_gap.restype = C.c_int32
-        L.or_max_gap.argtypes = [C.c_double]
-        L.or_row_block.restype = C.c_int64
-        L.or_row_block.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p]
-        L.or_row.restype = C.c_int64
-        L.or_row.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p]
-        L.or_csr_count.restype = C.c_int64
-        L.or_csr_count.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p]
-        L.or_csr_build.restype = C.c_int64
-        L.or_csr_build.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _i32p, _i32p, C.c_int64]
-        L.or_compact.restype = C.c_int32
-        L.or_compact.argtypes = [_u8p, C.c_int32, _i32p]
-        L.or_event_csr_matvec.argtypes = [_i32p, _i32p, C.c_void_p, C.c_double, C.c_int32, C.c_int32, _u8p, _f64p]
-        L.or_event_csr_counts.argtypes = [_i32p, _i32p, C.c_int32, C.c_int32, _u8p, _i64p]
-        L.or_event_csr_vjp.argtypes = [_i32p, _i32p, C.c_void_p, C.c_double, C.c_int32, C.c_int32, _u8p, _f64p,
-                                       C.c_void_p, C.c_void_p, C.c_void_p]
-        L.or_jit_weight.restype = C.c_double
-        L.or_jit_weight.argtypes = [C.c_uint64, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_int32,
-                                    C.c_int64, C.c_void_p]
-        L.or_jit_matvec.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
-                                    C.c_int32, C.c_int32, _u8p, _f64p]
-        L.or_jit_counts.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _u8p, _i64p]
-        L.or_jit_matmat_dense.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
-                                          C.c_int32, C.c_int32, C.c_int32, _f64p, _f64p]
-        L.or_jit_matvec_dense.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
-                                          C.c_int32, C.c_int32, _f64p, _f64p]
-        L.or_jit_vjp.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
-                                 C.c_int32, C.c_int32, _u8p, _f64p, C.c_void_p, C.c_void_p, C.c_void_p]
-        L.or_net_v0.argtypes = [C.POINTER(NetParams), _f32p]
-        L.or_net_ref_steps.restype = C.c_int32
-        L.or_net_ref_steps.argtypes = [C.POINTER(NetParams)]
-        L.or_net_run_f32.argtypes = [C.POINTER(NetParams), C.c_void_p, C.c_void_p, C.c_int32,
-                                     _f32p, _f32p, _f32p, _i32p, _u8p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                     C.c_void_p]
-        L.or_net_run_f64.argtypes = [C.POINTER(NetParams), C.c_void_p, C.c_void_p, C.c_int32,
-                                     _f64p, _f64p, _f64p, _i32p, _u8p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                     C.c_void_p]
-        L.or_snn_grad.restype = C.c_int
-        L.or_snn_grad.argtypes = [C.POINTER(SnnParams), _u8p, _i32p, _f64p, _i32p, _i32p, _f64p, _f64p, _f64p,
-                                  C.c_void_p, C.c_void_p, C.POINTER(C.c_double), _f64p, C.c_void_p, C.c_void_p,
-                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
-        L.or_snn_spike_fns.argtypes = [C.POINTER(SnnParams), _f64p, C.c_int64, C.c_void_p, C.c_void_p]
-        _lib = L
+        _lib = _load(_build.LIB)
     return _lib
+
+
+_lib_omp = None
+
+
+def lib_omp():
+    """The same oracle built with its OpenMP pragmas: the network loops spread
+    over the host cores (the CPU baseline).  Results are identical."""
+    global _lib_omp
+    if _lib_omp is None:
+        if not os.path.exists(_build.LIB_OMP):
+            _build.build()
+        _lib_omp = _load(_build.LIB_OMP)
+    return _lib_omp
+
+
+def _load(path):
+    L = C.CDLL(path)
+    L.or_set_threads.restype = C.c_int32
+    L.or_set_threads.argtypes = [C.c_int32]
+    L.or_hash.restype = C.c_uint32
+    L.or_hash.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]
+    L.or_hash_many.argtypes = [C.c_uint64, C.c_uint32, _u32p, _u32p, _u32p, _u32p, C.c_int64]
+    L.or_philox.argtypes = [_u32p, C.c_uint32, C.c_uint32, _u32p]
+    L.or_philox_many.argtypes = [_u32p, _u32p, _u32p, C.c_int64]
+    L.or_max_gap.restype = C.c_int32
+    L.or_max_gap.argtypes = [C.c_double]
+    L.or_row_block.restype = C.c_int64
+    L.or_row_block.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p]
+    L.or_row.restype = C.c_int64
+    L.or_row.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p]
+    L.or_csr_count.restype = C.c_int64
+    L.or_csr_count.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p]
+    L.or_csr_build.restype = C.c_int64
+    L.or_csr_build.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _i32p, _i32p, C.c_int64]
+    L.or_compact.restype = C.c_int32
+    L.or_compact.argtypes = [_u8p, C.c_int32, _i32p]
+    L.or_event_csr_matvec.argtypes = [_i32p, _i32p, C.c_void_p, C.c_double, C.c_int32, C.c_int32, _u8p, _f64p]
+    L.or_event_csr_counts.argtypes = [_i32p, _i32p, C.c_int32, C.c_int32, _u8p, _i64p]
+    L.or_event_csr_vjp.argtypes = [_i32p, _i32p, C.c_void_p, C.c_double, C.c_int32, C.c_int32, _u8p, _f64p,
+                                   C.c_void_p, C.c_void_p, C.c_void_p]
+    L.or_jit_weight.restype = C.c_double
+    L.or_jit_weight.argtypes = [C.c_uint64, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_int32,
+                                C.c_int64, C.c_void_p]
+    L.or_jit_matvec.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                C.c_int32, C.c_int32, _u8p, _f64p]
+    L.or_jit_counts.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _u8p, _i64p]
+    L.or_jit_matmat_dense.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                      C.c_int32, C.c_int32, C.c_int32, _f64p, _f64p]
+    L.or_jit_abs_terms.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                   C.c_int32, C.c_int32, C.c_int32, _f64p, _f64p]
+    L.or_jit_matvec_dense.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                      C.c_int32, C.c_int32, _f64p, _f64p]
+    L.or_jit_vjp.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                             C.c_int32, C.c_int32, _u8p, _f64p, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.or_net_v0.argtypes = [C.POINTER(NetParams), _f32p]
+    L.or_net_ref_steps.restype = C.c_int32
+    L.or_net_ref_steps.argtypes = [C.POINTER(NetParams)]
+    L.or_net_run_f32.argtypes = [C.POINTER(NetParams), C.c_void_p, C.c_void_p, C.c_int32,
+                                 _f32p, _f32p, _f32p, _i32p, _u8p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p]
+    L.or_net_run_f64.argtypes = [C.POINTER(NetParams), C.c_void_p, C.c_void_p, C.c_int32,
+                                 _f64p, _f64p, _f64p, _i32p, _u8p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p]
+    L.or_snn_grad.restype = C.c_int
+    L.or_snn_grad.argtypes = [C.POINTER(SnnParams), _u8p, _i32p, _f64p, _i32p, _i32p, _f64p, _f64p, _f64p,
+                              C.c_void_p, C.c_void_p, C.POINTER(C.c_double), _f64p, C.c_void_p, C.c_void_p,
+                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.or_snn_spike_fns.argtypes = [C.POINTER(SnnParams), _f64p, C.c_int64, C.c_void_p, C.c_void_p]
+    return L
 
 
 def _ptr(a):
@@ -238,6 +260,19 @@ def jit_matmat_dense(seed, K, B, wkind, w0, w1, n_post, X):
     return Y
 
 
+def jit_abs_terms(seed, K, B, wkind, w0, w1, n_post, X):
+    """Sum of |w_jk| |X[j, c]| over rows j, the magnitude of the terms of
+    J^T X (tolerance scale of FP32 sums).  X: a vector (spike bytes as 0/1,
+    or floats) or a [n_pre, m] matrix; the result has the same rank."""
+    XX = np.asarray(X)
+    vec = XX.ndim == 1
+    XX = np.ascontiguousarray(XX.reshape(XX.shape[0], -1), np.float64)
+    Sm = np.empty((n_post, XX.shape[1]), np.float64)
+    lib().or_jit_abs_terms(seed, K, B, wkind, float(w0), float(w1), XX.shape[0], n_post, XX.shape[1],
+                           XX.reshape(-1), Sm.reshape(-1))
+    return Sm[:, 0] if vec else Sm
+
+
 def jit_counts(seed, K, B, n_post, events):
     ev = np.ascontiguousarray(events, np.uint8)
     cnt = np.empty(n_post, np.int64)
@@ -288,7 +323,16 @@ class NetState:
         self.t = 0
 
 
-def net_run(P, state, T, indptr=None, indices=None, iext_vec=None, want_raster=True):
+def set_threads(threads=0):
+    """Threads of the OpenMP build's network loops (0: the runtime default);
+    returns how many it will use."""
+    return int(lib_omp().or_set_threads(int(threads)))
+
+
+def net_run(P, state, T, indptr=None, indices=None, iext_vec=None, want_raster=True, parallel=False):
+    """T steps of the network from `state` (updated in place).  parallel: run
+    the OpenMP build of the same loops (identical results)."""
+    L = lib_omp() if parallel else lib()
     raster = np.empty((T, P.n), np.uint8) if want_raster else None
     counts = np.empty(T, np.int32)
     events = np.zeros(1, np.int64)
@@ -296,10 +340,10 @@ def net_run(P, state, T, indptr=None, indices=None, iext_vec=None, want_raster=T
     ix = None if indices is None else np.ascontiguousarray(indices, np.int32)
     if state.precision == 32:
         iv = None if iext_vec is None else np.ascontiguousarray(iext_vec, np.float32)
-        fn = lib().or_net_run_f32
+        fn = L.or_net_run_f32
     else:
         iv = None if iext_vec is None else np.ascontiguousarray(iext_vec, np.float64)
-        fn = lib().or_net_run_f64
+        fn = L.or_net_run_f64
     fn(C.byref(P), _ptr(ip), _ptr(ix), T, state.V, state.ge, state.gi, state.ref, state.s_prev,
        _ptr(iv), _ptr(raster), _ptr(counts), _ptr(events))
     state.t += T

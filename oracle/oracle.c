@@ -44,6 +44,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------------ */
 /* Philox-4x32-10                                                           */
@@ -364,6 +367,30 @@ void or_jit_matmat_dense(uint64_t seed, int32_t K, int32_t B, int32_t wkind, dou
   free(buf);
 }
 
+/* Sum of the magnitudes of the terms of the batched product:
+ * S[k][c] = sum over rows j of |w_jk| |X[j][c]|, X row-major [n_pre][m].
+ * FP32 sums of the terms w_jk X[j][c] differ from the exact sum by a
+ * multiple of the unit roundoff times this sum, so parity tolerances are
+ * stated relative to it.  m = 1 serves the single-vector products (X = v,
+ * or the spike vector as 0/1). */
+void or_jit_abs_terms(uint64_t seed, int32_t K, int32_t B, int32_t wkind, double w0, double w1,
+                      int32_t n_pre, int32_t n_post, int32_t m, const double* X, double* S) {
+  int32_t* buf = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_post > 0 ? n_post : 1));
+  int32_t nb = n_blocks(n_post, B);
+  for (int64_t i = 0; i < (int64_t)n_post * m; ++i) S[i] = 0.0;
+  for (int32_t j = 0; j < n_pre; ++j) {
+    const double* x = X + (size_t)j * m;
+    for (int32_t b = 0; b < nb; ++b) {
+      int64_t cnt = or_row_block(seed, K, n_post, B, j, b, buf);
+      for (int64_t t = 0; t < cnt; ++t) {
+        const double w = fabs(or_jit_weight(seed, wkind, w0, w1, j, b, t, NULL));
+        for (int32_t c = 0; c < m; ++c) S[(size_t)buf[t] * m + c] += w * fabs(x[c]);
+      }
+    }
+  }
+  free(buf);
+}
+
 void or_jit_counts(uint64_t seed, int32_t K, int32_t B, int32_t n_pre, int32_t n_post,
                    const uint8_t* ev, int64_t* cnt) {
   int32_t* buf = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_post > 0 ? n_post : 1));
@@ -445,27 +472,56 @@ int32_t or_net_ref_steps(const or_net* P) {
 
 /* Counts of excitatory and inhibitory firing presynaptic rows reaching each
  * neuron: the synaptic input of one step (one-step delay: s_prev are the
- * spikes of the previous step). */
+ * spikes of the previous step).
+ * The rows are independent and the counts are integers, so the OpenMP build
+ * of this file (the CPU baseline) deals the rows to threads and adds the
+ * counts atomically: the same counts in any order.  A plain build ignores
+ * the pragmas and runs the loops as written. */
 static void net_inputs(const or_net* P, const int32_t* indptr, const int32_t* indices,
-                       const uint8_t* s_prev, int64_t* ce, int64_t* ci, int32_t* buf,
-                       int64_t* events) {
+                       const uint8_t* s_prev, int64_t* ce, int64_t* ci, int64_t* events) {
   int32_t n = P->n;
   int32_t nb = n_blocks(n, P->block);
+  int64_t ev = 0;
   for (int32_t k = 0; k < n; ++k) { ce[k] = 0; ci[k] = 0; }
-  for (int32_t j = 0; j < n; ++j) {
-    if (!s_prev[j]) continue;
-    int64_t* c = (j < P->n_exc) ? ce : ci;
-    if (P->conn == 0) {
-      for (int32_t idx = indptr[j]; idx < indptr[j + 1]; ++idx) c[indices[idx]] += 1;
-      *events += indptr[j + 1] - indptr[j];
-    } else {
-      for (int32_t b = 0; b < nb; ++b) {
-        int64_t m = or_row_block(P->seed, P->max_gap, n, P->block, j, b, buf);
-        for (int64_t q = 0; q < m; ++q) c[buf[q]] += 1;
-        *events += m;
+#pragma omp parallel reduction(+ : ev)
+  {
+    int32_t* buf = P->conn == 0 ? NULL : (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+#pragma omp for schedule(dynamic, 256)
+    for (int32_t j = 0; j < n; ++j) {
+      if (!s_prev[j]) continue;
+      int64_t* c = (j < P->n_exc) ? ce : ci;
+      if (P->conn == 0) {
+        for (int32_t idx = indptr[j]; idx < indptr[j + 1]; ++idx) {
+#pragma omp atomic
+          c[indices[idx]] += 1;
+        }
+        ev += indptr[j + 1] - indptr[j];
+      } else {
+        for (int32_t b = 0; b < nb; ++b) {
+          int64_t m = or_row_block(P->seed, P->max_gap, n, P->block, j, b, buf);
+          for (int64_t q = 0; q < m; ++q) {
+#pragma omp atomic
+            c[buf[q]] += 1;
+          }
+          ev += m;
+        }
       }
     }
+    free(buf);
   }
+  *events += ev;
+}
+
+/* Threads the network loops may use: the OpenMP build sets and reports them
+ * (threads <= 0 keeps the runtime's default), a plain build always has one. */
+int32_t or_set_threads(int32_t threads) {
+#ifdef _OPENMP
+  if (threads > 0) omp_set_num_threads(threads);
+  return (int32_t)omp_get_max_threads();
+#else
+  (void)threads;
+  return 1;
+#endif
 }
 
 /*
@@ -490,12 +546,12 @@ void or_net_run_f32(const or_net* P, const int32_t* indptr, const int32_t* indic
   int32_t ref_steps = or_net_ref_steps(P);
   int64_t* ce = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
   int64_t* ci = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
-  int32_t* buf = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
   uint8_t* s = (uint8_t*)malloc((size_t)n);
   int64_t ev = 0;
   for (int32_t t = 0; t < T; ++t) {
-    net_inputs(P, indptr, indices, s_prev, ce, ci, buf, &ev);
+    net_inputs(P, indptr, indices, s_prev, ce, ci, &ev);
     int32_t cnt = 0;
+#pragma omp parallel for reduction(+ : cnt)
     for (int32_t k = 0; k < n; ++k) {
       float xe = (float)ce[k] * P->w_exc;
       float xi = (float)ci[k] * P->w_inh;
@@ -525,7 +581,7 @@ void or_net_run_f32(const or_net* P, const int32_t* indptr, const int32_t* indic
     if (counts) counts[t] = cnt;
   }
   if (events) *events = ev;
-  free(ce); free(ci); free(buf); free(s);
+  free(ce); free(ci); free(s);
 }
 
 /* The same recursion carried in FP64 (parameters are the FP32 values, the
@@ -541,12 +597,12 @@ void or_net_run_f64(const or_net* P, const int32_t* indptr, const int32_t* indic
   int32_t ref_steps = or_net_ref_steps(P);
   int64_t* ce = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
   int64_t* ci = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
-  int32_t* buf = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
   uint8_t* s = (uint8_t*)malloc((size_t)n);
   int64_t ev = 0;
   for (int32_t t = 0; t < T; ++t) {
-    net_inputs(P, indptr, indices, s_prev, ce, ci, buf, &ev);
+    net_inputs(P, indptr, indices, s_prev, ce, ci, &ev);
     int32_t cnt = 0;
+#pragma omp parallel for reduction(+ : cnt)
     for (int32_t k = 0; k < n; ++k) {
       ge[k] = ge[k] * de + (double)ce[k] * (double)P->w_exc;
       gi[k] = gi[k] * di + (double)ci[k] * (double)P->w_inh;
@@ -573,5 +629,5 @@ void or_net_run_f64(const or_net* P, const int32_t* indptr, const int32_t* indic
     if (counts) counts[t] = cnt;
   }
   if (events) *events = ev;
-  free(ce); free(ci); free(buf); free(s);
+  free(ce); free(ci); free(s);
 }

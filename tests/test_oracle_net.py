@@ -132,3 +132,22 @@ def test_c0_network_fp32_vs_fp64():
         assert abs(f32 - f64) <= 0.02 * f64
     rate = r32.mean() / 1e-4
     assert 1.0 < rate < 200.0  # Hz, an active asynchronous regime
+
+
+@pytest.mark.parametrize("conn,block", [(0, 0), (1, 0), (1, 256)])
+def test_openmp_build_is_identical(conn, block):
+    # the CPU baseline runs the OpenMP build of the network loops; it must
+    # give exactly the plain build's rasters, counts, events and state
+    n, K = 3000, O.max_gap(0.05)
+    P = O.net_params(model=0, n=n, n_exc=2400, conn=conn, max_gap=K, block=block, seed=3, **COBA_PARAMS)
+    ip, ix = O.csr_build(3, K, n, n, block) if conn == 0 else (None, None)
+    a, b = O.NetState(P), O.NetState(P)
+    ra, ca, ea = O.net_run(P, a, 120, ip, ix)
+    assert O.set_threads(4) >= 1
+    rb, cb, eb = O.net_run(P, b, 120, ip, ix, parallel=True)
+    assert ca.sum() > 0
+    np.testing.assert_array_equal(ra, rb)
+    np.testing.assert_array_equal(ca, cb)
+    assert ea == eb
+    for f in ("V", "ge", "gi", "ref", "s_prev"):
+        np.testing.assert_array_equal(getattr(a, f), getattr(b, f))

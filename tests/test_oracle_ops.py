@@ -162,6 +162,30 @@ def test_jit_dense_matrix_bruteforce(wkind):
         np.testing.assert_array_equal(Y[:, c], O.jit_matvec_dense(seed, K, B, wkind, w0, w1, n_post, X[:, c]))
 
 
+@pytest.mark.parametrize("wkind", [O.W_HOMO, O.W_NORMAL, O.W_UNIFORM])
+def test_jit_abs_terms_bruteforce(wkind):
+    # the tolerance scale of the FP32 products: sum over rows of |w_jk| |x_j|
+    # equals |D|^T |X| for the dense matrix assembled entry by entry, and the
+    # product itself when every weight and every x is non-negative
+    seed, K, n_pre, n_post, B, m = 9, 5, 40, 66, 16, 3
+    w0, w1 = {O.W_HOMO: (-0.3, 0.0), O.W_NORMAL: (0.1, 1.0), O.W_UNIFORM: (-1.0, 2.0)}[wkind]
+    D = np.zeros((n_pre, n_post))
+    for j in range(n_pre):
+        for b in range(-(-n_post // B)):
+            for t, k in enumerate(O.row_block(seed, K, n_post, B, j, b)):
+                D[j, k] += O.jit_weight(seed, wkind, w0, w1, j, b, t)[0]
+    assert (D < 0).any()
+    X = np.stack([S.dense_vector(n_pre, 70 + c, zero_frac=0.3) for c in range(m)], 1).astype(np.float64)
+    np.testing.assert_allclose(O.jit_abs_terms(seed, K, B, wkind, w0, w1, n_post, X), np.abs(D).T @ np.abs(X),
+                               rtol=1e-12, atol=1e-12)
+    e = S.events(n_pre, 0.4, 3)
+    np.testing.assert_allclose(O.jit_abs_terms(seed, K, B, wkind, w0, w1, n_post, e), np.abs(D).T @ e,
+                               rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(O.jit_abs_terms(seed, K, B, O.W_UNIFORM, 0.5, 2.0, n_post, np.abs(X)),
+                               O.jit_matmat_dense(seed, K, B, O.W_UNIFORM, 0.5, 2.0, n_post, np.abs(X)),
+                               rtol=1e-12, atol=1e-12)
+
+
 def test_jit_normal_weights_are_normal():
     z = np.array([O.jit_weight(3, O.W_NORMAL, 0.0, 1.0, j, 0, m)[1] for j in range(400) for m in range(50)])
     assert abs(z.mean()) < 5 / math.sqrt(z.size)
