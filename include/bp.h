@@ -135,9 +135,17 @@ typedef struct {
                              (true for bp_csr_fill output) */
   const int32_t* tile_ptr; /* optional device int32[n_pre][n_tiles + 1] from
                               bp_csr_tile_index, n_tiles = ceil(n_post /
-                              tile_width); needed (with sorted = 1) for the
-                              tiled kernel when n_post > 16384, otherwise a
-                              slower device-atomic kernel is used */
+                              tile_width): a speed hint for sorted rows with
+                              n_post > 16384 (LDS tiles of tile_width columns,
+                              each row's tile segment read from the index).
+                              Without it sorted rows use equal tiles of at most
+                              16384 columns and the kernel finds each row's
+                              segment by a search of the row (same results).
+                              Unsorted rows with n_post > 16384 (and unsorted
+                              homogeneous rows split over several row chunks)
+                              take a device-atomic kernel: integer counts stay
+                              exact, FP32 sums are unordered as in every
+                              weighted path. */
   int32_t tile_width;
 } bp_csr;
 
@@ -314,7 +322,10 @@ size_t bp_state_bytes(bp_net net);
 bp_status bp_get_state(bp_net net, void* dst, size_t bytes, bp_stream stream);
 bp_status bp_set_state(bp_net net, const void* src, size_t bytes, int64_t step, bp_stream stream);
 
-/* Releases the host handle (never the workspace). */
+/* Releases the host handle (never the workspace).  The library keeps a table
+ * of live handles: destroying a handle twice, or passing a destroyed or
+ * foreign handle to any bp_* call, returns BP_ESTATE without reading the
+ * freed handle.  Calls on one net must not race with its destruction. */
 bp_status bp_destroy_net(bp_net net);
 
 /* ------------------------------------------------------------------------ */

@@ -38,6 +38,50 @@ def _dev(t, dtype, name):
     return t.contiguous()
 
 
+def _events(t, n, name="events"):
+    """A spike vector for the kernels: a contiguous CUDA uint8 (or bool, read
+    as its bytes) tensor of exactly n entries; raises before any launch."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype == torch.bool:
+        t = t.view(torch.uint8)
+    if t.dtype != torch.uint8:
+        raise TypeError(f"{name} must be uint8 or bool (one byte per neuron), got {t.dtype}")
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+    return t.contiguous()
+
+
+def _vec(t, n, dtype, name):
+    """A contiguous CUDA tensor of `dtype` with exactly n entries."""
+    t = _dev(t, dtype, name)
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+    return t
+
+
+def _out(t, n, dtype, device, name="out"):
+    """The caller's output buffer, or a new one."""
+    if t is None:
+        return torch.empty(n, dtype=dtype, device=device)
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous() \
+            or t.numel() != n:
+        raise ValueError(f"{name} must be a contiguous CUDA {dtype} tensor of {n} entries")
+    return t
+
+
+def _csr_args(indptr, indices, data, n_post):
+    indptr = _dev(indptr, torch.int32, "indptr")
+    indices = _dev(indices, torch.int32, "indices")
+    if indptr.dim() != 1 or indptr.numel() < 1:
+        raise ValueError("indptr must be a vector of n_pre + 1 entries")
+    if data is not None:
+        data = _vec(data, indices.numel(), torch.float32, "data")
+    if n_post < 0:
+        raise ValueError("n_post must be >= 0")
+    return indptr, indices, data
+
+
 def max_gap(p):
     """K of the connectivity sampler (Appendix C), -1 for p outside (0, 1]."""
     return int(lib().bp_max_gap(float(p)))
@@ -108,8 +152,12 @@ def _csr_struct(indptr, indices, data, w, n_post, tile_ptr=None, tile_width=0, s
 def event_csr_matvec(indptr, indices, data, w, n_post, events, tile_ptr=None, tile_width=0, sorted_rows=True,
                      out=None, ws=None):
     """y = M^T e over the firing rows (Appendix B).  data None: homogeneous w."""
+    indptr, indices, data = _csr_args(indptr, indices, data, n_post)
+    events = _events(events, indptr.numel() - 1)
+    if tile_ptr is not None:
+        tile_ptr = _dev(tile_ptr, torch.int32, "tile_ptr")
     m = _csr_struct(indptr, indices, data, w, n_post, tile_ptr, tile_width, sorted_rows)
-    y = out if out is not None else torch.empty(n_post, dtype=torch.float32, device=events.device)
+    y = _out(out, n_post, torch.float32, events.device)
     wsb = int(lib().bp_event_csr_ws_bytes(C.byref(m)))
     if ws is None or ws.numel() < wsb:
         ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=events.device)
@@ -125,7 +173,8 @@ def event_csr_ws(indptr, indices, data, w, n_post, tile_ptr=None, tile_width=0, 
 def jit_conn_matvec(conn: JitConn, events, out=None, ws=None):
     """y = M^T e with M regenerated from the seed (Appendix C)."""
     c = conn.c
-    y = out if out is not None else torch.empty(c.n_post, dtype=torch.float32, device=events.device)
+    events = _events(events, c.n_pre)
+    y = _out(out, c.n_post, torch.float32, events.device)
     wsb = int(lib().bp_jit_ws_bytes(C.byref(c)))
     if ws is None or ws.numel() < wsb:
         ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=events.device)
@@ -140,7 +189,7 @@ def jit_conn_matvec_dense(conn: JitConn, v, out=None, ws=None):
     _dev(v, torch.float32, "v")
     if v.numel() != c.n_pre or not v.is_contiguous():
         raise ValueError(f"v must be a contiguous float32 vector of {c.n_pre} entries")
-    y = out if out is not None else torch.empty(c.n_post, dtype=torch.float32, device=v.device)
+    y = _out(out, c.n_post, torch.float32, v.device)
     wsb = int(lib().bp_jit_dense_ws_bytes(C.byref(c)))
     if ws is None or ws.numel() < wsb:
         ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=v.device)
@@ -178,6 +227,9 @@ def jit_ws(conn: JitConn):
 
 def event_csr_backward(indptr, indices, data, w, n_post, events, dy, want_events=True, want_data=True,
                        want_w=True):
+    indptr, indices, data = _csr_args(indptr, indices, data, n_post)
+    events = _events(events, indptr.numel() - 1)
+    dy = _vec(dy, n_post, torch.float32, "dy")
     m = _csr_struct(indptr, indices, data, w, n_post)
     dev = events.device
     d_ev = torch.empty(indptr.numel() - 1, dtype=torch.float32, device=dev) if want_events else None
@@ -191,6 +243,8 @@ def event_csr_backward(indptr, indices, data, w, n_post, events, dy, want_events
 
 def jit_conn_backward(conn: JitConn, events, dy, want_events=True, want_w=True):
     c = conn.c
+    events = _events(events, c.n_pre)
+    dy = _vec(dy, c.n_post, torch.float32, "dy")
     dev = events.device
     d_ev = torch.empty(c.n_pre, dtype=torch.float32, device=dev) if want_events else None
     d_w = torch.empty(2, dtype=torch.float32, device=dev) if want_w else None
@@ -250,19 +304,32 @@ class Net:
         check(lib().bp_net_get_info(self.h, C.byref(i)))
         return i
 
-    def run(self, n_steps, raster=False, counts=True, i_ext=None):
+    def run(self, n_steps, raster=False, counts=True, i_ext=None, counts_out=None):
+        """n_steps steps in one launch; returns (raster or None, counts or
+        None).  counts_out: a caller-allocated int32 buffer of >= n_steps
+        entries to write the per-step spike counts into (nothing allocated)."""
+        if i_ext is not None:
+            i_ext = _vec(i_ext, self.n, torch.float32, "i_ext")
         r = torch.empty((n_steps, self.n), dtype=torch.uint8, device=self.device) if raster else None
-        c = torch.empty(max(n_steps, 1), dtype=torch.int32, device=self.device) if counts else None
+        if counts_out is not None:
+            c = _dev(counts_out, torch.int32, "counts_out")
+            if c.numel() < n_steps or c.data_ptr() != counts_out.data_ptr():
+                raise ValueError(f"counts_out must be a contiguous int32 buffer of >= {n_steps} entries")
+        else:
+            c = torch.empty(max(n_steps, 1), dtype=torch.int32, device=self.device) if counts else None
         check(lib().bp_run(self.h, n_steps, _p(i_ext), _p(r), _p(c), _stream()))
         return r, (c[:n_steps] if c is not None else None)
 
     def step(self, i_ext=None):
+        if i_ext is not None:
+            i_ext = _vec(i_ext, self.n, torch.float32, "i_ext")
         s = torch.empty(self.n, dtype=torch.uint8, device=self.device)
         check(lib().bp_step(self.h, _p(i_ext), _p(s), _stream()))
         return s
 
-    def events(self):
-        out = torch.empty(1, dtype=torch.int64, device=self.device)
+    def events(self, out=None):
+        """Synaptic events delivered since creation (device int64[1])."""
+        out = _out(out, 1, torch.int64, self.device)
         check(lib().bp_net_events(self.h, _p(out), _stream()))
         return out
 
@@ -281,6 +348,10 @@ class Net:
                     s_prev=buf[16 * n:17 * n], raw=buf, step=self.info().step)
 
     def set_state(self, raw, step):
+        raw = _dev(raw, torch.uint8, "raw")
+        nb = int(lib().bp_state_bytes(self.h))
+        if raw.numel() < nb:
+            raise ValueError(f"raw state has {raw.numel()} bytes, expected {nb}")
         check(lib().bp_set_state(self.h, _p(raw), raw.numel(), int(step), _stream()))
 
     def close(self):

@@ -32,22 +32,30 @@ class EventCSRMatvec(torch.autograd.Function):
 
 class JitConnMatvec(torch.autograd.Function):
     """y = M^T e with M regenerated from the seed; gradients for the event
-    values and the two weight parameters."""
+    values and the two weight parameters w01 = (w0, w1).
+
+    The kernels take the weight parameters by value, so they are read on the
+    host: pass w01 as a CPU tensor to keep the call free of device syncs
+    (a device tensor costs one device-to-host copy per call).  The caller's
+    JitConn is not modified; its w0 and w1 are ignored."""
 
     @staticmethod
     def forward(ctx, events, w01, conn: JitConn):
-        conn.c.w0 = float(w01[0])
-        conn.c.w1 = float(w01[1])
-        y = jit_conn_matvec(conn, events)
+        w = w01.detach().to("cpu", torch.float64)
+        c = conn.c
+        local = JitConn(c.n_pre, c.n_post, K=c.max_gap, block=c.block, seed=c.seed, wkind=c.wkind,
+                        w0=float(w[0]), w1=float(w[1]))
+        y = jit_conn_matvec(local, events)
         ctx.save_for_backward(events)
-        ctx.conn = conn
+        ctx.conn = local
+        ctx.w_device = w01.device
         return y
 
     @staticmethod
     def backward(ctx, dy):
         (ev,) = ctx.saved_tensors
         d_ev, d_w = jit_conn_backward(ctx.conn, ev, dy.contiguous())
-        return d_ev, d_w, None
+        return d_ev, d_w.to(ctx.w_device), None
 
 
 class JitConnMatvecDense(torch.autograd.Function):

@@ -56,7 +56,43 @@ struct MvArgs {
   int32_t n_pre, n_post;
   int32_t tile, n_tiles;    // tile width P, number of tiles
   int32_t chunks, chunk_rows;
+  int32_t search;           // sorted CSR without a tile index: find each row's tile segment in the kernel
 };
+
+// Segment [*first, *last) of the sorted row [b, e) whose columns lie in
+// [x0, x1), found by the 16 lanes of one quarter-wave (gl = lane in the group,
+// gshift = first bit of the group in a wave ballot): each round every lane
+// probes one of 16 evenly spaced entries for each bound, so a row of n
+// entries takes about log16(n) rounds of one load per lane and bound.
+// Every lane of the group must call it with the same arguments.
+__device__ __forceinline__ void group_bounds(const int32_t* __restrict__ idx, int32_t b, int32_t e, int32_t x0,
+                                             int32_t x1, int gl, int gshift, int32_t* first, int32_t* last) {
+  int32_t b0 = b, e0 = e, b1 = b, e1 = e;
+  bool d0 = false, d1 = false;
+  while (!(d0 && d1)) {
+    // the answer of bound i lies in [bi, ei]; entries at or past ei are not
+    // below xi (or do not exist)
+    const int32_t n0 = e0 - b0, n1 = e1 - b1;
+    const int32_t s0 = n0 <= 16 ? 1 : (n0 + 15) >> 4, s1 = n1 <= 16 ? 1 : (n1 + 15) >> 4;
+    const int32_t q0 = b0 + (gl + 1) * s0 - 1, q1 = b1 + (gl + 1) * s1 - 1;
+    const bool lt0 = !d0 && q0 < e0 && idx[q0] < x0;
+    const bool lt1 = !d1 && q1 < e1 && idx[q1] < x1;
+    const int c0 = __popc((uint32_t)(__ballot(lt0) >> gshift) & 0xFFFFu);
+    const int c1 = __popc((uint32_t)(__ballot(lt1) >> gshift) & 0xFFFFu);
+    if (!d0) {
+      b0 += c0 * s0;
+      if (s0 == 1) d0 = true;
+      else e0 = min(e0, b0 + s0 - 1);
+    }
+    if (!d1) {
+      b1 += c1 * s1;
+      if (s1 == 1) d1 = true;
+      else e1 = min(e1, b1 + s1 - 1);
+    }
+  }
+  *first = b0;
+  *last = b1;
+}
 
 struct MvShared {
   int ids[kIdCap];
@@ -210,6 +246,10 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
           const int32_t* tp = a.tile_ptr + (size_t)j * (a.n_tiles + 1) + t;
           st = tp[0];
           ln = tp[1] - st;
+        } else if (a.search) {
+          int32_t en;
+          group_bounds(a.indices, a.indptr[j], a.indptr[j + 1], lo, hi, l, lane_id() & ~(kGroup - 1), &st, &en);
+          ln = en - st;
         } else {
           st = a.indptr[j];
           ln = a.indptr[j + 1] - st;
@@ -276,7 +316,10 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
       const uint32_t K = (uint32_t)a.jit.max_gap;
       const int32_t wkind = a.jit.wkind, n_post = a.n_post;
       const float w0 = a.jit.w0, w1 = a.jit.w1;
-      if (B > 0 && nbt == 1 && items * 4 <= kMvThreads) {
+      // the four-lane walk emits every target from the block start, so it
+      // needs the tile to begin there (a block wider than the LDS tile is cut
+      // into several tiles, the later ones starting inside the block)
+      if (B > 0 && nbt == 1 && lo == (int64_t)b_lo * B && items * 4 <= kMvThreads) {
         // Few rows in the pass: four lanes per row.  In pass P lane q draws
         // generator block 4P + q (draws 16P + 4q .. 16P + 4q + 3); a prefix
         // of the lanes' gap sums over the quad places the targets, so a row
@@ -587,6 +630,12 @@ static MvPlan plan_csr(const bp_csr* m) {
   } else if (m->sorted && m->tile_ptr && m->tile_width > 0 && m->tile_width <= kTileMax) {
     p.tile = m->tile_width;
     p.n_tiles = (int32_t)(((int64_t)m->n_post + p.tile - 1) / p.tile);
+  } else if (m->sorted) {
+    // no tile index: equal tiles of at most kTileMax columns, each row's
+    // segment found by a search inside the kernel
+    const int32_t nt = (int32_t)(((int64_t)m->n_post + kTileMax - 1) / kTileMax);
+    p.tile = (int32_t)(((int64_t)m->n_post + nt - 1) / nt);
+    p.n_tiles = (int32_t)(((int64_t)m->n_post + p.tile - 1) / p.tile);
   } else {
     p.atomic_path = true;
     p.ws = (size_t)(m->n_post > 0 ? m->n_post : 1) * sizeof(uint32_t);
@@ -712,7 +761,8 @@ bp_status bp_event_csr_matvec(const bp_csr* m, const uint8_t* events, float* y, 
   }
   MvArgs a{};
   a.indptr = m->indptr; a.indices = m->indices; a.data = m->data;
-  a.tile_ptr = p.n_tiles > 1 ? m->tile_ptr : nullptr;
+  a.tile_ptr = p.n_tiles > 1 && m->tile_ptr && p.tile == m->tile_width ? m->tile_ptr : nullptr;
+  a.search = p.n_tiles > 1 && a.tile_ptr == nullptr;
   a.events = events; a.out = p.chunks > 1 ? ws : (void*)y; a.w = m->w;
   a.n_pre = m->n_pre; a.n_post = m->n_post; a.tile = p.tile; a.n_tiles = p.n_tiles;
   a.chunks = p.chunks; a.chunk_rows = p.chunk_rows;

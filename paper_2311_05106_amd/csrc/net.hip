@@ -39,7 +39,9 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
+#include <unordered_set>
 
 #include "bp_device.h"
 #include "bp_host.h"
@@ -1089,8 +1091,18 @@ struct bp_net_s {
 
 static constexpr uint32_t kNetMagic = 0xB1A1B1A1u;
 
+// Live handles: a handle is dereferenced only after it is found here, so a
+// destroyed (freed) or foreign handle is reported instead of read.
+static std::mutex g_nets_mu;
+static std::unordered_set<const bp_net_s*> g_nets;
+
 static bp_status check_net(bp_net net) {
-  if (!net || net->magic != kNetMagic) return set_error(BP_ESTATE, "invalid or destroyed network handle");
+  bool live;
+  {
+    std::lock_guard<std::mutex> g(g_nets_mu);
+    live = net != nullptr && g_nets.count(net) != 0;
+  }
+  if (!live || net->magic != kNetMagic) return set_error(BP_ESTATE, "invalid or destroyed network handle");
   return BP_OK;
 }
 
@@ -1241,6 +1253,10 @@ bp_status bp_create_net(const bp_net_desc* d, void* ws, size_t bytes, bp_stream 
     if (L.blk && (s = launch_tile_index(indptr, indices, d->n, d->block, L.nb, (int32_t*)(base + L.off_blkptr), st)))
       return fail(s);
   }
+  {
+    std::lock_guard<std::mutex> g(g_nets_mu);
+    g_nets.insert(net);
+  }
   *out = net;
   return BP_OK;
 }
@@ -1327,8 +1343,11 @@ bp_status bp_set_state(bp_net net, const void* src, size_t bytes, int64_t step, 
 }
 
 bp_status bp_destroy_net(bp_net net) {
-  bp_status s = check_net(net);
-  if (s) return s;
+  {
+    std::lock_guard<std::mutex> g(g_nets_mu);
+    if (net == nullptr || g_nets.erase(net) == 0)
+      return set_error(BP_ESTATE, "invalid or destroyed network handle");
+  }
   net->magic = 0;
   delete net;
   return BP_OK;

@@ -98,3 +98,38 @@ def test_net_bytes_scales_linearly_for_jit():
     marginal = (size[800_000] - size[400_000]) / 400_000
     assert marginal < 40
     assert size[800_000] / 800_000 < 50
+
+
+def test_binding_rejects_bad_tensors_before_launch():
+    # host tensors, wrong dtypes and wrong lengths are refused by the binding
+    # before any pointer reaches a kernel (a host pointer in a kernel would
+    # fault the GPU; a float spike vector would be read as bytes)
+    import torch
+    import paper_2311_05106_amd as bp
+    ip = torch.zeros(11, dtype=torch.int32)
+    ix = torch.zeros(0, dtype=torch.int32)
+    ev = torch.zeros(10, dtype=torch.uint8)
+    with pytest.raises(TypeError):
+        bp.event_csr_matvec(ip, ix, None, 1.0, 5, ev)
+    c = bp.JitConn(10, 20, K=5, seed=1)
+    with pytest.raises(TypeError):
+        bp.jit_conn_matvec(c, ev)
+    with pytest.raises(TypeError):
+        bp.jit_conn_backward(c, ev, torch.zeros(20))
+    with pytest.raises(TypeError):
+        bp.event_csr_backward(ip, ix, None, 1.0, 5, ev, torch.zeros(5))
+    with pytest.raises(TypeError):
+        bp.jit_conn_matvec_dense(c, torch.zeros(10))
+
+
+def test_destroyed_net_handle_is_rejected():
+    # a handle that was never created (or was destroyed) is refused without
+    # being read
+    import ctypes as C
+    from paper_2311_05106_amd import _abi
+    L = _abi.lib()
+    fake = C.c_void_p(0x10)
+    assert L.bp_destroy_net(fake) == _abi.BP_ESTATE
+    assert L.bp_destroy_net(None) == _abi.BP_ESTATE
+    assert L.bp_run(fake, 1, None, None, None, None) == _abi.BP_ESTATE
+    assert b"destroyed" in L.bp_last_error()

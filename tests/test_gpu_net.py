@@ -192,3 +192,64 @@ def test_large_jit_net_first_steps(bp, block):
     r, c = net.run(40, raster=True)
     assert first_diff(r.cpu().numpy(), r_ref) is None
     assert int(net.events().item()) == ev_ref
+
+
+def _raw_state(st):
+    return np.concatenate([st.V.view(np.uint8), st.ge.view(np.uint8), st.gi.view(np.uint8),
+                           st.ref.astype(np.int32).view(np.uint8), st.s_prev.astype(np.uint8)])
+
+
+@pytest.mark.parametrize("block", [0, 2560])
+def test_large_jit_net_steady_state(bp, block):
+    # 400k neurons in the regime the benchmark times (after the initial
+    # transient): the oracle's FP32 run of 1000 steps from the initial state
+    # equals the GPU's run bit for bit (state at step 1000), and from the
+    # oracle's state at step 1000 the net (given that state with
+    # bp_set_state) and the oracle step 100 more steps with identical rasters,
+    # event counts and final states.
+    n = 400_000
+    print(f"steady-state 400k net, block {block}", flush=True)
+    P, net, _, _ = make(bp, n, 80 / n, O.CONN_JIT, block, seed=0)
+    st = O.NetState(P)
+    _, c_ref, _ = O.net_run(P, st, 1000, want_raster=False, parallel=True)
+    _, c = net.run(1000, counts=True)
+    np.testing.assert_array_equal(c.cpu().numpy(), c_ref)
+    g = net.get_state()
+    np.testing.assert_array_equal(g["raw"].cpu().numpy(), _raw_state(st))
+    # steady state: well below the transient's rates, about 2 spikes per ms per 100 neurons
+    assert 200 < c_ref[-100:].mean() < 2000
+    P2, net2, _, _ = make(bp, n, 80 / n, O.CONN_JIT, block, seed=0)
+    net2.set_state(torch.from_numpy(_raw_state(st)).cuda(), 1000)
+    ev0 = int(net2.events().item())
+    r_ref, c2_ref, ev_ref = O.net_run(P, st, 100, parallel=True)
+    r, c2 = net2.run(100, raster=True)
+    assert first_diff(r.cpu().numpy(), r_ref) is None
+    np.testing.assert_array_equal(c2.cpu().numpy(), c2_ref)
+    assert int(net2.events().item()) - ev0 == ev_ref
+    np.testing.assert_array_equal(net2.get_state()["raw"].cpu().numpy(), _raw_state(st))
+    assert net2.info().step == 1100
+    net.close()
+    net2.close()
+
+
+def test_destroy_twice_is_rejected(bp):
+    from paper_2311_05106_amd import _abi
+    _, net, _, _ = make(bp, 2000, 0.02, O.CONN_JIT, 0, seed=1)
+    h = net.h
+    assert _abi.lib().bp_destroy_net(h) == _abi.BP_OK
+    assert _abi.lib().bp_destroy_net(h) == _abi.BP_ESTATE
+    assert _abi.lib().bp_run(h, 1, None, None, None, None) == _abi.BP_ESTATE
+    net.h = None
+
+
+def test_net_inputs_are_validated(bp):
+    _, net, _, _ = make(bp, 2000, 0.02, O.CONN_JIT, 0, seed=1)
+    with pytest.raises(ValueError):
+        net.run(5, i_ext=torch.zeros(1999, device="cuda"))
+    with pytest.raises(TypeError):
+        net.run(5, i_ext=torch.zeros(2000))
+    with pytest.raises(ValueError):
+        net.set_state(torch.zeros(10, dtype=torch.uint8, device="cuda"), 0)
+    with pytest.raises(TypeError):
+        net.set_state(torch.zeros(2000 * 17, dtype=torch.uint8), 0)
+    net.close()

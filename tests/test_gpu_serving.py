@@ -67,3 +67,26 @@ def test_plain_path_matches_event_totals(mods):
     ea = {r["id"]: r["events"] for r in a["records"]}
     eb = {r["id"]: r["events"] for r in b["records"]}
     assert ea == eb
+
+
+def test_served_requests_match_the_oracle(mods):
+    # three requests served in the mix (stored COBA, stored CUBA, JIT COBA of
+    # 60,000 neurons) against the oracle's FP32 recursion of the same net:
+    # per-step spike counts and event totals identical
+    import oracle as O
+    bp, sv = mods
+    reqs = requests()
+    res = sv.serve_batched(reqs, hbm_budget=64 << 20, quantum=170, max_wgs=16, record_counts=True)
+    recs = {r["id"]: r for r in res["records"]}
+    fields = [f for f, _ in O.NetParams._fields_]
+    for i in (0, 1, 5):
+        r = reqs[i]
+        d = sv.request_desc(r, max_wgs=16)
+        P = O.net_params(**{f: getattr(d, f) for f in fields})
+        ip = ix = None
+        if d.conn == bp.CONN_CSR:
+            ip, ix = O.csr_build(d.seed, d.max_gap, d.n, d.n, d.block)
+        _, c_ref, ev_ref = O.net_run(P, O.NetState(P), r["steps"], ip, ix, want_raster=False, parallel=True)
+        assert c_ref.sum() > 0
+        np.testing.assert_array_equal(recs[i]["counts"], c_ref)
+        assert recs[i]["events"] == ev_ref
