@@ -2,18 +2,23 @@
 
 Headline workload: the COBA E/I LIF network scaled to 400,000 neurons
 (320,000 excitatory / 80,000 inhibitory), fixed-probability connectivity
-p = 80/N regenerated every step from the seed (JIT, post blocks of 2560),
-w_e = 0.6, w_i = 6.7, tau_e = 5 ms, tau_i = 10 ms, V_rest = -60 mV,
-V_th = -50 mV, refractory 5 ms, V0 ~ U(-60, -50) mV, I_ext = 20, dt = 0.1 ms,
-FP32 state.  One bench step = one simulation time step; the default K =
-10,000 steps is one simulated second, run as ten persistent-kernel launches
-of 1,000 steps on the same net after W warm-up steps.
+p = 80/N regenerated every step from the seed (JIT; one block per row, the
+paper's per-row gap sequence), w_e = 0.6, w_i = 6.7, tau_e = 5 ms,
+tau_i = 10 ms, V_rest = -60 mV, V_th = -50 mV, refractory 5 ms,
+V0 ~ U(-60, -50) mV, I_ext = 20, dt = 0.1 ms, FP32 state.  One bench step =
+one persistent-kernel launch of 1000 simulation steps (0.1 s simulated) on
+the same net, after W >= 1 warm-up launches (the initial transient); the
+default K = 10 timed launches are one simulated second.
 
-value = synaptic events delivered per wall second (sum over steps of the row
-lengths of the rows that fired the step before).  Also printed: simulated
-seconds per wall second, the state-streaming roofline of the network kernel,
-the oracle timed on the host cores on a bounded sample, and the operator
-sweep (event CSR / JIT matvec at 0.1 %, 1 %, 10 % firing, n = 1e5, p = 0.01).
+value = synaptic events delivered per wall second (sum over simulation steps
+of the row lengths of the rows that fired the step before).  Also printed:
+simulated seconds per wall second, the state-streaming roofline of the
+network kernel, the oracle timed on the host cores on the same window
+(started from the GPU's state, its spike counts checked against the GPU's),
+and extras: the same net with blocked connectivity, the 4000-neuron net, the
+operator sweep (event CSR / JIT matvec at 0.1 %, 1 %, 10 % firing,
+n = 1e5, p = 0.01), the dense-vector JIT products, the SNN training step and
+serving.
 """
 import argparse
 import hashlib
@@ -34,7 +39,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-C2_BLOCK = 2560
+C2_BLOCK = 0  # the headline net: one block per row, the paper's per-row sequence
+C2_BLOCKED = 2560  # the extra: rows restarted in post blocks of 2560 columns (one per workgroup)
 
 
 def c2_desc(bp, n=400_000, seed=0, block=None):
@@ -69,58 +75,108 @@ def counters_traffic(kernel_file, key, per_launch_units, block=None):
         return None
 
 
-LAUNCH_STEPS = 1000  # steps per persistent-kernel launch (0.1 s simulated)
+LAUNCH_STEPS = 1000  # simulation steps per bench step: one persistent-kernel launch (0.1 s simulated)
 
 
 def bench_network(bp, torch, steps, warmup, block=None):
-    """W warm-up steps, then K timed steps of the same net, both in launches
-    of LAUNCH_STEPS (state stays on the device between launches).  Each timed
-    launch is bracketed by HIP events on the stream it runs on."""
+    """max(W, 1) warm-up launches of LAUNCH_STEPS steps (the initial transient
+    is over after the first), then K timed launches of the same net, one per
+    bench step; the state stays on the device throughout.  Every buffer is
+    allocated before the first event; each launch is bracketed by HIP events
+    on the stream it runs on."""
     d = c2_desc(bp, block=block)
     net = bp.Net(d)
-    left = warmup
-    while left > 0:
-        k = min(LAUNCH_STEPS, left)
-        net.run(k, counts=False)
-        left -= k
-    torch.cuda.synchronize()
-    ev0 = int(net.events().item())
-    torch.cuda.synchronize()
+    warm = max(warmup, 1)
+    for _ in range(warm):
+        net.run(LAUNCH_STEPS, counts=False)
     stream = torch.cuda.current_stream()
-    marks, counts = [], []
+    counts = torch.empty((steps, LAUNCH_STEPS), dtype=torch.int32, device="cuda")
+    ev_before = torch.empty(1, dtype=torch.int64, device="cuda")
+    ev_after = torch.empty(1, dtype=torch.int64, device="cuda")
+    marks = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    net.events(out=ev_before)
+    state0 = net.get_state()  # the state at the start of the timed window (CPU baseline)
+    step0 = int(state0["step"])
+    raw0 = state0["raw"].cpu()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    left = steps
-    while left > 0:
-        k = min(LAUNCH_STEPS, left)
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for i in range(steps):
+        a, b = marks[i]
         a.record(stream)
-        counts.append(net.run(k, counts=True)[1])
+        net.run(LAUNCH_STEPS, counts_out=counts[i])
         b.record(stream)
-        marks.append((a, b, k))
-        left -= k
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    launch_ms = [a.elapsed_time(b) for a, b, _ in marks]
-    events = int(net.events().item()) - ev0
-    spikes = int(sum(int(c.sum().item()) for c in counts))
-    assert net.error_flag() == 0, "network kernel gave up waiting"
+    net.events(out=ev_after)
+    launch_ms = [a.elapsed_time(b) for a, b in marks]
+    events = int(ev_after.item()) - int(ev_before.item())
+    counts_h = counts.cpu().numpy()
+    err = net.error_flag()
     info = net.info()
-    return dict(wall=wall, launch_ms=launch_ms, launch_steps=[k for _, _, k in marks], events=events, spikes=spikes,
-                n=d.n, n_wg=info.n_wg, range=info.wg_range, dt_ms=d.dt)
+    net.close()
+    assert err == 0, "network kernel gave up waiting"
+    return dict(wall=wall, launch_ms=launch_ms, events=events, spikes=int(counts_h.sum()), counts=counts_h,
+                n=d.n, n_wg=info.n_wg, range=info.wg_range, dt_ms=d.dt, block=d.block, warmup_launches=warm,
+                step0=step0, raw0=raw0)
 
 
-def oracle_sample(steps):
+def oracle_window(r, min_seconds=10.0, single_steps=200):
+    """The oracle on the benchmark's own window: started from the GPU's state
+    at the first timed step, the OpenMP build of the FP32 network loops on
+    every host core runs until about min_seconds of CPU work are done; the
+    plain build (one thread) runs the first single_steps steps.  Both must
+    reproduce the GPU's spike counts of those steps exactly."""
+    import numpy as np
     import oracle as O
-    n = 400_000
-    P = O.net_params(model=0, n=n, n_exc=int(0.8 * n), conn=1, max_gap=O.max_gap(80.0 / n), block=C2_BLOCK, seed=0,
-                     w_exc=0.6, w_inh=6.7, tau_m=20.0, tau_e=5.0, tau_i=10.0, tau_ref=5.0, v_rest=-60.0,
+    n = r["n"]
+    P = O.net_params(model=0, n=n, n_exc=int(0.8 * n), conn=1, max_gap=O.max_gap(80.0 / n), block=r["block"],
+                     seed=0, w_exc=0.6, w_inh=6.7, tau_m=20.0, tau_e=5.0, tau_i=10.0, tau_ref=5.0, v_rest=-60.0,
                      v_th=-50.0, v_reset=-60.0, e_exc=0.0, e_inh=-80.0, r=1.0, i_ext=20.0, dt=0.1, v0_lo=-60.0,
                      v0_hi=-50.0)
-    st = O.NetState(P)
+    raw = r["raw0"].numpy()
+
+    def state():
+        st = O.NetState(P)
+        st.V = raw[0:4 * n].view(np.float32).copy()
+        st.ge = raw[4 * n:8 * n].view(np.float32).copy()
+        st.gi = raw[8 * n:12 * n].view(np.float32).copy()
+        st.ref = raw[12 * n:16 * n].view(np.int32).copy()
+        st.s_prev = raw[16 * n:17 * n].copy()
+        st.t = r["step0"]
+        return st
+
+    gpu_counts = r["counts"].reshape(-1)
+    threads = O.set_threads(0)
+    st = state()
+    done, ev, sec, match = 0, 0, 0.0, True
+    while sec < min_seconds and done + 100 <= gpu_counts.size:
+        t0 = time.perf_counter()
+        _, c, e = O.net_run(P, st, 100, want_raster=False, parallel=True)
+        sec += time.perf_counter() - t0
+        match = match and bool(np.array_equal(c, gpu_counts[done:done + 100]))
+        done += 100
+        ev += e
+    st1 = state()
+    k = min(single_steps, gpu_counts.size)
     t0 = time.perf_counter()
-    _, counts, events = O.net_run(P, st, steps, want_raster=False)
-    dt = time.perf_counter() - t0
-    return dict(value=events / dt, events=events, seconds=dt, spikes=int(counts.sum()))
+    _, c1, e1 = O.net_run(P, st1, k, want_raster=False)
+    sec1 = time.perf_counter() - t0
+    match1 = bool(np.array_equal(c1, gpu_counts[:k]))
+    return dict(value=ev / sec, threads=threads, steps=done, seconds=sec, events=ev, counts_match=match,
+                single_value=e1 / sec1, single_steps=k, single_seconds=sec1, single_counts_match=match1)
+
+
+def host_cpu():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return dict(nproc=os.cpu_count(), model=model)
 
 
 def bench_c0(bp, torch, reps=5):
@@ -265,8 +321,9 @@ def bench_dense(bp, torch, calls=640):
         b.record()
         torch.cuda.synchronize()
         us = a.elapsed_time(b) * 1e3 / (reps * 8)
-        # CSR-equivalent bytes: what a stored matrix would stream (4 B index + 4 B weight per synapse)
-        gbs = 8.0 * nnz / (us * 1e-6) / 1e9
+        # CSR-equivalent bytes: what a stored matrix would stream per synapse
+        # (4 B index, plus 4 B weight unless the weights are homogeneous)
+        gbs = (4.0 if wk == bp.W_HOMO else 8.0) * nnz / (us * 1e-6) / 1e9
         out.append(dict(op=f"jit_dense_{name}", block=DENSE_OP_BLOCK, us_per_call=us, synapses=nnz,
                         synapses_per_s=nnz / (us * 1e-6),
                         csr_equiv_GBps=gbs, csr_equiv_frac=gbs / HBM_PEAK_GBS))
@@ -364,11 +421,13 @@ def bench_serving(bp, torch, n_requests=100, rate_hz=20.0, budget_gib=1.0, quant
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10000)
-    ap.add_argument("--warmup", type=int, default=1000)
-    ap.add_argument("--oracle-steps", type=int, default=300)
+    ap.add_argument("--steps", type=int, default=10,
+                    help=f"timed bench steps, each one launch of {LAUNCH_STEPS} simulation steps")
+    ap.add_argument("--warmup", type=int, default=2, help="warm-up launches (at least one is run)")
+    ap.add_argument("--oracle-seconds", type=float, default=10.0,
+                    help="CPU seconds of the OpenMP oracle on the timed window")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--block", type=int, default=C2_BLOCK, help="post-block width of the JIT connectivity")
+    ap.add_argument("--block", type=int, default=C2_BLOCK, help="post-block width of the headline net's connectivity")
     ap.add_argument("--calls", type=int, default=10000, help="products per point of the operator sweep")
     ap.add_argument("--ops-frac", type=float, default=None,
                     help="run the operator sweep at this firing fraction only (for profiling)")
@@ -397,42 +456,57 @@ def main():
 
     r = bench_network(bp, torch, args.steps, args.warmup)
     steps = args.steps
+    sim_steps = steps * LAUNCH_STEPS
     value = r["events"] / r["wall"]
     ms_per_step = r["wall"] * 1e3 / steps
-    sim_s = steps * r["dt_ms"] * 1e-3
-    # state-streaming roofline of the network kernel: per neuron and step the
-    # state V, g_e, g_i (3 x 4 B) and the refractory counter (1 B) read and
-    # written once (26 B) plus the spike flag written and read once (2 B) =
-    # 28 B, plus 8 B per spike (compacted id stored, then loaded by the owners
-    # of its targets).
-    launches = len(r["launch_ms"])
-    alg_bytes = (28.0 * r["n"] * steps + 8.0 * r["spikes"]) / launches  # per launch
-    launch_s = sum(r["launch_ms"]) / launches * 1e-3  # average launch duration
+    # state-streaming roofline of the network kernel: per neuron and
+    # simulation step the state V, g_e, g_i (3 x 4 B) and the refractory
+    # counter (1 B) read and written once (26 B) plus the spike flag written
+    # and read once (2 B) = 28 B, plus 8 B per spike (compacted id stored,
+    # then loaded by the owners of its targets).  One launch = LAUNCH_STEPS
+    # steps of all n neurons.
+    alg_bytes = (28.0 * r["n"] * sim_steps + 8.0 * r["spikes"]) / steps  # per launch
+    launch_s = sum(r["launch_ms"]) / steps * 1e-3  # average launch duration
     achieved = alg_bytes / launch_s / 1e9
-    traffic = counters_traffic("net.hip", "net_run_k_coba400k_jit", steps / launches, block=C2_BLOCK)
+    traffic = counters_traffic("net.hip", "net_run_k_coba400k_jit", LAUNCH_STEPS, block=r["block"])
     roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
                     traffic=traffic, kernel="net_run_k", alg_bytes_per_launch=alg_bytes,
-                    launch_ms=launch_s * 1e3, launches=launches, steps_per_launch=LAUNCH_STEPS)
-    orc = oracle_sample(args.oracle_steps)
-    cpu = dict(value=orc["value"], unit="synaptic events/s", cores=1, kind="oracle",
-               sample=f"first {args.oracle_steps} of the {steps} steps of the same 400k-neuron net, "
-                      f"FP32 C oracle, single thread ({orc['seconds']:.1f} s)")
+                    launch_ms=launch_s * 1e3, launches=steps, steps_per_launch=LAUNCH_STEPS,
+                    us_per_sim_step=launch_s * 1e6 / LAUNCH_STEPS)
+    orc = oracle_window(r, min_seconds=args.oracle_seconds)
+    cpu = dict(value=orc["value"], unit="synaptic events/s", cores=orc["threads"], kind="oracle",
+               sample=f"simulation steps {r['step0']}..{r['step0'] + orc['steps'] - 1} of the timed window "
+                      f"(started from the GPU's state at its first step), FP32 oracle network loops built with "
+                      f"OpenMP on {orc['threads']} threads, {orc['seconds']:.1f} s; spike counts equal to the "
+                      f"GPU's: {orc['counts_match']}",
+               single_thread=dict(value=orc["single_value"], steps=orc["single_steps"],
+                                  seconds=orc["single_seconds"], counts_match=orc["single_counts_match"]),
+               host=host_cpu())
     line = dict(metric=METRIC, value=value, unit="synaptic events/s", n_gpus=1, steps=steps, warmup=args.warmup,
                 ms_per_step=ms_per_step, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
                 data="synthetic",
-                config=dict(workload="COBA E/I LIF 400k (320k E / 80k I), JIT connectivity p=80/N blocks of "
-                                     f"{C2_BLOCK}, 10,000 steps dt=0.1 ms", n=r["n"], workgroups=r["n_wg"],
-                            neurons_per_workgroup=r["range"], parallelism="1 GPU"),
-                sim_s_per_wall_s=sim_s / r["wall"], us_per_step=r["wall"] * 1e6 / steps,
-                spikes_per_step=r["spikes"] / steps, mean_rate_hz=r["spikes"] / steps / r["n"] / (r["dt_ms"] * 1e-3),
-                events_per_step=r["events"] / steps, roofline=roofline, cpu_baseline=cpu)
+                config=dict(workload=f"COBA E/I LIF 400k (320k E / 80k I), JIT connectivity p=80/N regenerated "
+                                     f"every step, one block per row (the paper's per-row gap sequence), dt=0.1 ms; "
+                                     f"one bench step = one persistent launch of {LAUNCH_STEPS} simulation steps; "
+                                     f"{r['warmup_launches']} warm-up launches, then {steps} timed launches = "
+                                     f"{sim_steps} simulation steps ({sim_steps * r['dt_ms'] * 1e-3:g} s simulated) "
+                                     f"starting at step {r['step0']}",
+                            n=r["n"], block=r["block"], workgroups=r["n_wg"], neurons_per_workgroup=r["range"],
+                            parallelism="1 GPU"),
+                sim_steps=sim_steps, sim_s_per_wall_s=sim_steps * r["dt_ms"] * 1e-3 / r["wall"],
+                us_per_sim_step=r["wall"] * 1e6 / sim_steps,
+                spikes_per_sim_step=r["spikes"] / sim_steps,
+                mean_rate_hz=r["spikes"] / sim_steps / r["n"] / (r["dt_ms"] * 1e-3),
+                events_per_sim_step=r["events"] / sim_steps, roofline=roofline, cpu_baseline=cpu)
     if not args.no_extra:
-        w = bench_network(bp, torch, 2000, 1000, block=0)
-        line["c2_whole_rows"] = dict(
-            workload="the same 400k net with the connectivity of one block per row (the paper's per-row gap "
-                     "sequence), spikes exchanged as their targets; 1000 warm-up + 2000 timed steps",
-            workgroups=w["n_wg"], us_per_step=w["wall"] * 1e6 / 2000, synaptic_events_per_s=w["events"] / w["wall"],
-            sim_s_per_wall_s=2000 * w["dt_ms"] * 1e-3 / w["wall"])
+        w = bench_network(bp, torch, 4, 1, block=C2_BLOCKED)
+        line["c2_blocked"] = dict(
+            workload=f"the same 400k net with connectivity restarted in post blocks of {C2_BLOCKED} columns "
+                     "(a different random graph of the same statistics), spike ids exchanged; 1 warm-up + 4 "
+                     f"timed launches of {LAUNCH_STEPS} steps",
+            workgroups=w["n_wg"], us_per_sim_step=w["wall"] * 1e6 / (4 * LAUNCH_STEPS),
+            launch_ms=sum(w["launch_ms"]) / 4, synaptic_events_per_s=w["events"] / w["wall"],
+            sim_s_per_wall_s=4 * LAUNCH_STEPS * w["dt_ms"] * 1e-3 / w["wall"])
         line["c0"] = bench_c0(bp, torch)
         line["operator_sweep"] = bench_ops(bp, torch, calls=args.calls)
         line["jit_dense_vector"] = bench_dense(bp, torch)
