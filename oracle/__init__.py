@@ -261,8 +261,10 @@ def jit_matmat_dense(seed, K, B, wkind, w0, w1, n_post, X):
 
 
 def jit_abs_terms(seed, K, B, wkind, w0, w1, n_post, X):
-    """Sum of |w_jk| |X[j, c]| over rows j, the magnitude of the terms of
-    J^T X (tolerance scale of FP32 sums).  X: a vector (spike bytes as 0/1,
+    """Sum of (|a_jk| + |b_jk|) |X[j, c]| over rows j, with w_jk = a_jk + b_jk
+    the two terms of the weight formula (a = w0; b = w1 z normal, (w1 - w0) u
+    uniform, 0 homogeneous): the magnitude of the terms of J^T X, the
+    tolerance scale of FP32 weights and sums.  X: a vector (spike bytes as 0/1,
     or floats) or a [n_pre, m] matrix; the result has the same rank."""
     XX = np.asarray(X)
     vec = XX.ndim == 1

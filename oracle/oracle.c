@@ -368,11 +368,15 @@ void or_jit_matmat_dense(uint64_t seed, int32_t K, int32_t B, int32_t wkind, dou
 }
 
 /* Sum of the magnitudes of the terms of the batched product:
- * S[k][c] = sum over rows j of |w_jk| |X[j][c]|, X row-major [n_pre][m].
- * FP32 sums of the terms w_jk X[j][c] differ from the exact sum by a
- * multiple of the unit roundoff times this sum, so parity tolerances are
- * stated relative to it.  m = 1 serves the single-vector products (X = v,
- * or the spike vector as 0/1). */
+ * S[k][c] = sum over rows j of (|a_jk| + |b_jk|) |X[j][c]|, X row-major
+ * [n_pre][m], where w_jk = a_jk + b_jk are the two terms of the weight
+ * formula (Section 5.2's distributions): a = w0, b = w1 z (normal),
+ * b = (w1 - w0) u (uniform), b = 0 (homogeneous).  An FP32 evaluation of the
+ * weight errs by a multiple of the unit roundoff times |a| + |b| (more than
+ * |w| times it when the two terms cancel), and FP32 sums of the products
+ * w_jk X[j][c] by a multiple of it times the sum of their magnitudes, so
+ * parity tolerances are stated relative to S.  m = 1 serves the
+ * single-vector products (X = v, or the spike vector as 0/1). */
 void or_jit_abs_terms(uint64_t seed, int32_t K, int32_t B, int32_t wkind, double w0, double w1,
                       int32_t n_pre, int32_t n_post, int32_t m, const double* X, double* S) {
   int32_t* buf = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_post > 0 ? n_post : 1));
@@ -383,7 +387,10 @@ void or_jit_abs_terms(uint64_t seed, int32_t K, int32_t B, int32_t wkind, double
     for (int32_t b = 0; b < nb; ++b) {
       int64_t cnt = or_row_block(seed, K, n_post, B, j, b, buf);
       for (int64_t t = 0; t < cnt; ++t) {
-        const double w = fabs(or_jit_weight(seed, wkind, w0, w1, j, b, t, NULL));
+        double unit = 0.0;
+        (void)or_jit_weight(seed, wkind, w0, w1, j, b, t, &unit);
+        const double tb = wkind == OR_W_NORMAL ? w1 * unit : wkind == OR_W_UNIFORM ? (w1 - w0) * unit : 0.0;
+        const double w = fabs(w0) + fabs(tb);
         for (int32_t c = 0; c < m; ++c) S[(size_t)buf[t] * m + c] += w * fabs(x[c]);
       }
     }

@@ -164,26 +164,41 @@ def test_jit_dense_matrix_bruteforce(wkind):
 
 @pytest.mark.parametrize("wkind", [O.W_HOMO, O.W_NORMAL, O.W_UNIFORM])
 def test_jit_abs_terms_bruteforce(wkind):
-    # the tolerance scale of the FP32 products: sum over rows of |w_jk| |x_j|
-    # equals |D|^T |X| for the dense matrix assembled entry by entry, and the
-    # product itself when every weight and every x is non-negative
+    # the tolerance scale of the FP32 products: with each weight split into
+    # the two terms of its formula, w = a + b (a = w0; b = w1 z normal,
+    # (w1 - w0) u uniform, 0 homogeneous), the scale equals
+    # (|A| + |B|)^T |X| for the two term matrices assembled entry by entry;
+    # it is at least |D|^T |X| (D = A + B), and equals the product itself
+    # when every term and every x is non-negative
     seed, K, n_pre, n_post, B, m = 9, 5, 40, 66, 16, 3
     w0, w1 = {O.W_HOMO: (-0.3, 0.0), O.W_NORMAL: (0.1, 1.0), O.W_UNIFORM: (-1.0, 2.0)}[wkind]
     D = np.zeros((n_pre, n_post))
+    TA = np.zeros((n_pre, n_post))
+    TB = np.zeros((n_pre, n_post))
     for j in range(n_pre):
         for b in range(-(-n_post // B)):
             for t, k in enumerate(O.row_block(seed, K, n_post, B, j, b)):
-                D[j, k] += O.jit_weight(seed, wkind, w0, w1, j, b, t)[0]
+                w, unit = O.jit_weight(seed, wkind, w0, w1, j, b, t)
+                D[j, k] += w
+                TA[j, k] += abs(w0)
+                if wkind == O.W_NORMAL:
+                    TB[j, k] += abs(w1 * unit)
+                elif wkind == O.W_UNIFORM:
+                    TB[j, k] += abs((w1 - w0) * unit)
     assert (D < 0).any()
+    np.testing.assert_allclose(D, np.where(TA > 0, D, 0.0))  # every weight sits on a connection
     X = np.stack([S.dense_vector(n_pre, 70 + c, zero_frac=0.3) for c in range(m)], 1).astype(np.float64)
-    np.testing.assert_allclose(O.jit_abs_terms(seed, K, B, wkind, w0, w1, n_post, X), np.abs(D).T @ np.abs(X),
-                               rtol=1e-12, atol=1e-12)
+    sc = O.jit_abs_terms(seed, K, B, wkind, w0, w1, n_post, X)
+    np.testing.assert_allclose(sc, (TA + TB).T @ np.abs(X), rtol=1e-12, atol=1e-12)
+    assert np.all(sc >= np.abs(D).T @ np.abs(X) - 1e-12)
     e = S.events(n_pre, 0.4, 3)
-    np.testing.assert_allclose(O.jit_abs_terms(seed, K, B, wkind, w0, w1, n_post, e), np.abs(D).T @ e,
+    np.testing.assert_allclose(O.jit_abs_terms(seed, K, B, wkind, w0, w1, n_post, e), (TA + TB).T @ e,
                                rtol=1e-12, atol=1e-12)
     np.testing.assert_allclose(O.jit_abs_terms(seed, K, B, O.W_UNIFORM, 0.5, 2.0, n_post, np.abs(X)),
                                O.jit_matmat_dense(seed, K, B, O.W_UNIFORM, 0.5, 2.0, n_post, np.abs(X)),
                                rtol=1e-12, atol=1e-12)
+    if wkind == O.W_HOMO:
+        np.testing.assert_allclose(sc, np.abs(D).T @ np.abs(X), rtol=1e-12, atol=1e-12)
 
 
 def test_jit_normal_weights_are_normal():
