@@ -163,6 +163,24 @@ size_t bp_event_csr_ws_bytes(const bp_csr* m);
 bp_status bp_event_csr_matvec(const bp_csr* m, const uint8_t* events, float* y, void* ws, size_t ws_bytes,
                               bp_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * bp_event_csr_matvec with no workspace argument, same kernels and results.
+ * Its scratch (row-chunk partials, or the accumulators of the device-atomic
+ * path) is a static device array of BP_STATIC_SCRATCH_BYTES inside the
+ * library; each GPU the library runs on holds its own copy until the process
+ * ends.  The call allocates nothing (no hipMalloc, hipFree or allocating
+ * library routine); the first call on a device looks up the array's address
+ * there (with that device current) and caches it.  BP_EINVAL, before any
+ * device work, when bp_event_csr_ws_bytes(m) exceeds BP_STATIC_SCRATCH_BYTES
+ * (for sorted rows with a tile index, about n_post <= 60,000 x 32 row chunks
+ * of FP32 partials; homogeneous weights need half).  Every call on one GPU
+ * shares that GPU's array and leaves the last call's partials in it: calls
+ * that overlap on one GPU (several streams or threads) race and must be
+ * serialized by the caller.  Nothing in the array needs to start at zero. */
+#define BP_STATIC_SCRATCH_BYTES ((size_t)16 << 20)
+bp_status bp_event_csr_matvec_noalloc(const bp_csr* m, const uint8_t* events, float* y, bp_stream stream);
+
 /* Reverse mode of y = M^T e for an upstream gradient dy (device float[n_post]):
  *   d_events[j] = sum over row j of M[j,k] dy[k]            (every row)
  *   d_data[idx] = (e[j] != 0) * dy[indices[idx]]             (zero off firing rows)

@@ -16,6 +16,7 @@ from ._abi import (COBA, CONN_CSR, CONN_JIT, CUBA, STREAM_CONN, STREAM_V0, STREA
 
 __all__ = [
     "lib", "BpError", "max_gap", "hash_words", "csr_build", "csr_tile_index", "compact", "event_csr_matvec",
+    "event_csr_matvec_noalloc",
     "jit_conn_matvec", "jit_conn_matvec_dense", "jit_conn_matmat_dense", "event_csr_backward", "jit_conn_backward", "Net", "run_batch", "JitConn",
     "COBA", "CUBA", "CONN_CSR", "CONN_JIT", "W_HOMO", "W_NORMAL", "W_UNIFORM",
 ]
@@ -162,6 +163,23 @@ def event_csr_matvec(indptr, indices, data, w, n_post, events, tile_ptr=None, ti
     if ws is None or ws.numel() < wsb:
         ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=events.device)
     check(lib().bp_event_csr_matvec(C.byref(m), _p(events), _p(y), _p(ws), wsb, _stream()))
+    return y
+
+
+def event_csr_matvec_noalloc(indptr, indices, data, w, n_post, events, out, tile_ptr=None, tile_width=0,
+                             sorted_rows=True):
+    """event_csr_matvec into the caller's `out` with the library's static
+    scratch in place of a workspace: allocates nothing (for graph capture and
+    callers that cannot allocate).  Calls that overlap on one GPU race."""
+    indptr, indices, data = _csr_args(indptr, indices, data, n_post)
+    events = _events(events, indptr.numel() - 1)
+    if tile_ptr is not None:
+        tile_ptr = _dev(tile_ptr, torch.int32, "tile_ptr")
+    m = _csr_struct(indptr, indices, data, w, n_post, tile_ptr, tile_width, sorted_rows)
+    if out is None:
+        raise ValueError("out is required (the call allocates nothing)")
+    y = _out(out, n_post, torch.float32, events.device)
+    check(lib().bp_event_csr_matvec_noalloc(C.byref(m), _p(events), _p(y), _stream()))
     return y
 
 

@@ -6,6 +6,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbpmi.so")
 
 BP_OK, BP_EINVAL, BP_ENOMEM, BP_EDEVICE, BP_ESTATE, BP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+STATIC_SCRATCH_BYTES = 16 << 20  # BP_STATIC_SCRATCH_BYTES
 W_HOMO, W_NORMAL, W_UNIFORM = 0, 1, 2
 STREAM_CONN, STREAM_W, STREAM_V0 = 1, 2, 3
 COBA, CUBA = 0, 1
@@ -63,6 +64,7 @@ SIGNATURES = {
     "bp_csr_tile_index": (_i32, [_vp, _vp, _i32, _i32, _i32, _vp, _vp]),
     "bp_event_csr_ws_bytes": (_sz, [C.POINTER(Csr)]),
     "bp_event_csr_matvec": (_i32, [C.POINTER(Csr), _vp, _vp, _vp, _sz, _vp]),
+    "bp_event_csr_matvec_noalloc": (_i32, [C.POINTER(Csr), _vp, _vp, _vp]),
     "bp_event_csr_backward": (_i32, [C.POINTER(Csr), _vp, _vp, _vp, _vp, _vp, _vp]),
     "bp_jit_ws_bytes": (_sz, [C.POINTER(JitConn)]),
     "bp_jit_conn_matvec": (_i32, [C.POINTER(JitConn), _vp, _vp, _vp, _sz, _vp]),

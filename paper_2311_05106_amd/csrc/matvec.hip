@@ -25,6 +25,8 @@
 //   pass lists at most 256 rows; the tile is one block, so no lane generates
 //   targets outside its tile, and with enough blocks to cover the chip no
 //   row chunks (and no partials) are used.
+#include <mutex>
+
 #include "bp_device.h"
 #include "bp_host.h"
 
@@ -705,6 +707,49 @@ static bp_status finish_partials(const MvPlan& p, bool homo, void* ws, int32_t n
   return BP_OK;
 }
 
+// ---------------------------------------------------------------- static scratch
+// The scratch of the allocation-free entry point: a file-scope device array
+// (each GPU the library runs on holds its own copy until the process ends).
+// In host code its name is only a host-side stand-in; the device address of
+// each GPU's copy comes from hipGetSymbolAddress with that GPU current, is
+// kept per device, and is the only way host code refers to the array.
+constexpr size_t kStaticScratchBytes = (size_t)16 << 20;
+static_assert(kStaticScratchBytes == BP_STATIC_SCRATCH_BYTES, "static scratch size");
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+// Device address of the static scratch on the GPU that runs `st`, looked up
+// once per device (with that device current) and cached.
+static bp_status static_scratch(hipStream_t st, void** out) {
+  int dev = 0;
+  if (st) {
+    BP_HIP(hipStreamGetDevice(st, &dev));
+  } else {
+    BP_HIP(hipGetDevice(&dev));
+  }
+  if (dev < 0 || dev >= kMaxDevices) return set_error(BP_EUNSUPPORTED, "device %d beyond the scratch table", dev);
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = 0;
+    BP_HIP(hipGetDevice(&cur));
+    if (cur != dev) BP_HIP(hipSetDevice(dev));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) BP_HIP(hipSetDevice(cur));
+    if (e != hipSuccess || ptr == nullptr)
+      return set_error(BP_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return BP_OK;
+}
+
+static bp_status event_csr_run(const bp_csr* m, const MvPlan& p, const uint8_t* events, float* y, void* ws,
+                               hipStream_t st);
+
 }  // namespace bp
 
 using namespace bp;
@@ -734,9 +779,36 @@ bp_status bp_event_csr_matvec(const bp_csr* m, const uint8_t* events, float* y, 
   if (m->n_post == 0) return BP_OK;
   BP_REQUIRE(y != nullptr, "null y");
   BP_REQUIRE(m->n_pre == 0 || events != nullptr, "null events");
-  hipStream_t st = as_stream(stream);
   const MvPlan p = plan_csr(m);
   BP_REQUIRE(ws_bytes >= p.ws && (p.ws == 0 || ws != nullptr), "workspace too small (%zu < %zu)", ws_bytes, p.ws);
+  return event_csr_run(m, p, events, y, ws, as_stream(stream));
+}
+
+bp_status bp_event_csr_matvec_noalloc(const bp_csr* m, const uint8_t* events, float* y, bp_stream stream) {
+  bp_status s = check_csr(m);
+  if (s) return s;
+  if (m->n_post == 0) return BP_OK;
+  BP_REQUIRE(y != nullptr, "null y");
+  BP_REQUIRE(m->n_pre == 0 || events != nullptr, "null events");
+  const MvPlan p = plan_csr(m);
+  BP_REQUIRE(p.ws <= kStaticScratchBytes, "scratch of %zu bytes needed, the static array holds %zu", p.ws,
+             kStaticScratchBytes);
+  hipStream_t st = as_stream(stream);
+  void* ws = nullptr;
+  if (p.ws > 0) {
+    s = static_scratch(st, &ws);
+    if (s) return s;
+  }
+  return event_csr_run(m, p, events, y, ws, st);
+}
+
+}  // extern "C"
+
+namespace bp {
+
+static bp_status event_csr_run(const bp_csr* m, const MvPlan& p, const uint8_t* events, float* y, void* ws,
+                               hipStream_t st) {
+  bp_status s = BP_OK;
   const bool homo = m->data == nullptr;
   if (p.atomic_path) {
     uint32_t* acc = (uint32_t*)ws;
@@ -770,6 +842,10 @@ bp_status bp_event_csr_matvec(const bp_csr* m, const uint8_t* events, float* y, 
   if (s) return s;
   return finish_partials(p, homo, ws, m->n_post, m->w, y, st);
 }
+
+}  // namespace bp
+
+extern "C" {
 
 size_t bp_jit_ws_bytes(const bp_jit_conn* c) {
   if (!c) return 0;

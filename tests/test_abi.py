@@ -133,3 +133,21 @@ def test_destroyed_net_handle_is_rejected():
     assert L.bp_destroy_net(None) == _abi.BP_ESTATE
     assert L.bp_run(fake, 1, None, None, None, None) == _abi.BP_ESTATE
     assert b"destroyed" in L.bp_last_error()
+
+
+def test_noalloc_product_rejects_scratch_beyond_its_static_array():
+    # the allocation-free event product checks the scratch it needs against
+    # the static array before any device work: an unsorted CSR wider than one
+    # LDS tile needs n_post x 4 bytes of device-atomic accumulators
+    import ctypes as C
+    from paper_2311_05106_amd import _abi
+    L = _abi.lib()
+    fake = C.c_void_p(0x1000)
+    n_post = 5_000_000
+    m = _abi.Csr(0x1000, 0x1000, 0x1000, 0.0, 10, n_post, 0, None, 0)
+    assert L.bp_event_csr_ws_bytes(C.byref(m)) == 4 * n_post > _abi.STATIC_SCRATCH_BYTES
+    assert L.bp_event_csr_matvec_noalloc(C.byref(m), fake, fake, None) == _abi.BP_EINVAL
+    assert b"static array" in L.bp_last_error()
+    assert L.bp_event_csr_matvec_noalloc(None, fake, fake, None) == _abi.BP_EINVAL
+    m = _abi.Csr(0x1000, 0x1000, None, 0.5, 10, 100, 1, None, 0)
+    assert L.bp_event_csr_matvec_noalloc(C.byref(m), fake, None, None) == _abi.BP_EINVAL
