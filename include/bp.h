@@ -163,6 +163,27 @@ size_t bp_event_csr_ws_bytes(const bp_csr* m);
 bp_status bp_event_csr_matvec(const bp_csr* m, const uint8_t* events, float* y, void* ws, size_t ws_bytes,
                               bp_stream stream);
 
+/* Batched form (Appendix B's product on a matrix of spike vectors, the
+ * matrix-matrix member of the event-driven operator family of Section 4.2):
+ * Y[b] = M^T E[b] for b < batch, E a device uint8 [batch][n_pre] with row
+ * stride ev_stride >= n_pre bytes, Y a device float [batch][n_post] with row
+ * stride y_stride >= n_post floats (rows overwritten; padding untouched).
+ * Each firing row is streamed once per group of up to eight vectors and its
+ * entries are added to every vector of the group that fires it, so a row
+ * firing in several vectors costs one read.  Row b of Y equals
+ * bp_event_csr_matvec of E[b] (homogeneous: exactly; data: up to FP32
+ * summation order).  Rows must be strictly increasing (m->sorted;
+ * BP_EUNSUPPORTED otherwise) and n_pre < 2^24.  A tile index whose width
+ * leaves room for two vectors per group is used; otherwise tiles are found by
+ * the in-kernel row search.  ws: bp_event_csr_matmat_ws_bytes(m, batch)
+ * bytes of device scratch (0 when one row chunk covers the matrix).  Errors
+ * (BP_EINVAL, before any launch): negative batch, strides below the vector
+ * lengths, null E or Y with work to do, a short workspace.  batch == 0 is a
+ * no-op. */
+size_t bp_event_csr_matmat_ws_bytes(const bp_csr* m, int32_t batch);
+bp_status bp_event_csr_matmat(const bp_csr* m, const uint8_t* events, int32_t batch, int64_t ev_stride, float* y,
+                              int64_t y_stride, void* ws, size_t ws_bytes, bp_stream stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc):
  * bp_event_csr_matvec with no workspace argument, same kernels and results.
@@ -199,6 +220,19 @@ bp_status bp_event_csr_backward(const bp_csr* m, const uint8_t* events, const fl
 size_t bp_jit_ws_bytes(const bp_jit_conn* c);
 bp_status bp_jit_conn_matvec(const bp_jit_conn* c, const uint8_t* events, float* y, void* ws, size_t ws_bytes,
                              bp_stream stream);
+
+/* Batched JIT product on spike vectors: Y[b] = M^T E[b] with M regenerated
+ * from (seed, K, block, weights), E and Y laid out as in bp_event_csr_matmat
+ * (strided rows).  Each firing (row, block) is generated once per group of up
+ * to eight vectors (fewer when weighted blocks are wider than 2048 columns or
+ * homogeneous blocks wider than 4096) and its targets are added to every
+ * vector of the group that fires the row.  Row b of Y equals
+ * bp_jit_conn_matvec of E[b] (homogeneous: exactly; weighted: up to FP32
+ * summation order).  n_pre < 2^24.  ws: bp_jit_conn_matmat_ws_bytes(c, batch)
+ * bytes.  Errors as bp_event_csr_matmat. */
+size_t bp_jit_conn_matmat_ws_bytes(const bp_jit_conn* c, int32_t batch);
+bp_status bp_jit_conn_matmat(const bp_jit_conn* c, const uint8_t* events, int32_t batch, int64_t ev_stride, float* y,
+                             int64_t y_stride, void* ws, size_t ws_bytes, bp_stream stream);
 
 /* Float-vector form of the JIT product (Section 5.2's operator on a dense
  * vector): y (device float[n_post], overwritten) = J^T v, y[k] = sum over

@@ -215,6 +215,25 @@ def event_csr_counts(indptr, indices, n_post, events):
     return cnt
 
 
+def event_csr_matmat(indptr, indices, data, w, n_post, E):
+    """Y[b] = M^T E[b] for a batch of spike vectors E [batch, n_pre]: the
+    single-vector product of Appendix B applied to each vector; FP64."""
+    E = np.asarray(E)
+    Y = np.empty((E.shape[0], n_post), np.float64)
+    for b in range(E.shape[0]):
+        Y[b] = event_csr_matvec(indptr, indices, data, w, n_post, E[b])
+    return Y
+
+
+def event_csr_counts_batch(indptr, indices, n_post, E):
+    """Integer counts of event_csr_matmat with homogeneous weight 1."""
+    E = np.asarray(E)
+    Y = np.empty((E.shape[0], n_post), np.int64)
+    for b in range(E.shape[0]):
+        Y[b] = event_csr_counts(indptr, indices, n_post, E[b])
+    return Y
+
+
 def event_csr_vjp(indptr, indices, data, w, n_post, events, dy):
     ev = np.ascontiguousarray(events, np.uint8)
     n_pre = ev.shape[0]
@@ -280,6 +299,24 @@ def jit_counts(seed, K, B, n_post, events):
     cnt = np.empty(n_post, np.int64)
     lib().or_jit_counts(seed, K, B, ev.shape[0], n_post, ev, cnt)
     return cnt
+
+
+def jit_matmat(seed, K, B, wkind, w0, w1, n_post, E):
+    """Y[b] = M^T E[b] with the JIT matrix of (seed, K, B, weights), for a
+    batch of spike vectors E [batch, n_pre]; FP64."""
+    E = np.asarray(E)
+    Y = np.empty((E.shape[0], n_post), np.float64)
+    for b in range(E.shape[0]):
+        Y[b] = jit_matvec(seed, K, B, wkind, w0, w1, n_post, E[b])
+    return Y
+
+
+def jit_counts_batch(seed, K, B, n_post, E):
+    E = np.asarray(E)
+    Y = np.empty((E.shape[0], n_post), np.int64)
+    for b in range(E.shape[0]):
+        Y[b] = jit_counts(seed, K, B, n_post, E[b])
+    return Y
 
 
 def jit_vjp(seed, K, B, wkind, w0, w1, n_post, events, dy):

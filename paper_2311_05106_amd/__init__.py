@@ -16,7 +16,7 @@ from ._abi import (COBA, CONN_CSR, CONN_JIT, CUBA, STREAM_CONN, STREAM_V0, STREA
 
 __all__ = [
     "lib", "BpError", "max_gap", "hash_words", "csr_build", "csr_tile_index", "compact", "event_csr_matvec",
-    "event_csr_matvec_noalloc",
+    "event_csr_matvec_noalloc", "event_csr_matmat", "jit_conn_matmat",
     "jit_conn_matvec", "jit_conn_matvec_dense", "jit_conn_matmat_dense", "event_csr_backward", "jit_conn_backward", "Net", "run_batch", "JitConn",
     "COBA", "CUBA", "CONN_CSR", "CONN_JIT", "W_HOMO", "W_NORMAL", "W_UNIFORM",
 ]
@@ -186,6 +186,76 @@ def event_csr_matvec_noalloc(indptr, indices, data, w, n_post, events, out, tile
 def event_csr_ws(indptr, indices, data, w, n_post, tile_ptr=None, tile_width=0, sorted_rows=True):
     m = _csr_struct(indptr, indices, data, w, n_post, tile_ptr, tile_width, sorted_rows)
     return int(lib().bp_event_csr_ws_bytes(C.byref(m)))
+
+
+def _spike_matrix(E, n, name="events"):
+    """A batch of spike vectors for the kernels: a CUDA uint8 (or bool) matrix
+    [batch, n] whose rows are contiguous (any row stride >= n); returns the
+    byte view and its row stride."""
+    if not isinstance(E, torch.Tensor) or not E.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if E.dtype == torch.bool:
+        E = E.view(torch.uint8)
+    if E.dtype != torch.uint8:
+        raise TypeError(f"{name} must be uint8 or bool (one byte per neuron), got {E.dtype}")
+    if E.dim() != 2 or E.shape[1] != n:
+        raise ValueError(f"{name} must be [batch, {n}], got {tuple(E.shape)}")
+    if E.shape[0] > 0 and (E.stride(1) != 1 or E.stride(0) < n):
+        E = E.contiguous()
+    return E, (E.stride(0) if E.shape[0] > 0 else n)
+
+
+def _out_matrix(out, batch, n, device):
+    if out is None:
+        Y = torch.empty((batch, n), dtype=torch.float32, device=device)
+    else:
+        Y = out
+        if not isinstance(Y, torch.Tensor) or not Y.is_cuda or Y.dtype != torch.float32 or Y.dim() != 2 \
+                or tuple(Y.shape) != (batch, n) or (batch > 0 and (Y.stride(1) != 1 or Y.stride(0) < n)):
+            raise ValueError(f"out must be a CUDA float32 [batch, {n}] matrix with contiguous rows")
+    return Y, (Y.stride(0) if batch > 0 else n)
+
+
+def event_csr_matmat(indptr, indices, data, w, n_post, E, tile_ptr=None, tile_width=0, out=None, ws=None):
+    """Y[b] = M^T E[b] for a batch of spike vectors E [batch, n_pre] (rows may
+    be strided); each firing row is streamed once per group of up to eight
+    vectors (sorted rows)."""
+    indptr, indices, data = _csr_args(indptr, indices, data, n_post)
+    E, ev_stride = _spike_matrix(E, indptr.numel() - 1)
+    if tile_ptr is not None:
+        tile_ptr = _dev(tile_ptr, torch.int32, "tile_ptr")
+    m = _csr_struct(indptr, indices, data, w, n_post, tile_ptr, tile_width, True)
+    batch = int(E.shape[0])
+    Y, y_stride = _out_matrix(out, batch, n_post, E.device)
+    wsb = int(lib().bp_event_csr_matmat_ws_bytes(C.byref(m), batch))
+    if ws is None or ws.numel() < wsb:
+        ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=E.device)
+    check(lib().bp_event_csr_matmat(C.byref(m), _p(E), batch, ev_stride, _p(Y), y_stride, _p(ws), wsb, _stream()))
+    return Y
+
+
+def jit_conn_matmat(conn: JitConn, E, out=None, ws=None):
+    """Y[b] = M^T E[b] for a batch of spike vectors with M regenerated from
+    the seed; each firing (row, block) is generated once per group of up to
+    eight vectors."""
+    c = conn.c
+    E, ev_stride = _spike_matrix(E, c.n_pre)
+    batch = int(E.shape[0])
+    Y, y_stride = _out_matrix(out, batch, c.n_post, E.device)
+    wsb = int(lib().bp_jit_conn_matmat_ws_bytes(C.byref(c), batch))
+    if ws is None or ws.numel() < wsb:
+        ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=E.device)
+    check(lib().bp_jit_conn_matmat(C.byref(c), _p(E), batch, ev_stride, _p(Y), y_stride, _p(ws), wsb, _stream()))
+    return Y
+
+
+def event_csr_matmat_ws(indptr, indices, data, w, n_post, batch, tile_ptr=None, tile_width=0):
+    m = _csr_struct(indptr, indices, data, w, n_post, tile_ptr, tile_width, True)
+    return int(lib().bp_event_csr_matmat_ws_bytes(C.byref(m), batch))
+
+
+def jit_conn_matmat_ws(conn: JitConn, batch):
+    return int(lib().bp_jit_conn_matmat_ws_bytes(C.byref(conn.c), batch))
 
 
 def jit_conn_matvec(conn: JitConn, events, out=None, ws=None):

@@ -66,6 +66,10 @@ SIGNATURES = {
     "bp_event_csr_matvec": (_i32, [C.POINTER(Csr), _vp, _vp, _vp, _sz, _vp]),
     "bp_event_csr_matvec_noalloc": (_i32, [C.POINTER(Csr), _vp, _vp, _vp]),
     "bp_event_csr_backward": (_i32, [C.POINTER(Csr), _vp, _vp, _vp, _vp, _vp, _vp]),
+    "bp_event_csr_matmat_ws_bytes": (_sz, [C.POINTER(Csr), _i32]),
+    "bp_event_csr_matmat": (_i32, [C.POINTER(Csr), _vp, _i32, _i64, _vp, _i64, _vp, _sz, _vp]),
+    "bp_jit_conn_matmat_ws_bytes": (_sz, [C.POINTER(JitConn), _i32]),
+    "bp_jit_conn_matmat": (_i32, [C.POINTER(JitConn), _vp, _i32, _i64, _vp, _i64, _vp, _sz, _vp]),
     "bp_jit_ws_bytes": (_sz, [C.POINTER(JitConn)]),
     "bp_jit_conn_matvec": (_i32, [C.POINTER(JitConn), _vp, _vp, _vp, _sz, _vp]),
     "bp_jit_dense_ws_bytes": (_sz, [C.POINTER(JitConn)]),

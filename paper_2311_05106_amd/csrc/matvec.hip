@@ -40,8 +40,16 @@ constexpr int kTileMax = 16384;                    // LDS tile columns (64 KB)
 constexpr int kGroup = 16;                         // lanes streaming one CSR segment
 constexpr int kSegLoads = 10;                      // loads per lane and segment pass (160 entries)
 
-enum MvMode { kCsrHomo = 0, kCsrData = 1, kJitHomo = 2, kJitWeighted = 3, kJitVec = 4, kJitMat = 5 };
-constexpr int kMatCols = 8;  // kJitMat: columns of X per workgroup (blockIdx.y = column group)
+enum MvMode {
+  kCsrHomo = 0, kCsrData = 1, kJitHomo = 2, kJitWeighted = 3, kJitVec = 4, kJitMat = 5,
+  // batched spike products: the same four operators on `batch` spike
+  // vectors at once, up to kMatCols per workgroup (blockIdx.y = group)
+  kCsrHomoB = 6, kCsrDataB = 7, kJitHomoB = 8, kJitWeightedB = 9
+};
+constexpr int kMatCols = 8;  // kJitMat / batched: columns per workgroup
+constexpr bool is_batch(int m) { return m >= kCsrHomoB; }
+constexpr int base_mode(int m) { return m >= kCsrHomoB ? m - kCsrHomoB : m; }
+constexpr bool counts_mode(int m) { return base_mode(m) == kCsrHomo || base_mode(m) == kJitHomo; }
 
 struct MvArgs {
   const int32_t* indptr;
@@ -52,6 +60,8 @@ struct MvArgs {
   const float* vec;         // kJitVec: dense input vector (rows with v[j] != 0 are listed)
   const float* x;           // kJitMat: X row-major [n_pre][m] (every row is listed)
   int32_t m, mg;            // kJitMat: columns of X, columns per group
+  int32_t batch, mb;        // batched: spike vectors, vectors per group
+  int64_t ev_stride, y_stride;  // batched: bytes between spike vectors, floats between outputs
   void* out;                // y (chunks == 1) or partials [chunks][n_post]
   bp_jit_conn jit;
   float w;
@@ -140,9 +150,12 @@ __device__ __forceinline__ uint32_t nonzero_floats16(const float* __restrict__ v
   return b;
 }
 
-// Appends rows r + q (bit q of bits) to ids[total + ...]: one LDS atomic per
-// wave reserves the wave's slots, a wave scan places each lane's rows.
-__device__ __forceinline__ void append_rows(uint32_t bits, int32_t r, int total, int* cnt, int* ids) {
+// Appends entry(q) for every set bit q of bits to ids[total + ...]: one LDS
+// atomic per wave reserves the wave's slots, a wave scan places each lane's
+// rows.  entry(q) is the row r + q, or for batched products
+// (r + q) << 8 | (bit b set iff vector b of the group fires row r + q).
+template <class Entry>
+__device__ __forceinline__ void append_rows(uint32_t bits, int total, int* cnt, int* ids, Entry&& entry) {
   const int c = __popc(bits);
   const int inc = wave_incl_scan(c);
   const int wtot = __builtin_amdgcn_readlane(inc, kWave - 1);
@@ -154,9 +167,27 @@ __device__ __forceinline__ void append_rows(uint32_t bits, int32_t r, int total,
   while (bits) {
     const int q = __ffs(bits) - 1;
     bits &= bits - 1;
-    if (off < kIdCap) ids[off] = r + q;
+    if (off < kIdCap) ids[off] = entry(q);
     ++off;
   }
+}
+
+// Batched products, one target of a row firing in the group's vectors
+// `mask` (bit b: vector b) at LDS offset off.  Counts: two vectors per
+// 32-bit word (vector b in word b / 2, half b % 2; a row chunk adds at most
+// 65520 to a column, host plan), so one add serves a pair.  Sums: vector b
+// at acc[b * width + off].
+__device__ __forceinline__ void batch_count(uint32_t* acc, int off, int width, uint32_t mask) {
+#pragma unroll
+  for (int q = 0; q < kMatCols / 2; ++q) {
+    const uint32_t inc = ((mask >> (2 * q)) & 1u) | (((mask >> (2 * q + 1)) & 1u) << 16);
+    if (inc) atomicAdd(&acc[q * width + off], inc);
+  }
+}
+__device__ __forceinline__ void batch_sum(float* acc, int off, int width, uint32_t mask, float v) {
+#pragma unroll
+  for (int b = 0; b < kMatCols; ++b)
+    if ((mask >> b) & 1u) lds_add_f32(&acc[b * width + off], v);
 }
 
 // The factor(s) of one listed row: v[j] for kJitVec, X[j][c0 .. c0 + mg)
@@ -189,9 +220,29 @@ struct RowScale {
   }
 };
 
+// One generated target of a JIT row at LDS offset off: a count (homogeneous),
+// or the m-th weight of the row's W sub-stream times the row's factor(s);
+// batched products add to the vectors in mk.
+template <int MODE>
+__device__ __forceinline__ void jit_put(void* accv, int off, int width, uint32_t mk, const RowScale<MODE>& sc,
+                                        DrawSeq& wd, int wkind, float w0, float w1, uint32_t m, int mg) {
+  if constexpr (MODE == kJitHomo) {
+    atomicAdd(reinterpret_cast<uint32_t*>(accv) + off, 1u);
+  } else if constexpr (MODE == kJitHomoB) {
+    batch_count(reinterpret_cast<uint32_t*>(accv), off, width, mk);
+  } else {
+    float unit;
+    const float w = jit_weight(wd, wkind, w0, w1, m, &unit);
+    if constexpr (MODE == kJitWeightedB) batch_sum(reinterpret_cast<float*>(accv), off, width, mk, w);
+    else sc.add(reinterpret_cast<float*>(accv), off, w, mg, width);
+  }
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
-  using Acc = typename std::conditional<(MODE == kCsrHomo || MODE == kJitHomo), uint32_t, float>::type;
+  constexpr bool kB = is_batch(MODE);
+  constexpr int BM = base_mode(MODE);
+  using Acc = typename std::conditional<counts_mode(MODE), uint32_t, float>::type;
   __shared__ Acc acc[kTileMax];
   __shared__ MvShared sh;
   const int t = blockIdx.x % a.n_tiles;
@@ -201,49 +252,76 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
   const int32_t width = hi - lo;
   const int32_t r_begin = c * a.chunk_rows;
   const int32_t r_end = min(r_begin + a.chunk_rows, a.n_pre);
-  const int c0 = MODE == kJitMat ? (int)blockIdx.y * a.mg : 0;
-  const int mg = MODE == kJitMat ? min(a.mg, a.m - c0) : 1;  // width * mg <= kTileMax (host plan)
-  for (int i = threadIdx.x; i < (width * mg + 3) / 4; i += kMvThreads)  // kTileMax is a multiple of 4
+  const int c0 = MODE == kJitMat ? (int)blockIdx.y * a.mg : kB ? (int)blockIdx.y * a.mb : 0;
+  const int mg = MODE == kJitMat ? min(a.mg, a.m - c0) : kB ? min(a.mb, a.batch - c0) : 1;
+  // LDS words per column: mg floats (kJitMat, batched sums), mg / 2 rounded
+  // up for batched counts, else 1; width * words <= kTileMax (host plan)
+  const int words = (kB && counts_mode(MODE)) ? (mg + 1) / 2 : (MODE == kJitMat || kB) ? mg : 1;
+  for (int i = threadIdx.x; i < (width * words + 3) / 4; i += kMvThreads)  // kTileMax is a multiple of 4
     reinterpret_cast<uint4*>(acc)[i] = make_uint4(0u, 0u, 0u, 0u);
   if (threadIdx.x < 3) sh.cnt[threadIdx.x] = 0;
   __syncthreads();
   const uintptr_t src = MODE == kJitVec ? reinterpret_cast<uintptr_t>(a.vec) : reinterpret_cast<uintptr_t>(a.events);
-  const bool vec = ((src | (uintptr_t)r_begin) & 15) == 0;
+  const bool vec = ((src | (uintptr_t)r_begin | (kB ? (uintptr_t)a.ev_stride : 0)) & 15) == 0;
+  const uint8_t* evg = kB ? a.events + (size_t)c0 * a.ev_stride : a.events;  // the group's first vector
 
   int total = 0;  // listed rows, equal in every lane
   int s = 0;
   for (int32_t r0 = r_begin; r0 < r_end; r0 += kSweep, ++s) {
     const int32_t r = r0 + (int32_t)threadIdx.x * kRowsPerLane;
     uint32_t bits = 0u;
+    uint32_t vb[kB ? kMatCols : 1] = {};  // batched: the spike bits of each vector of the group
     if (r < r_end) {
-      if constexpr (MODE == kJitMat) bits = r + kRowsPerLane <= r_end ? 0xFFFFu : (1u << (r_end - r)) - 1u;
-      else if constexpr (MODE == kJitVec) bits = nonzero_floats16(a.vec, r, r_end, vec);
-      else bits = spike_bits16(a.events, r, r_end, vec);
+      if constexpr (MODE == kJitMat) {
+        bits = r + kRowsPerLane <= r_end ? 0xFFFFu : (1u << (r_end - r)) - 1u;
+      } else if constexpr (MODE == kJitVec) {
+        bits = nonzero_floats16(a.vec, r, r_end, vec);
+      } else if constexpr (kB) {
+#pragma unroll
+        for (int b = 0; b < kMatCols; ++b) {
+          vb[b] = b < mg ? spike_bits16(evg + (size_t)b * a.ev_stride, r, r_end, vec) : 0u;
+          bits |= vb[b];
+        }
+      } else {
+        bits = spike_bits16(a.events, r, r_end, vec);
+      }
     }
     // the counter of the next sweep was last read before the previous barrier
     if (threadIdx.x == 0) sh.cnt[(s + 1) % 3] = 0;
-    append_rows(bits, r, total, &sh.cnt[s % 3], sh.ids);
+    if constexpr (kB) {
+      append_rows(bits, total, &sh.cnt[s % 3], sh.ids, [&](int q) {
+        uint32_t mk = 0;
+#pragma unroll
+        for (int b = 0; b < kMatCols; ++b) mk |= ((vb[b] >> q) & 1u) << b;
+        return (int)((uint32_t)(r + q) << 8 | mk);
+      });
+    } else {
+      append_rows(bits, total, &sh.cnt[s % 3], sh.ids, [&](int q) { return r + q; });
+    }
     __syncthreads();
     total += sh.cnt[s % 3];
     if (total <= kIdCap - kSweep && r0 + kSweep < r_end) continue;
     if (total > kIdCap) total = kIdCap;  // unreachable: a sweep adds at most kSweep rows
 
-    if constexpr (MODE == kCsrHomo || MODE == kCsrData) {
+    if constexpr (BM == kCsrHomo || BM == kCsrData) {
       // quarter-wave g streams the segments of rows g, g + G, ...; lane l
       // reads entries l, l + 16, ... of a segment.  Rows go in batches of R
       // per group: the loads of all R segments (kSegLoads per lane, 160
       // entries each) are issued together, then the bounds of the next batch,
       // then the LDS adds; the rare entries beyond 160 follow row by row.
-      constexpr int R = MODE == kCsrHomo ? 4 : 2;
+      constexpr int R = BM == kCsrHomo ? 4 : 2;
       constexpr int U = kSegLoads;
       constexpr int kPass = kGroup * U;
       const int G = kMvThreads / kGroup;
       const int g = threadIdx.x / kGroup, l = threadIdx.x % kGroup;
-      auto segment = [&](int i, int& st, int& ln) {
+      auto segment = [&](int i, int& st, int& ln, uint32_t& mk) {
         st = 0;
         ln = 0;
+        mk = 0;
         if (i >= total) return;
-        const int32_t j = sh.ids[i];
+        const int32_t id = sh.ids[i];
+        const int32_t j = kB ? (int32_t)((uint32_t)id >> 8) : id;
+        if constexpr (kB) mk = (uint32_t)id & 0xFFu;
         if (a.tile_ptr) {
           const int32_t* tp = a.tile_ptr + (size_t)j * (a.n_tiles + 1) + t;
           st = tp[0];
@@ -257,13 +335,16 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
           ln = a.indptr[j + 1] - st;
         }
       };
-      auto add = [&](int c, float v) {
+      auto add = [&](int c, float v, uint32_t mk) {
         if constexpr (MODE == kCsrHomo) atomicAdd(&acc[c - lo], 1u);
-        else lds_add_f32(&acc[c - lo], v);
+        else if constexpr (MODE == kCsrData) lds_add_f32(&acc[c - lo], v);
+        else if constexpr (MODE == kCsrHomoB) batch_count(reinterpret_cast<uint32_t*>(acc), c - lo, width, mk);
+        else batch_sum(reinterpret_cast<float*>(acc), c - lo, width, mk, v);
       };
       int st[R], ln[R];
+      uint32_t mk[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) segment(g + r * G, st[r], ln[r]);
+      for (int r = 0; r < R; ++r) segment(g + r * G, st[r], ln[r], mk[r]);
       for (int i0 = g; i0 < total; i0 += R * G) {
         int col[R][U];
         float val[R][U];
@@ -273,17 +354,18 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
           for (int u = 0; u < U; ++u) {
             const int e = l + kGroup * u;
             col[r][u] = e < ln[r] ? a.indices[st[r] + e] : -1;
-            if constexpr (MODE == kCsrData) val[r][u] = e < ln[r] ? a.data[st[r] + e] : 0.f;
+            if constexpr (BM == kCsrData) val[r][u] = e < ln[r] ? a.data[st[r] + e] : 0.f;
           }
         }
         int nst[R], nln[R];
+        uint32_t nmk[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) segment(i0 + (R + r) * G, nst[r], nln[r]);
+        for (int r = 0; r < R; ++r) segment(i0 + (R + r) * G, nst[r], nln[r], nmk[r]);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
 #pragma unroll
           for (int u = 0; u < U; ++u)
-            if (col[r][u] >= 0) add(col[r][u], MODE == kCsrData ? val[r][u] : 0.f);
+            if (col[r][u] >= 0) add(col[r][u], BM == kCsrData ? val[r][u] : 0.f, mk[r]);
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -294,17 +376,18 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
             for (int u = 0; u < U; ++u) {
               const int e = base + l + kGroup * u;
               c2[u] = e < ln[r] ? a.indices[st[r] + e] : -1;
-              if constexpr (MODE == kCsrData) v2[u] = e < ln[r] ? a.data[st[r] + e] : 0.f;
+              if constexpr (BM == kCsrData) v2[u] = e < ln[r] ? a.data[st[r] + e] : 0.f;
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
-              if (c2[u] >= 0) add(c2[u], MODE == kCsrData ? v2[u] : 0.f);
+              if (c2[u] >= 0) add(c2[u], BM == kCsrData ? v2[u] : 0.f, mk[r]);
           }
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           st[r] = nst[r];
           ln[r] = nln[r];
+          mk[r] = nmk[r];
         }
       }
     } else {
@@ -334,7 +417,8 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
         const uint32_t b = (uint32_t)b_lo;
         const int64_t end = hi;
         const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-        const uint32_t j = act ? (uint32_t)sh.ids[ai] : 0u;
+        const uint32_t id = act ? (uint32_t)sh.ids[ai] : 0u;
+        const uint32_t j = kB ? id >> 8 : id, mk = kB ? id & 0xFFu : 0u;
         RowScale<MODE> sc;
         sc.load(a, j, c0, mg);  // row 0 exists whenever a pass runs
         DrawSeq wd(seed, kStreamW, j, b);
@@ -365,25 +449,13 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
           const int64_t b0 = pass == 0 ? shfl64(first, qb) : prev;
           const int64_t excl = (q > 0 ? s0 : 0) + (q > 1 ? s1 : 0) + (q > 2 ? s2 : 0);
           int64_t pos = b0 + excl;
-          if (live && blk == 0 && pos < end) {  // target 0
-            if constexpr (MODE == kJitHomo) {
-              atomicAdd(&acc[pos - lo], 1u);
-            } else {
-              float unit;
-              sc.add(acc, (int)(pos - lo), jit_weight(wd, wkind, w0, w1, 0u, &unit), mg, width);
-            }
-          }
+          if (live && blk == 0 && pos < end)  // target 0
+            jit_put<MODE>(acc, (int)(pos - lo), width, mk, sc, wd, wkind, w0, w1, 0u, mg);
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             pos += g[u];
-            if (live && g[u] > 0 && pos < end) {
-              if constexpr (MODE == kJitHomo) {
-                atomicAdd(&acc[pos - lo], 1u);
-              } else {
-                float unit;
-                sc.add(acc, (int)(pos - lo), jit_weight(wd, wkind, w0, w1, 4u * blk - 1u + (uint32_t)u, &unit), mg, width);
-              }
-            }
+            if (live && g[u] > 0 && pos < end)
+              jit_put<MODE>(acc, (int)(pos - lo), width, mk, sc, wd, wkind, w0, w1, 4u * blk - 1u + (uint32_t)u, mg);
           }
           prev = shfl64(pos, qb + 3);  // the pass's last position
           live = live && prev < end;
@@ -393,17 +465,13 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
       for (int it = threadIdx.x; it < items; it += kMvThreads) {
         const int ai = nbt == 1 ? it : it / nbt;
         const uint32_t b = (uint32_t)(b_lo + (nbt == 1 ? 0 : it % nbt));
-        const uint32_t j = (uint32_t)sh.ids[ai];
+        const uint32_t id = (uint32_t)sh.ids[ai];
+        const uint32_t j = kB ? id >> 8 : id, mk = kB ? id & 0xFFu : 0u;
         RowScale<MODE> sc;
         sc.load(a, j, c0, mg);
         DrawSeq wd(seed, kStreamW, j, b);
         gen_block(seed, K, n_post, B, j, b, lo, hi, [&](int32_t pos, uint32_t m) {
-          if constexpr (MODE == kJitHomo) {
-            atomicAdd(&acc[pos - lo], 1u);
-          } else {
-            float unit;
-            sc.add(acc, pos - lo, jit_weight(wd, wkind, w0, w1, m, &unit), mg, width);
-          }
+          jit_put<MODE>(acc, pos - lo, width, mk, sc, wd, wkind, w0, w1, m, mg);
         });
       }
     }
@@ -417,6 +485,26 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
     for (int i2 = threadIdx.x; i2 < width * mg; i2 += kMvThreads) {
       const int i = i2 / mg, cc = i2 - i * mg;
       dst[(size_t)(lo + i) * a.m + c0 + cc] = acc[cc * width + i];
+    }
+    return;
+  }
+  if constexpr (kB) {
+    // vector c0 + b of the group: Y[c0 + b][lo + i] (one chunk), or the
+    // partial [c][c0 + b][lo + i] of [chunks][batch][n_post]
+    for (int i2 = threadIdx.x; i2 < width * mg; i2 += kMvThreads) {
+      const int b = i2 / width, i = i2 - b * width;
+      uint32_t cnt = 0;
+      float sum = 0.f;
+      if constexpr (counts_mode(MODE)) cnt = (acc[(b >> 1) * width + i] >> (16 * (b & 1))) & 0xFFFFu;
+      else sum = acc[b * width + i];
+      if (a.chunks == 1) {
+        reinterpret_cast<float*>(a.out)[(size_t)(c0 + b) * a.y_stride + lo + i] =
+            counts_mode(MODE) ? (float)cnt * a.w : sum;
+      } else {
+        const size_t at = ((size_t)c * a.batch + c0 + b) * a.n_post + lo + i;
+        if constexpr (counts_mode(MODE)) reinterpret_cast<uint16_t*>(a.out)[at] = (uint16_t)cnt;
+        else reinterpret_cast<float*>(a.out)[at] = sum;
+      }
     }
     return;
   }
@@ -504,6 +592,33 @@ __global__ void mv_reduce_f32_k(const float* __restrict__ part, int32_t chunks, 
 #pragma unroll 8
       for (int c = 0; c < chunks; ++c) s += part[(size_t)c * n_post + k + q];
       y[k + q] = s;
+    }
+  }
+}
+
+// Batched products: Y[b][k] = (w *) sum_c part[c][b][k] in chunk order, part
+// [chunks][batch][n_post] (16-bit counts or FP32 sums); blockIdx.y = b, two
+// consecutive columns per thread.
+template <bool COUNTS>
+__global__ void mv_reduce_batch_k(const void* __restrict__ part, int32_t chunks, int32_t batch, int32_t n_post,
+                                  float w, float* __restrict__ y, int64_t y_stride) {
+  const int32_t b = blockIdx.y;
+  const int32_t k0 = (blockIdx.x * blockDim.x + threadIdx.x) * 2;
+  const size_t cs = (size_t)batch * n_post;
+  for (int q = 0; q < 2; ++q) {
+    const int32_t k = k0 + q;
+    if (k >= n_post) break;
+    const size_t at = (size_t)b * n_post + k;
+    if constexpr (COUNTS) {
+      uint32_t sum = 0;
+#pragma unroll 8
+      for (int c = 0; c < chunks; ++c) sum += reinterpret_cast<const uint16_t*>(part)[c * cs + at];
+      y[(size_t)b * y_stride + k] = (float)sum * w;
+    } else {
+      float sum = 0.f;
+#pragma unroll 8
+      for (int c = 0; c < chunks; ++c) sum += reinterpret_cast<const float*>(part)[c * cs + at];
+      y[(size_t)b * y_stride + k] = sum;
     }
   }
 }
@@ -612,11 +727,13 @@ struct MvPlan {
 // chunks as keep tiles x chunks within the compute units, each at least a
 // quarter sweep of rows.  Chunk starts are multiples of 16 (aligned spike
 // loads); 16-bit partial counts cap homogeneous chunks at 65520 rows.
-static void set_chunks(MvPlan& p, int32_t n_pre, bool homo, int32_t n_post) {
+static void set_chunks(MvPlan& p, int32_t n_pre, bool homo, int32_t n_post, bool packed = false) {
   const int32_t cus = device_cu_count();
   int32_t want = max(1, cus / p.n_tiles);
   want = max(1, min(want, (n_pre + kSweep / 4 - 1) / (kSweep / 4)));
-  if (homo && want > 1) want = max(want, (n_pre + 65519) / 65520);
+  // 16-bit partial counts (and the batched products' packed 16-bit LDS
+  // counts, even with one chunk) hold at most 65520 rows' worth per column
+  if (homo && (want > 1 || packed)) want = max(want, (n_pre + 65519) / 65520);
   int32_t rows = (n_pre + want - 1) / want;
   rows = (rows + 15) & ~15;
   p.chunk_rows = max(16, rows);
@@ -681,6 +798,78 @@ static MvPlan plan_jit_mat(const bp_jit_conn* c, int32_t m, int32_t* mg, int32_t
   p.n_tiles = nt;
   p.ws = p.chunks > 1 ? (size_t)p.chunks * c->n_post * m * sizeof(float) : 0;
   return p;
+}
+
+// Batched spike products: up to kMatCols vectors per workgroup (group on
+// blockIdx.y) while the LDS tile holds them: counts take one 32-bit word per
+// column and pair of vectors, sums one float per column and vector.  Tiles
+// are the single-vector ones when they leave room for at least two vectors,
+// else narrower (CSR: equal tiles found by the in-kernel row search, or the
+// caller's tile index when its width fits; JIT: the tile is still one block
+// when the block fits, else equal tiles).  Partials are [chunks][batch][n_post].
+static int32_t batch_group(int32_t tile, bool counts, int32_t batch) {
+  const int32_t words = kTileMax / max(tile, 1);  // LDS words per column
+  const int32_t per = counts ? 2 * words : words;
+  return max(1, min(min(kMatCols, per), batch));
+}
+
+static MvPlan plan_csr_batch(const bp_csr* m, int32_t batch, int32_t* mb, int32_t* groups) {
+  MvPlan p{};
+  const bool counts = m->data == nullptr;
+  const int32_t cap = counts ? kTileMax / (kMatCols / 2) : kTileMax / kMatCols;  // room for 8 vectors
+  if (m->n_post <= cap) {
+    p.tile = m->n_post > 0 ? m->n_post : 1;
+    p.n_tiles = 1;
+  } else if (m->tile_ptr && m->tile_width > 0 && m->tile_width <= kTileMax / (counts ? 1 : 2)) {
+    p.tile = m->tile_width;  // the caller's index, at least two vectors per group
+    p.n_tiles = (int32_t)(((int64_t)m->n_post + p.tile - 1) / p.tile);
+  } else {
+    const int32_t nt = (int32_t)(((int64_t)m->n_post + cap - 1) / cap);
+    p.tile = (int32_t)(((int64_t)m->n_post + nt - 1) / nt);
+    p.n_tiles = (int32_t)(((int64_t)m->n_post + p.tile - 1) / p.tile);
+  }
+  *mb = batch_group(p.tile, counts, batch);
+  *groups = (batch + *mb - 1) / *mb;
+  const int32_t nt = p.n_tiles;
+  p.n_tiles = nt * *groups;
+  set_chunks(p, m->n_pre, counts, m->n_post, counts);
+  p.n_tiles = nt;
+  p.ws = p.chunks > 1 ? (size_t)p.chunks * batch * m->n_post * (counts ? 2 : 4) : 0;
+  return p;
+}
+
+static MvPlan plan_jit_batch(const bp_jit_conn* c, int32_t batch, int32_t* mb, int32_t* groups) {
+  const bool counts = c->wkind == kWHomo;
+  MvPlan p{};
+  const int32_t cap = counts ? kTileMax / (kMatCols / 2) : kTileMax / kMatCols;
+  if (c->block > 0 && c->block <= kTileMax / (counts ? 1 : 2) && c->n_post > c->block) {
+    p.tile = c->block;  // one block per tile, at least two vectors per group
+  } else if (c->n_post <= cap) {
+    p.tile = c->n_post > 0 ? c->n_post : 1;
+  } else {
+    const int32_t nt = (int32_t)(((int64_t)c->n_post + cap - 1) / cap);
+    p.tile = (int32_t)(((int64_t)c->n_post + nt - 1) / nt);
+  }
+  p.n_tiles = (int32_t)(((int64_t)c->n_post + p.tile - 1) / p.tile);
+  if (p.n_tiles < 1) p.n_tiles = 1;
+  *mb = batch_group(p.tile, counts, batch);
+  *groups = (batch + *mb - 1) / *mb;
+  const int32_t nt = p.n_tiles;
+  p.n_tiles = nt * *groups;
+  set_chunks(p, c->n_pre, counts, c->n_post, counts);
+  p.n_tiles = nt;
+  p.ws = p.chunks > 1 ? (size_t)p.chunks * batch * c->n_post * (counts ? 2 : 4) : 0;
+  return p;
+}
+
+static bp_status finish_batch(const MvPlan& p, bool counts, const void* ws, int32_t batch, int32_t n_post, float w,
+                              float* y, int64_t y_stride, hipStream_t st) {
+  if (p.chunks <= 1 || n_post == 0) return BP_OK;
+  const dim3 g((unsigned)((n_post + 511) / 512), (unsigned)batch);
+  if (counts) mv_reduce_batch_k<true><<<g, 256, 0, st>>>(ws, p.chunks, batch, n_post, w, y, y_stride);
+  else mv_reduce_batch_k<false><<<g, 256, 0, st>>>(ws, p.chunks, batch, n_post, w, y, y_stride);
+  BP_LAUNCHED("mv_reduce_batch_k");
+  return BP_OK;
 }
 
 static bp_status check_csr(const bp_csr* m) {
@@ -846,6 +1035,83 @@ static bp_status event_csr_run(const bp_csr* m, const MvPlan& p, const uint8_t* 
 }  // namespace bp
 
 extern "C" {
+
+size_t bp_event_csr_matmat_ws_bytes(const bp_csr* m, int32_t batch) {
+  if (!m || batch <= 0) return 0;
+  int32_t mb, groups;
+  return plan_csr_batch(m, batch, &mb, &groups).ws;
+}
+
+// Shared argument checks of the batched spike products.
+static bp_status check_batch(int32_t batch, int64_t ev_stride, int64_t y_stride, int32_t n_pre, int32_t n_post,
+                             const uint8_t* events, const float* y) {
+  BP_REQUIRE(batch >= 0, "negative batch");
+  BP_REQUIRE(n_pre < (1 << 24), "batched products take n_pre < 2^24 (got %d)", n_pre);
+  BP_REQUIRE(ev_stride >= n_pre && y_stride >= n_post, "strides below the vector lengths");
+  BP_REQUIRE(batch == 0 || n_post == 0 || y != nullptr, "null y");
+  BP_REQUIRE(batch == 0 || n_pre == 0 || events != nullptr, "null events");
+  return BP_OK;
+}
+
+bp_status bp_event_csr_matmat(const bp_csr* m, const uint8_t* events, int32_t batch, int64_t ev_stride, float* y,
+                              int64_t y_stride, void* ws, size_t ws_bytes, bp_stream stream) {
+  bp_status s = check_csr(m);
+  if (s) return s;
+  s = check_batch(batch, ev_stride, y_stride, m->n_pre, m->n_post, events, y);
+  if (s) return s;
+  if (batch == 0 || m->n_post == 0) return BP_OK;
+  if (!m->sorted) return set_error(BP_EUNSUPPORTED, "batched CSR products need strictly increasing rows");
+  int32_t mb, groups;
+  const MvPlan p = plan_csr_batch(m, batch, &mb, &groups);
+  BP_REQUIRE(groups <= 65535, "too many vector groups (%d)", groups);
+  BP_REQUIRE(ws_bytes >= p.ws && (p.ws == 0 || ws != nullptr), "workspace too small (%zu < %zu)", ws_bytes, p.ws);
+  const bool counts = m->data == nullptr;
+  hipStream_t st = as_stream(stream);
+  MvArgs a{};
+  a.indptr = m->indptr; a.indices = m->indices; a.data = m->data;
+  a.tile_ptr = p.n_tiles > 1 && m->tile_ptr && p.tile == m->tile_width ? m->tile_ptr : nullptr;
+  a.search = p.n_tiles > 1 && a.tile_ptr == nullptr;
+  a.events = events; a.out = p.chunks > 1 ? ws : (void*)y; a.w = m->w;
+  a.batch = batch; a.mb = mb; a.ev_stride = ev_stride; a.y_stride = y_stride;
+  a.n_pre = m->n_pre; a.n_post = m->n_post; a.tile = p.tile; a.n_tiles = p.n_tiles;
+  a.chunks = p.chunks; a.chunk_rows = p.chunk_rows;
+  const dim3 grid((unsigned)(p.n_tiles * p.chunks), (unsigned)groups);
+  if (counts) mv_scatter_k<kCsrHomoB><<<grid, kMvThreads, 0, st>>>(a);
+  else mv_scatter_k<kCsrDataB><<<grid, kMvThreads, 0, st>>>(a);
+  BP_LAUNCHED("mv_scatter_k");
+  return finish_batch(p, counts, ws, batch, m->n_post, m->w, y, y_stride, st);
+}
+
+size_t bp_jit_conn_matmat_ws_bytes(const bp_jit_conn* c, int32_t batch) {
+  if (!c || batch <= 0) return 0;
+  int32_t mb, groups;
+  return plan_jit_batch(c, batch, &mb, &groups).ws;
+}
+
+bp_status bp_jit_conn_matmat(const bp_jit_conn* c, const uint8_t* events, int32_t batch, int64_t ev_stride, float* y,
+                             int64_t y_stride, void* ws, size_t ws_bytes, bp_stream stream) {
+  bp_status s = check_conn(c, true);
+  if (s) return s;
+  s = check_batch(batch, ev_stride, y_stride, c->n_pre, c->n_post, events, y);
+  if (s) return s;
+  if (batch == 0 || c->n_post == 0) return BP_OK;
+  int32_t mb, groups;
+  const MvPlan p = plan_jit_batch(c, batch, &mb, &groups);
+  BP_REQUIRE(groups <= 65535, "too many vector groups (%d)", groups);
+  BP_REQUIRE(ws_bytes >= p.ws && (p.ws == 0 || ws != nullptr), "workspace too small (%zu < %zu)", ws_bytes, p.ws);
+  const bool counts = c->wkind == kWHomo;
+  hipStream_t st = as_stream(stream);
+  MvArgs a{};
+  a.jit = *c; a.events = events; a.out = p.chunks > 1 ? ws : (void*)y; a.w = c->w0;
+  a.batch = batch; a.mb = mb; a.ev_stride = ev_stride; a.y_stride = y_stride;
+  a.n_pre = c->n_pre; a.n_post = c->n_post; a.tile = p.tile; a.n_tiles = p.n_tiles;
+  a.chunks = p.chunks; a.chunk_rows = p.chunk_rows;
+  const dim3 grid((unsigned)(p.n_tiles * p.chunks), (unsigned)groups);
+  if (counts) mv_scatter_k<kJitHomoB><<<grid, kMvThreads, 0, st>>>(a);
+  else mv_scatter_k<kJitWeightedB><<<grid, kMvThreads, 0, st>>>(a);
+  BP_LAUNCHED("mv_scatter_k");
+  return finish_batch(p, counts, ws, batch, c->n_post, c->w0, y, y_stride, st);
+}
 
 size_t bp_jit_ws_bytes(const bp_jit_conn* c) {
   if (!c) return 0;

@@ -76,6 +76,35 @@ def test_event_csr_special_cases():
     np.testing.assert_array_equal(O.event_csr_counts(ip, ix, 400, e2), cnt)
 
 
+def test_batched_products_bruteforce():
+    # a batch of spike vectors E [batch, n_pre]: Y = E M, the dense matrix
+    # product of numpy, for stored (duplicated, unsorted columns, data and
+    # homogeneous) and JIT matrices; all-zero and all-one vectors included
+    rng = np.random.default_rng(8)
+    n_pre, n_post = 30, 41
+    ip, ix = _random_csr(rng, n_pre, n_post, 0.3, dup=True)
+    data = rng.standard_normal(ix.size).astype(np.float32)
+    E = np.stack([S.events(n_pre, f, 20 + i) for i, f in enumerate((0.0, 0.2, 0.5, 1.0, 0.05))])
+    E[2] *= np.uint8(5)  # any non-zero byte is a spike
+    for d, w in ((None, 0.6), (data, 0.0)):
+        D = _dense(ip, ix, d, w, n_pre, n_post)
+        np.testing.assert_allclose(O.event_csr_matmat(ip, ix, d, w, n_post, E), (E != 0) @ D, rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(O.event_csr_counts_batch(ip, ix, n_post, E),
+                                  (E != 0).astype(np.int64) @ _dense(ip, ix, None, 1, n_pre, n_post).astype(np.int64))
+    seed, K, B = 6, 5, 16
+    for wkind, w0, w1 in ((O.W_HOMO, 0.7, 0.0), (O.W_NORMAL, 0.5, 0.1), (O.W_UNIFORM, -1.0, 2.0)):
+        D = np.zeros((n_pre, n_post))
+        for j in range(n_pre):
+            for b in range(-(-n_post // B)):
+                for m, k in enumerate(O.row_block(seed, K, n_post, B, j, b)):
+                    D[j, k] += O.jit_weight(seed, wkind, w0, w1, j, b, m)[0]
+        np.testing.assert_allclose(O.jit_matmat(seed, K, B, wkind, w0, w1, n_post, E), (E != 0) @ D,
+                                   rtol=1e-12, atol=1e-12)
+    ipj, ixj = O.csr_build(seed, K, n_pre, n_post, B)
+    np.testing.assert_array_equal(O.jit_counts_batch(seed, K, B, n_post, E),
+                                  O.event_csr_counts_batch(ipj, ixj, n_post, E))
+
+
 @pytest.mark.parametrize("B", [0, 64])
 def test_jit_equals_csr_of_same_seed(B):
     seed, K, n_pre, n_post = 77, 49, 700, 900
