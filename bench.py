@@ -418,6 +418,26 @@ def bench_serving(bp, torch, n_requests=100, rate_hz=20.0, budget_gib=1.0, quant
                 max_wgs_per_net=max_wgs, batched=a, plain=b)
 
 
+def bench_copy(bp, torch, mib=1024, reps=2):
+    """A plain device-to-device copy of `mib` MiB (torch copy_): the known
+    byte count that calibrates the HBM traffic counters (FETCH_SIZE and
+    WRITE_SIZE per dispatch) and the copy bandwidth this GPU reaches."""
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    return dict(bytes_read=4 * n, bytes_written=4 * n, dispatches=reps + 1, ms_per_copy=ms,
+                read_plus_write_GBps=8.0 * n / (ms * 1e-3) / 1e9)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -431,7 +451,7 @@ def main():
     ap.add_argument("--calls", type=int, default=10000, help="products per point of the operator sweep")
     ap.add_argument("--ops-frac", type=float, default=None,
                     help="run the operator sweep at this firing fraction only (for profiling)")
-    ap.add_argument("--section", choices=["c0", "ops", "dense", "snn", "serving"],
+    ap.add_argument("--section", choices=["c0", "ops", "dense", "snn", "serving", "copy"],
                     help="run only this secondary workload and print its JSON (for profiling)")
     args = ap.parse_args()
     globals()["C2_BLOCK"] = args.block
@@ -450,7 +470,8 @@ def main():
             res = bench_ops(bp, torch, calls=args.calls,
                             **({} if args.ops_frac is None else {"fracs": (args.ops_frac,)}))
         else:
-            res = dict(c0=bench_c0, dense=bench_dense, snn=bench_snn, serving=bench_serving)[args.section](bp, torch)
+            res = dict(c0=bench_c0, dense=bench_dense, snn=bench_snn, serving=bench_serving,
+                       copy=bench_copy)[args.section](bp, torch)
         print(json.dumps({args.section: res}), flush=True)
         return
 
@@ -468,7 +489,7 @@ def main():
     alg_bytes = (28.0 * r["n"] * sim_steps + 8.0 * r["spikes"]) / steps  # per launch
     launch_s = sum(r["launch_ms"]) / steps * 1e-3  # average launch duration
     achieved = alg_bytes / launch_s / 1e9
-    traffic = counters_traffic("net.hip", "net_run_k_coba400k_jit", LAUNCH_STEPS, block=r["block"])
+    traffic = counters_traffic("net.hip", f"net_run_k_coba400k_jit_b{r['block']}", LAUNCH_STEPS, block=r["block"])
     roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
                     traffic=traffic, kernel="net_run_k", alg_bytes_per_launch=alg_bytes,
                     launch_ms=launch_s * 1e3, launches=steps, steps_per_launch=LAUNCH_STEPS,
