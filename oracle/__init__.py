@@ -111,6 +111,24 @@ def _load(path):
                                       C.c_int32, C.c_int32, _f64p, _f64p]
     L.or_jit_vjp.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
                              C.c_int32, C.c_int32, _u8p, _f64p, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.or_ln_f32.restype = C.c_float
+    L.or_ln_f32.argtypes = [C.c_uint32]
+    L.or_ln_f32_many.argtypes = [_u32p, _f32p, C.c_int64]
+    L.or_geo_inv_rate.restype = C.c_float
+    L.or_geo_inv_rate.argtypes = [C.c_double]
+    L.or_geo_gap.restype = C.c_uint32
+    L.or_geo_gap.argtypes = [C.c_uint32, C.c_float]
+    L.or_geo_gap_many.argtypes = [_u32p, C.c_float, _u32p, C.c_int64]
+    L.or_fd_target.restype = C.c_uint32
+    L.or_fd_target.argtypes = [_u32p, C.c_int32, C.c_uint32]
+    L.or_rule_row_block.restype = C.c_int64
+    L.or_rule_row_block.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_float, C.c_int32, C.c_int32, C.c_int32,
+                                    C.c_int32, C.c_int32, C.c_void_p]
+    L.or_rule_csr.restype = C.c_int64
+    L.or_rule_csr.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_float, C.c_int32, C.c_int32, C.c_int32,
+                              C.c_int32, _i32p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]
+    L.or_rule_weights.argtypes = [C.c_uint64, C.c_int32, C.c_double, C.c_double, C.c_int32, _i32p, _i32p, _i32p,
+                                  _f64p]
     L.or_net_v0.argtypes = [C.POINTER(NetParams), _f32p]
     L.or_net_ref_steps.restype = C.c_int32
     L.or_net_ref_steps.argtypes = [C.POINTER(NetParams)]
@@ -188,6 +206,83 @@ def csr_build(seed, K, n_pre, n_post, B):
     got = lib().or_csr_build(seed, K, n_pre, n_post, B, indptr, indices, nnz)
     assert got == nnz
     return indptr, indices[:nnz]
+
+
+# ---------------------------------------------------------------- connectivity rules
+RULE_UNIFORM, RULE_GEOMETRIC, RULE_FIXED_DEGREE = 0, 1, 2
+
+
+def ln_f32(k):
+    """ln(k 2^-24) by the fixed FP32 operation sequence (k in [1, 2^24])."""
+    kk = np.ascontiguousarray(k, np.uint32)
+    out = np.empty(kk.shape, np.float32)
+    lib().or_ln_f32_many(kk.reshape(-1), out.reshape(-1), kk.size)
+    return out
+
+
+def geo_inv_rate(p):
+    """1 / (-ln(1 - p)) computed in FP64, rounded once to FP32."""
+    return float(lib().or_geo_inv_rate(float(p)))
+
+
+def geo_gaps(words, inv_rate):
+    w = np.ascontiguousarray(words, np.uint32)
+    out = np.empty(w.shape, np.uint32)
+    lib().or_geo_gap_many(w.reshape(-1), C.c_float(inv_rate), out.reshape(-1), w.size)
+    return out
+
+
+def fd_target(key, n, i):
+    """Target i of a fixed-degree row with Feistel round keys `key` (4 words)."""
+    kk = np.ascontiguousarray(key, np.uint32)
+    return int(lib().or_fd_target(kk, int(n), int(i)))
+
+
+def rule_row_block(seed, rule, K, inv_rate, degree, n_post, B, j, b):
+    """Targets of (row j, block b) under a connectivity rule, generation order."""
+    buf = np.empty(max(n_post, 1), np.int32)
+    c = lib().or_rule_row_block(seed, rule, K, C.c_float(inv_rate), degree, n_post, B, j, b, _ptr(buf))
+    return buf[:c].copy()
+
+
+def rule_csr(seed, rule, K, inv_rate, degree, n_pre, n_post, B):
+    """(indptr, indices, blk, idx) of a rule's matrix in generation order."""
+    indptr = np.empty(n_pre + 1, np.int32)
+    nnz = lib().or_rule_csr(seed, rule, K, C.c_float(inv_rate), degree, n_pre, n_post, B, indptr, None, None,
+                            None, 1 << 62)
+    indices = np.empty(max(nnz, 1), np.int32)
+    blk = np.empty(max(nnz, 1), np.int32)
+    idx = np.empty(max(nnz, 1), np.int32)
+    lib().or_rule_csr(seed, rule, K, C.c_float(inv_rate), degree, n_pre, n_post, B, indptr, _ptr(indices),
+                      _ptr(blk), _ptr(idx), nnz)
+    return indptr, indices[:nnz], blk[:nnz], idx[:nnz]
+
+
+def rule_csr_sorted(seed, rule, K, inv_rate, degree, n_pre, n_post, B):
+    """(indptr, indices) of the rule's matrix with every row ascending (the
+    stored CSR form)."""
+    ip, ix, _, _ = rule_csr(seed, rule, K, inv_rate, degree, n_pre, n_post, B)
+    ix = ix.copy()
+    for j in range(n_pre):
+        ix[ip[j]:ip[j + 1]].sort()
+    return ip, ix
+
+
+def rule_weights(seed, wkind, w0, w1, indptr, blk, idx):
+    w = np.empty(max(int(indptr[-1]), 1), np.float64)
+    lib().or_rule_weights(seed, wkind, float(w0), float(w1), indptr.size - 1, indptr, blk, idx, w)
+    return w[:int(indptr[-1])]
+
+
+def rule_matvec(indptr, indices, weights, n_post, X):
+    """y = M^T x for a rule CSR in generation order with per-entry weights
+    (None: count each entry once), FP64: x a spike vector (truthy bytes) or
+    a float vector; the sum over rows of weight times x[row]."""
+    x = np.asarray(X)
+    xv = (x != 0).astype(np.float64) if x.dtype == np.uint8 else x.astype(np.float64)
+    rows = np.repeat(np.arange(indptr.size - 1), np.diff(indptr))
+    terms = xv[rows] * (1.0 if weights is None else weights)
+    return np.bincount(indices, weights=terms, minlength=n_post).astype(np.float64)
 
 
 def compact(s):

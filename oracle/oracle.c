@@ -184,6 +184,184 @@ int64_t or_row(uint64_t seed, int32_t K, int32_t n_post, int32_t B, int32_t j, i
 }
 
 /* ------------------------------------------------------------------------ */
+/* Exact-statistics connectivity rules                                       */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Two alternatives to the paper's uniform gaps, each a connectivity rule of
+ * its own (a different matrix for the same seed):
+ *
+ * Rule 1, geometric gaps (Appendix C names them as the exact way to draw a
+ * Bernoulli(p) process: the distance to the next connection is Geo[p],
+ * sampled by inverting the CDF, gap = 1 + floor(log(U) / log(1 - p))).  Every
+ * position is then connected independently with probability p, up to the
+ * resolution of U (24 bits: gaps longer than 16.6 / p, probability 2^-24,
+ * are cut there).  The logarithm decides an integer, so it is evaluated by a
+ * fixed sequence of IEEE single-precision operations, ln_f32 below, the same
+ * on every device; 1 / (-log(1 - p)) is computed once in FP64 and rounded to
+ * FP32 (inv_rate).  Block restarts keep the law exactly: the gap process is
+ * memoryless, so the first target of a block is its start plus gap - 1.
+ *
+ * Rule 2, exactly fixed out-degree k (each row connects to exactly k
+ * distinct targets, each k-subset of [0, n_post) drawn by a keyed
+ * pseudo-random permutation): target i of row j, i < k, is pi_j(i) with pi_j
+ * a permutation of [0, n_post) built by cycle walking (Black and Rogaway,
+ * "Ciphers with arbitrary finite domains", CT-RSA 2002) over a four-round
+ * balanced Feistel network on [0, 4^h), 4^h >= n_post, whose round function
+ * is the 32-bit finalizer of MurmurHash3 (Appleby) applied to the right half
+ * xor a round key; the four round keys are the four words of Philox block
+ * (j, 0, 0, CONN).  Targets come in index order (not sorted); one post block
+ * (B = 0) only.
+ */
+
+/* ln(k 2^-24) for k in [1, 2^24]: k = m 2^e with m in [sqrt(1/2), sqrt(2)),
+ * ln m = 2 atanh(s), s = (m - 1) / (m + 1), by its series to s^9; each step is
+ * one IEEE single-precision operation in the order written. */
+float or_ln_f32(uint32_t k) {
+  int e = 31 - __builtin_clz(k);
+  float m = (float)k;
+  /* m 2^-e, exact (a power-of-two scaling of an integer below 2^25) */
+  m = m * ldexpf(1.0f, -e);
+  if (m > 1.41421356f) {
+    m = m * 0.5f;
+    e += 1;
+  }
+  const float f = m - 1.0f;
+  const float s = f / (2.0f + f);
+  const float z = s * s;
+  float poly = 0.222222222f;            /* 2/9 */
+  poly = 0.285714286f + z * poly;       /* 2/7 */
+  poly = 0.4f + z * poly;               /* 2/5 */
+  poly = 0.666666667f + z * poly;       /* 2/3 */
+  poly = 2.0f + z * poly;
+  const float lnm = s * poly;
+  const float ef = (float)(e - 24);
+  return ef * 0.693145752f + (ef * 1.42860677e-06f + lnm); /* ln 2 = 0.693145752 + 1.42860677e-6 */
+}
+
+void or_ln_f32_many(const uint32_t* k, float* out, int64_t n) {
+  for (int64_t i = 0; i < n; ++i) out[i] = or_ln_f32(k[i]);
+}
+
+/* 1 / (-ln(1 - p)) in FP64, rounded once to FP32; 0 for p outside (0, 1). */
+float or_geo_inv_rate(double p) {
+  if (!(p > 0.0) || !(p < 1.0)) return 0.0f;
+  return (float)(1.0 / -log1p(-p));
+}
+
+/* Geometric gap from one 32-bit word: 1 + floor(-ln(U) inv_rate), U =
+ * ((w >> 8) + 1) 2^-24 in (0, 1], capped at 2^30. */
+uint32_t or_geo_gap(uint32_t w, float inv_rate) {
+  const float L = -or_ln_f32((w >> 8) + 1u);
+  const float t = L * inv_rate;
+  if (!(t < 1073741824.0f)) return 1073741824u;
+  return 1u + (uint32_t)t;
+}
+
+void or_geo_gap_many(const uint32_t* w, float inv_rate, uint32_t* out, int64_t n) {
+  for (int64_t i = 0; i < n; ++i) out[i] = or_geo_gap(w[i], inv_rate);
+}
+
+static uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35u;
+  h ^= h >> 16;
+  return h;
+}
+
+/* Half width h of the Feistel domain: the smallest h >= 1 with 4^h >= n. */
+static uint32_t fd_half_bits(int32_t n) {
+  uint32_t h = 1;
+  while (h < 16 && ((uint64_t)1 << (2 * h)) < (uint64_t)n) ++h;
+  return h;
+}
+
+/* pi(i) for the row whose round keys are key[0..3], i < n. */
+uint32_t or_fd_target(const uint32_t key[4], int32_t n, uint32_t i) {
+  const uint32_t h = fd_half_bits(n);
+  const uint32_t mask = (1u << h) - 1u;
+  uint32_t x = i;
+  do {
+    uint32_t L = x >> h, R = x & mask;
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t F = fmix32(R ^ key[r]) & mask;
+      const uint32_t nl = R;
+      R = L ^ F;
+      L = nl;
+    }
+    x = (L << h) | R;
+  } while (x >= (uint32_t)n);
+  return x;
+}
+
+/* Positions of row j inside post block b under `rule` (0: the paper's
+ * uniform gaps, or_row_block; 1: geometric gaps; 2: exactly `degree`
+ * targets, block 0 only), in generation order; returns how many.  Target m
+ * of (j, b) in this order is connection m of the JIT weight streams. */
+int64_t or_rule_row_block(uint64_t seed, int32_t rule, int32_t K, float inv_rate, int32_t degree,
+                          int32_t n_post, int32_t B, int32_t j, int32_t b, int32_t* out) {
+  if (rule == 0) return or_row_block(seed, K, n_post, B, j, b, out);
+  if (rule == 2) {
+    if (b != 0 || n_post <= 0) return 0;
+    uint32_t key[4];
+    const uint32_t ctr[4] = {(uint32_t)j, 0u, 0u, OR_STREAM_CONN};
+    or_philox(ctr, (uint32_t)seed, (uint32_t)(seed >> 32), key);
+    const int32_t k = degree < n_post ? degree : n_post;
+    for (int32_t i = 0; i < k; ++i)
+      if (out) out[i] = (int32_t)or_fd_target(key, n_post, (uint32_t)i);
+    return k;
+  }
+  /* rule 1: draw 0 places the first target gap - 1 after the block start,
+   * every later draw is one more gap */
+  int64_t start = B > 0 ? (int64_t)b * B : 0;
+  int64_t end = B > 0 ? start + B : n_post;
+  if (end > n_post) end = n_post;
+  int64_t pos = start + (int64_t)or_geo_gap(or_hash(seed, OR_STREAM_CONN, (uint32_t)j, (uint32_t)b, 0), inv_rate) - 1;
+  uint32_t i = 1;
+  int64_t cnt = 0;
+  while (pos < end) {
+    if (out) out[cnt] = (int32_t)pos;
+    ++cnt;
+    pos += (int64_t)or_geo_gap(or_hash(seed, OR_STREAM_CONN, (uint32_t)j, (uint32_t)b, i), inv_rate);
+    ++i;
+  }
+  return cnt;
+}
+
+/* The whole matrix of a rule as CSR in generation order: row j holds its
+ * blocks in order, blk[e] / idx[e] give each entry's block and its index in
+ * the block's generation order (the JIT weight coordinates).  Returns nnz,
+ * or -1 if it exceeds cap; indices / blk / idx may be NULL to count. */
+int64_t or_rule_csr(uint64_t seed, int32_t rule, int32_t K, float inv_rate, int32_t degree, int32_t n_pre,
+                    int32_t n_post, int32_t B, int32_t* indptr, int32_t* indices, int32_t* blk, int32_t* idx,
+                    int64_t cap) {
+  int32_t* buf = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_post > 0 ? n_post : 1));
+  const int32_t nb = rule == 2 ? 1 : n_blocks(n_post, B);
+  int64_t nnz = 0;
+  indptr[0] = 0;
+  for (int32_t j = 0; j < n_pre; ++j) {
+    for (int32_t b = 0; b < nb; ++b) {
+      int64_t c = or_rule_row_block(seed, rule, K, inv_rate, degree, n_post, B, j, b, buf);
+      if (nnz + c > cap) {
+        free(buf);
+        return -1;
+      }
+      for (int64_t m = 0; m < c; ++m) {
+        if (indices) indices[nnz + m] = buf[m];
+        if (blk) blk[nnz + m] = b;
+        if (idx) idx[nnz + m] = (int32_t)m;
+      }
+      nnz += c;
+    }
+    indptr[j + 1] = (int32_t)nnz;
+  }
+  free(buf);
+  return nnz;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Appendix B: CSR (data, indices, indptr) built from the seeded rows        */
 /* ------------------------------------------------------------------------ */
 
@@ -309,6 +487,15 @@ double or_jit_weight(uint64_t seed, int32_t wkind, double w0, double w1, int32_t
   }
   if (unit) *unit = 1.0;
   return w0;
+}
+
+/* w[e] = weight of entry e of a rule CSR in generation order (row j, block
+ * blk[e], index idx[e]): the JIT weight kinds, FP64. */
+void or_rule_weights(uint64_t seed, int32_t wkind, double w0, double w1, int32_t n_pre, const int32_t* indptr,
+                     const int32_t* blk, const int32_t* idx, double* w) {
+  for (int32_t j = 0; j < n_pre; ++j)
+    for (int32_t e = indptr[j]; e < indptr[j + 1]; ++e)
+      w[e] = or_jit_weight(seed, wkind, w0, w1, j, blk[e], idx[e], NULL);
 }
 
 /* y[k] = sum over firing rows j of the weight of (j, k) if connected. */
