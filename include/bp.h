@@ -88,12 +88,40 @@ bp_status bp_hash(uint64_t seed, uint32_t rng_stream, const uint32_t* a, const u
  * Draw i of (j, b) is hash(seed, BP_STREAM_CONN, j, b, i). */
 typedef struct {
   int32_t n_pre, n_post;
-  int32_t max_gap; /* K from bp_max_gap(p), >= 1 */
+  int32_t max_gap; /* K from bp_max_gap(p), >= 1 (rule BP_RULE_UNIFORM) */
   int32_t block;   /* >= 0 */
   uint64_t seed;
   int32_t wkind;   /* BP_W_* (JIT products only) */
   float w0, w1;    /* weight parameters (see BP_W_*) */
+  int32_t rule;    /* BP_RULE_*; 0 = the sampler above */
+  float geo_inv_rate; /* BP_RULE_GEOMETRIC: bp_geo_inv_rate(p) */
+  int32_t degree;  /* BP_RULE_FIXED_DEGREE: targets per row (block must be 0) */
 } bp_jit_conn;
+
+/* Exact-statistics alternatives to the uniform gaps (each defines its own
+ * matrix for a seed; the products, the CSR build and the network treat every
+ * rule alike):
+ *   BP_RULE_GEOMETRIC: the exact Bernoulli(p) process named in Appendix C,
+ *     gaps Geo[p] = 1 + floor(-ln(U) / -ln(1 - p)) with U = ((w >> 8) + 1)
+ *     2^-24 from draw w of (j, b), the logarithm evaluated by a fixed
+ *     sequence of FP32 operations (same gaps on every device); the first
+ *     target of a block is its start plus gap - 1 (memoryless, so blocks keep
+ *     the law), every later draw is one more gap.  Gaps are capped at 2^30.
+ *   BP_RULE_FIXED_DEGREE: every row has exactly min(degree, n_post) distinct
+ *     targets: target i is pi_j(i), pi_j a keyed permutation of [0, n_post)
+ *     (four-round Feistel network over [0, 4^h) with MurmurHash3's 32-bit
+ *     finalizer as round function, cycle-walked into [0, n_post); round keys
+ *     the four words of Philox block (j, 0, 0, BP_STREAM_CONN)).  Targets are
+ *     generated in index order; connection i of the JIT weight streams is
+ *     target i.  One post block only (block == 0). */
+#define BP_RULE_UNIFORM 0
+#define BP_RULE_GEOMETRIC 1
+#define BP_RULE_FIXED_DEGREE 2
+
+/* 1 / (-ln(1 - p)) computed in FP64 and rounded once to FP32: the rate
+ * parameter of BP_RULE_GEOMETRIC.  0 for p outside (0, 1) (p = 1: every
+ * position is connected under a rate of 0). */
+float bp_geo_inv_rate(double p);
 
 /* ------------------------------------------------------------------------ */
 /* Seeded CSR build (Appendix B storage of the Appendix C matrix)            */
@@ -313,6 +341,9 @@ typedef struct {
   int32_t max_wgs; /* upper bound on the workgroups the net runs on
                       (0 = default: one per compute unit, at most 160);
                       fewer lets more nets share the GPU in bp_run_batch */
+  int32_t rule;    /* connectivity rule BP_RULE_* (as in bp_jit_conn) */
+  float geo_inv_rate;
+  int32_t degree;  /* BP_RULE_FIXED_DEGREE: exact out-degree (block 0) */
 } bp_net_desc;
 
 typedef struct bp_net_s* bp_net;

@@ -11,14 +11,15 @@ import math
 import torch
 
 from . import _abi
-from ._abi import (COBA, CONN_CSR, CONN_JIT, CUBA, STREAM_CONN, STREAM_V0, STREAM_W, W_HOMO, W_NORMAL,
-                   W_UNIFORM, BpError, check, lib)
+from ._abi import (COBA, CONN_CSR, CONN_JIT, CUBA, RULE_FIXED_DEGREE, RULE_GEOMETRIC, RULE_UNIFORM, STREAM_CONN,
+                   STREAM_V0, STREAM_W, W_HOMO, W_NORMAL, W_UNIFORM, BpError, check, lib)
 
 __all__ = [
     "lib", "BpError", "max_gap", "hash_words", "csr_build", "csr_tile_index", "compact", "event_csr_matvec",
     "event_csr_matvec_noalloc", "event_csr_matmat", "jit_conn_matmat",
     "jit_conn_matvec", "jit_conn_matvec_dense", "jit_conn_matmat_dense", "event_csr_backward", "jit_conn_backward", "Net", "run_batch", "JitConn",
-    "COBA", "CUBA", "CONN_CSR", "CONN_JIT", "W_HOMO", "W_NORMAL", "W_UNIFORM",
+    "COBA", "CUBA", "CONN_CSR", "CONN_JIT", "W_HOMO", "W_NORMAL", "W_UNIFORM", "RULE_UNIFORM", "RULE_GEOMETRIC",
+    "RULE_FIXED_DEGREE", "geo_inv_rate",
 ]
 
 
@@ -88,6 +89,11 @@ def max_gap(p):
     return int(lib().bp_max_gap(float(p)))
 
 
+def geo_inv_rate(p):
+    """1 / -ln(1 - p) in FP64 rounded to FP32: the geometric rule's rate."""
+    return float(lib().bp_geo_inv_rate(float(p)))
+
+
 def hash_words(seed, rng_stream, a, b, k):
     a = _dev(a, torch.int32, "a")
     b = _dev(b, torch.int32, "b")
@@ -98,14 +104,24 @@ def hash_words(seed, rng_stream, a, b, k):
 
 
 class JitConn:
-    """Fixed-probability connectivity regenerated from a seed."""
+    """Fixed-probability connectivity regenerated from a seed.  rule:
+    RULE_UNIFORM (the paper's gaps uniform on [1, K]), RULE_GEOMETRIC (exact
+    Bernoulli(p): pass p or inv_rate), RULE_FIXED_DEGREE (exactly `degree`
+    targets per row, block 0)."""
 
-    def __init__(self, n_pre, n_post, p=None, K=None, block=0, seed=0, wkind=W_HOMO, w0=1.0, w1=0.0):
-        if K is None:
-            K = max_gap(p)
-        if K < 1:
-            raise ValueError(f"invalid connection probability {p}")
-        self.c = _abi.JitConn(n_pre, n_post, K, block, seed, wkind, w0, w1)
+    def __init__(self, n_pre, n_post, p=None, K=None, block=0, seed=0, wkind=W_HOMO, w0=1.0, w1=0.0,
+                 rule=RULE_UNIFORM, inv_rate=None, degree=0):
+        if rule == RULE_UNIFORM:
+            if K is None:
+                K = max_gap(p)
+            if K < 1:
+                raise ValueError(f"invalid connection probability {p}")
+        else:
+            K = 1 if K is None else K
+        if rule == RULE_GEOMETRIC and inv_rate is None:
+            inv_rate = geo_inv_rate(p)
+        self.c = _abi.JitConn(n_pre, n_post, K, block, seed, wkind, w0, w1, rule,
+                              0.0 if inv_rate is None else inv_rate, degree)
 
     def __getattr__(self, name):
         return getattr(self.__dict__["c"], name)
@@ -346,15 +362,20 @@ COBA_DEFAULTS = dict(w_exc=0.6, w_inh=6.7, tau_m=20.0, tau_e=5.0, tau_i=10.0, ta
                      v0_lo=-60.0, v0_hi=-50.0)
 
 
-def net_desc(n, n_exc=None, p=None, K=None, conn=CONN_JIT, block=0, seed=0, model=COBA, max_wgs=0, **params):
+def net_desc(n, n_exc=None, p=None, K=None, conn=CONN_JIT, block=0, seed=0, model=COBA, max_wgs=0,
+             rule=RULE_UNIFORM, degree=0, inv_rate=None, **params):
     kw = dict(COBA_DEFAULTS)
     kw.update(params)
     if n_exc is None:
         n_exc = int(math.floor(0.8 * n))
+    pp = p if p is not None else 80.0 / n
     if K is None:
-        K = max_gap(p if p is not None else 80.0 / n)
+        K = max_gap(pp)
+    if rule == RULE_GEOMETRIC and inv_rate is None:
+        inv_rate = geo_inv_rate(pp)
     return _abi.NetDesc(model=model, n=n, n_exc=n_exc, conn=conn, max_gap=K, block=block, seed=seed,
-                        max_wgs=max_wgs, **kw)
+                        max_wgs=max_wgs, rule=rule, geo_inv_rate=0.0 if inv_rate is None else inv_rate,
+                        degree=degree, **kw)
 
 
 def net_bytes(desc):

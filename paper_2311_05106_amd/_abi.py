@@ -11,11 +11,13 @@ W_HOMO, W_NORMAL, W_UNIFORM = 0, 1, 2
 STREAM_CONN, STREAM_W, STREAM_V0 = 1, 2, 3
 COBA, CUBA = 0, 1
 CONN_CSR, CONN_JIT = 0, 1
+RULE_UNIFORM, RULE_GEOMETRIC, RULE_FIXED_DEGREE = 0, 1, 2
 
 
 class JitConn(C.Structure):
     _fields_ = [("n_pre", C.c_int32), ("n_post", C.c_int32), ("max_gap", C.c_int32), ("block", C.c_int32),
-                ("seed", C.c_uint64), ("wkind", C.c_int32), ("w0", C.c_float), ("w1", C.c_float)]
+                ("seed", C.c_uint64), ("wkind", C.c_int32), ("w0", C.c_float), ("w1", C.c_float),
+                ("rule", C.c_int32), ("geo_inv_rate", C.c_float), ("degree", C.c_int32)]
 
 
 class Csr(C.Structure):
@@ -31,7 +33,7 @@ class NetDesc(C.Structure):
                 ("tau_i", C.c_float), ("tau_ref", C.c_float), ("v_rest", C.c_float), ("v_th", C.c_float),
                 ("v_reset", C.c_float), ("e_exc", C.c_float), ("e_inh", C.c_float), ("r", C.c_float),
                 ("i_ext", C.c_float), ("dt", C.c_float), ("v0_lo", C.c_float), ("v0_hi", C.c_float),
-                ("max_wgs", C.c_int32)]
+                ("max_wgs", C.c_int32), ("rule", C.c_int32), ("geo_inv_rate", C.c_float), ("degree", C.c_int32)]
 
 
 class NetInfo(C.Structure):
@@ -56,6 +58,7 @@ SIGNATURES = {
     "bp_last_error": (C.c_char_p, []),
     "bp_version": (C.c_char_p, []),
     "bp_max_gap": (_i32, [C.c_double]),
+    "bp_geo_inv_rate": (C.c_float, [C.c_double]),
     "bp_hash": (_i32, [_u64, _u32, _vp, _vp, _vp, _vp, _i64, _vp]),
     "bp_csr_count": (_i32, [C.POINTER(JitConn), _vp, _vp]),
     "bp_csr_fill": (_i32, [C.POINTER(JitConn), _vp, _vp, _vp]),

@@ -79,31 +79,132 @@ __device__ __forceinline__ float u_open0(uint32_t w) { return (float)((w >> 8) +
 __device__ __forceinline__ float u_open1(uint32_t w) { return (float)(w >> 8) * (1.0f / 16777216.0f); }
 
 // ---------------------------------------------------------------------------
-// Positions of row j inside post block b of the fixed-probability matrix
-// (gaps uniform on [1, K]; block == 0: one block, first target = gap - 1;
-// block > 0: stationary start block_start + min(ra, rb)), restricted to the
-// window [lo, hi).  emit(pos, m) receives every target in the window, m being
-// its index among all targets of (j, b) in generation order.  Returns the
-// number of targets generated before the walk left the window or block.
+// Connectivity rules.  0: the paper's sampler (gaps uniform on [1, K]).
+// 1: geometric gaps, the exact Bernoulli(p) process (gap = 1 +
+// floor(-ln(U) / -ln(1 - p)), the logarithm by the fixed FP32 operation
+// sequence of ln_f32 so that every device decides the same gaps).
+// 2: exactly `degree` distinct targets per row (one post block): target i is
+// pi_j(i) for a keyed permutation of the columns, a four-round balanced
+// Feistel network over [0, 4^h) whose round function is MurmurHash3's 32-bit
+// finalizer of the right half xor a round key, cycle-walked into
+// [0, n_post) (Black and Rogaway, CT-RSA 2002); the round keys are the four
+// words of Philox block (j, 0, 0, CONN).
 // ---------------------------------------------------------------------------
-template <class Emit>
-__device__ __forceinline__ void gen_block(uint64_t seed, uint32_t K, int32_t n_post, int32_t B, uint32_t j,
-                                          uint32_t b, int64_t lo, int64_t hi, Emit&& emit) {
-  DrawSeq d(seed, kStreamConn, j, b);
+constexpr int kRuleUniform = 0, kRuleGeometric = 1, kRuleFixedDegree = 2;
+
+struct ConnGen {
+  uint64_t seed;
+  uint32_t K;        // rule 0
+  int32_t n_post, B;
+  int32_t rule;
+  float inv_rate;    // rule 1: 1 / -ln(1 - p), FP32
+  int32_t degree;    // rule 2
+};
+
+// ln(k 2^-24) for k in [1, 2^24]: k = m 2^e, m folded into
+// [sqrt(1/2), sqrt(2)), ln m = 2 atanh(s), s = (m - 1) / (m + 1), by its
+// series to s^9; every step one IEEE single-precision operation in this order
+// (contraction is disabled for the library; the division is correctly
+// rounded), with ln 2 split into a head of 16 bits and a tail.
+__device__ __forceinline__ float ln_f32(uint32_t k) {
+  int e = 31 - __clz((int)k);
+  float m = (float)k * __uint_as_float((uint32_t)(127 - e) << 23);  // k 2^-e, exact
+  if (m > 1.41421356f) {
+    m = m * 0.5f;
+    e += 1;
+  }
+  const float f = m - 1.0f;
+  const float s = f / (2.0f + f);
+  const float z = s * s;
+  float poly = 0.222222222f;
+  poly = 0.285714286f + z * poly;
+  poly = 0.4f + z * poly;
+  poly = 0.666666667f + z * poly;
+  poly = 2.0f + z * poly;
+  const float lnm = s * poly;
+  const float ef = (float)(e - 24);
+  return ef * 0.693145752f + (ef * 1.42860677e-06f + lnm);
+}
+
+// Geometric gap from one word: 1 + floor(-ln(U) inv_rate), U = ((w >> 8) + 1)
+// 2^-24, capped at 2^30.
+__device__ __forceinline__ uint32_t geo_gap(uint32_t w, float inv_rate) {
+  const float t = -ln_f32((w >> 8) + 1u) * inv_rate;
+  return t < 1073741824.0f ? 1u + (uint32_t)t : 1073741824u;
+}
+
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35u;
+  h ^= h >> 16;
+  return h;
+}
+
+// Half width h of the Feistel domain: the smallest h >= 1 with 4^h >= n.
+__device__ __forceinline__ uint32_t fd_half_bits(int32_t n) {
+  const uint32_t bits = n > 1 ? 32u - (uint32_t)__clz(n - 1) : 0u;
+  const uint32_t h = (bits + 1u) >> 1;
+  return h < 1u ? 1u : (h > 16u ? 16u : h);
+}
+
+// pi(i), i < n, for the round keys `key` and half width h.
+__device__ __forceinline__ uint32_t fd_target(const Words4& key, uint32_t h, int32_t n, uint32_t i) {
+  const uint32_t mask = (1u << h) - 1u;
+  uint32_t x = i;
+  do {
+    uint32_t L = x >> h, R = x & mask;
+    uint32_t F = fmix32(R ^ key.x) & mask;
+    L ^= F;
+    F = fmix32(L ^ key.y) & mask;
+    R ^= F;
+    F = fmix32(R ^ key.z) & mask;
+    L ^= F;
+    F = fmix32(L ^ key.w) & mask;
+    R ^= F;
+    x = (L << h) | R;  // four rounds of (L, R) -> (R, L ^ F(R)), written in place
+  } while (x >= (uint32_t)n);
+  return x;
+}
+
+__device__ __forceinline__ Words4 fd_keys(uint64_t seed, uint32_t j) {
+  return philox10(j, 0u, 0u, kStreamConn, (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+// ---------------------------------------------------------------------------
+// Positions of row j inside post block b of the connectivity (rule 0: gaps
+// uniform on [1, K]; block == 0: one block, first target = gap - 1; block >
+// 0: stationary start block_start + min(ra, rb); rule 1: first target gap - 1
+// after the block start, then geometric gaps; rule 2: the degree targets of
+// the row in index order), restricted to the window [lo, hi).  emit(pos, m)
+// receives every target in the window, m being its index among all targets
+// of (j, b) in generation order (the JIT weight coordinate).
+// ---------------------------------------------------------------------------
+template <int RULE, class Emit>
+__device__ __forceinline__ void gen_walk(const ConnGen& g, uint32_t j, uint32_t b, int64_t lo, int64_t hi,
+                                         Emit&& emit) {
+  DrawSeq d(g.seed, kStreamConn, j, b);
   int64_t start, end, pos;
   uint32_t i;
-  if (B > 0) {
-    start = (int64_t)b * B;
-    end = start + B;
-    if (end > n_post) end = n_post;
-    const uint32_t ra = below(d(0), K);
-    const uint32_t rb = below(d(1), K + 1u);
+  if (g.B > 0) {
+    start = (int64_t)b * g.B;
+    end = start + g.B;
+    if (end > g.n_post) end = g.n_post;
+  } else {
+    start = 0;
+    end = g.n_post;
+  }
+  if constexpr (RULE == kRuleGeometric) {
+    pos = start + (int64_t)geo_gap(d(0), g.inv_rate) - 1;
+    i = 1;
+  } else if (g.B > 0) {
+    const uint32_t ra = below(d(0), g.K);
+    const uint32_t rb = below(d(1), g.K + 1u);
     pos = start + (int64_t)(ra < rb ? ra : rb);
     i = 2;
   } else {
-    start = 0;
-    end = n_post;
-    pos = (int64_t)below(d(0), K);
+    pos = (int64_t)below(d(0), g.K);
     i = 1;
   }
   if (hi < end) end = hi;
@@ -111,8 +212,28 @@ __device__ __forceinline__ void gen_block(uint64_t seed, uint32_t K, int32_t n_p
   while (pos < end) {
     if (pos >= lo) emit((int32_t)pos, m);
     ++m;
-    pos += 1 + (int64_t)below(d(i), K);
+    if constexpr (RULE == kRuleGeometric) pos += (int64_t)geo_gap(d(i), g.inv_rate);
+    else pos += 1 + (int64_t)below(d(i), g.K);
     ++i;
+  }
+}
+
+template <class Emit>
+__device__ __forceinline__ void gen_block(const ConnGen& g, uint32_t j, uint32_t b, int64_t lo, int64_t hi,
+                                          Emit&& emit) {
+  if (g.rule == kRuleFixedDegree) {
+    if (b != 0u) return;
+    const Words4 key = fd_keys(g.seed, j);
+    const uint32_t h = fd_half_bits(g.n_post);
+    const int32_t k = g.degree < g.n_post ? g.degree : g.n_post;
+    for (int32_t i = 0; i < k; ++i) {
+      const int32_t t = (int32_t)fd_target(key, h, g.n_post, (uint32_t)i);
+      if (t >= lo && t < hi) emit(t, (uint32_t)i);
+    }
+  } else if (g.rule == kRuleGeometric) {
+    gen_walk<kRuleGeometric>(g, j, b, lo, hi, emit);
+  } else {
+    gen_walk<kRuleUniform>(g, j, b, lo, hi, emit);
   }
 }
 

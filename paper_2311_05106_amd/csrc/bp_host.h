@@ -8,6 +8,7 @@
 #include <stdio.h>
 
 #include "../../include/bp.h"
+#include "bp_device.h"
 
 namespace bp {
 
@@ -39,7 +40,21 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 int device_cu_count();
 
+// The device generator of a connectivity descriptor.
+__host__ __device__ inline ConnGen conn_gen(const bp_jit_conn& c) {
+  ConnGen g;
+  g.seed = c.seed;
+  g.K = (uint32_t)c.max_gap;
+  g.n_post = c.n_post;
+  g.B = c.block;
+  g.rule = c.rule;
+  g.inv_rate = c.geo_inv_rate;
+  g.degree = c.degree;
+  return g;
+}
+
 bp_status check_conn(const bp_jit_conn* c, bool weights);
+bp_status check_rule(int32_t rule, int32_t max_gap, float inv_rate, int32_t degree, int32_t block);
 
 // tp[j][t] = first position of sorted row j with column >= t * tile
 // (tp[j][n_tiles] = end of row); tp has n_pre * (n_tiles + 1) entries.

@@ -35,11 +35,14 @@ __global__ void hash_k(uint64_t seed, uint32_t stream, const uint32_t* __restric
 __global__ void csr_rowlen_k(bp_jit_conn c, int32_t* __restrict__ rowlen) {
   const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= c.n_pre) return;
+  if (c.rule == kRuleFixedDegree) {  // exactly min(degree, n_post) targets
+    rowlen[j] = c.degree < c.n_post ? c.degree : c.n_post;
+    return;
+  }
+  const ConnGen G = conn_gen(c);
   const int32_t nb = c.block > 0 ? (int32_t)(((int64_t)c.n_post + c.block - 1) / c.block) : 1;
   int32_t cnt = 0;
-  for (int32_t b = 0; b < nb; ++b)
-    gen_block(c.seed, (uint32_t)c.max_gap, c.n_post, c.block, (uint32_t)j, (uint32_t)b, 0, c.n_post,
-              [&](int32_t, uint32_t) { ++cnt; });
+  for (int32_t b = 0; b < nb; ++b) gen_block(G, (uint32_t)j, (uint32_t)b, 0, c.n_post, [&](int32_t, uint32_t) { ++cnt; });
   rowlen[j] = cnt;
 }
 
@@ -74,13 +77,36 @@ __global__ void csr_fill_k(bp_jit_conn c, const int32_t* __restrict__ indptr, in
   const int32_t nb = c.block > 0 ? (int32_t)(((int64_t)c.n_post + c.block - 1) / c.block) : 1;
   int32_t* out = indices + indptr[j];
   const int32_t cap = indptr[j + 1] - indptr[j];
+  const ConnGen G = conn_gen(c);
   int32_t cnt = 0;
   for (int32_t b = 0; b < nb; ++b)
-    gen_block(c.seed, (uint32_t)c.max_gap, c.n_post, c.block, (uint32_t)j, (uint32_t)b, 0, c.n_post,
-              [&](int32_t pos, uint32_t) {
-                if (cnt < cap) out[cnt] = pos;
-                ++cnt;
-              });
+    gen_block(G, (uint32_t)j, (uint32_t)b, 0, c.n_post, [&](int32_t pos, uint32_t) {
+      if (cnt < cap) out[cnt] = pos;
+      ++cnt;
+    });
+  if (c.rule == kRuleFixedDegree) {
+    // the targets come in permutation order: heapsort the row in place so
+    // that stored rows are strictly increasing like the other rules'
+    const int32_t n = cnt < cap ? cnt : cap;
+    auto sift = [&](int32_t root, int32_t end) {
+      const int32_t v = out[root];
+      while (2 * root + 1 < end) {
+        int32_t ch = 2 * root + 1;
+        if (ch + 1 < end && out[ch + 1] > out[ch]) ++ch;
+        if (out[ch] <= v) break;
+        out[root] = out[ch];
+        root = ch;
+      }
+      out[root] = v;
+    };
+    for (int32_t r = n / 2 - 1; r >= 0; --r) sift(r, n);
+    for (int32_t e = n - 1; e > 0; --e) {
+      const int32_t t = out[0];
+      out[0] = out[e];
+      out[e] = t;
+      sift(0, e);
+    }
+  }
 }
 
 // Tile index of a sorted CSR: tp[j][t] = first idx of row j with column >= t*P.
@@ -112,11 +138,24 @@ bp_status launch_tile_index(const int32_t* indptr, const int32_t* indices, int32
   return BP_OK;
 }
 
+bp_status check_rule(int32_t rule, int32_t max_gap, float inv_rate, int32_t degree, int32_t block) {
+  BP_REQUIRE(rule == kRuleUniform || rule == kRuleGeometric || rule == kRuleFixedDegree, "unknown rule %d", rule);
+  if (rule == kRuleUniform) BP_REQUIRE(max_gap >= 1, "max_gap must be >= 1 (got %d)", max_gap);
+  if (rule == kRuleGeometric)
+    BP_REQUIRE(inv_rate >= 0.f && inv_rate < 1e30f, "geo_inv_rate must be finite and >= 0 (got %g)", inv_rate);
+  if (rule == kRuleFixedDegree) {
+    BP_REQUIRE(degree >= 0, "degree must be >= 0 (got %d)", degree);
+    BP_REQUIRE(block == 0, "fixed out-degree rows take one post block (block 0, got %d)", block);
+  }
+  return BP_OK;
+}
+
 bp_status check_conn(const bp_jit_conn* c, bool weights) {
   BP_REQUIRE(c != nullptr, "null connectivity descriptor");
   BP_REQUIRE(c->n_pre >= 0 && c->n_post >= 0, "negative size (n_pre %d, n_post %d)", c->n_pre, c->n_post);
-  BP_REQUIRE(c->max_gap >= 1, "max_gap must be >= 1 (got %d)", c->max_gap);
   BP_REQUIRE(c->block >= 0, "block must be >= 0 (got %d)", c->block);
+  bp_status s = check_rule(c->rule, c->max_gap, c->geo_inv_rate, c->degree, c->block);
+  if (s) return s;
   if (weights)
     BP_REQUIRE(c->wkind == kWHomo || c->wkind == kWNormal || c->wkind == kWUniform, "unknown weight kind %d",
                c->wkind);
@@ -131,6 +170,11 @@ extern "C" {
 
 const char* bp_last_error(void) { return bp::g_err; }
 const char* bp_version(void) { return "bpmi 0.1 gfx950"; }
+
+float bp_geo_inv_rate(double p) {
+  if (!(p > 0.0) || !(p < 1.0)) return 0.0f;
+  return (float)(1.0 / -log1p(-p));
+}
 
 int32_t bp_max_gap(double p) {
   if (!(p > 0.0) || p > 1.0) return -1;

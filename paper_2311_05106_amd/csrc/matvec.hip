@@ -399,12 +399,14 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
       const int items = total * nbt;
       const uint64_t seed = a.jit.seed;
       const uint32_t K = (uint32_t)a.jit.max_gap;
+      const ConnGen G = conn_gen(a.jit);
       const int32_t wkind = a.jit.wkind, n_post = a.n_post;
       const float w0 = a.jit.w0, w1 = a.jit.w1;
       // the four-lane walk emits every target from the block start, so it
       // needs the tile to begin there (a block wider than the LDS tile is cut
       // into several tiles, the later ones starting inside the block)
-      if (B > 0 && nbt == 1 && lo == (int64_t)b_lo * B && items * 4 <= kMvThreads) {
+      // (uniform gaps only: it reads the gap law off the draws directly)
+      if (a.jit.rule == kRuleUniform && B > 0 && nbt == 1 && lo == (int64_t)b_lo * B && items * 4 <= kMvThreads) {
         // Few rows in the pass: four lanes per row.  In pass P lane q draws
         // generator block 4P + q (draws 16P + 4q .. 16P + 4q + 3); a prefix
         // of the lanes' gap sums over the quad places the targets, so a row
@@ -470,7 +472,7 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
         RowScale<MODE> sc;
         sc.load(a, j, c0, mg);
         DrawSeq wd(seed, kStreamW, j, b);
-        gen_block(seed, K, n_post, B, j, b, lo, hi, [&](int32_t pos, uint32_t m) {
+        gen_block(G, j, b, lo, hi, [&](int32_t pos, uint32_t m) {
           jit_put<MODE>(acc, pos - lo, width, mk, sc, wd, wkind, w0, w1, m, mg);
         });
       }
@@ -686,12 +688,12 @@ __global__ void jit_backward_k(bp_jit_conn c, const uint8_t* __restrict__ ev, co
     const bool on = ev[j] != 0;
     float acc = 0.f;
     const uint64_t seed = c.seed;
-    const uint32_t K = (uint32_t)c.max_gap;
+    const ConnGen G = conn_gen(c);
     const int32_t n_post = c.n_post, B = c.block, wkind = c.wkind;
     const float w0 = c.w0, w1 = c.w1;
     for (int32_t b = 0; b < nb; ++b) {
       DrawSeq wd(seed, kStreamW, (uint32_t)j, (uint32_t)b);
-      gen_block(seed, K, n_post, B, (uint32_t)j, (uint32_t)b, 0, n_post, [&](int32_t pos, uint32_t m) {
+      gen_block(G, (uint32_t)j, (uint32_t)b, 0, n_post, [&](int32_t pos, uint32_t m) {
         float unit;
         const float wjk = jit_weight(wd, wkind, w0, w1, m, &unit);
         const float g = dy[pos];

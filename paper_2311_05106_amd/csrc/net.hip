@@ -65,6 +65,8 @@ constexpr uint32_t kSpinLimit = 1u << 22;
 struct NetDev {
   int32_t model, n, n_exc, conn, K, block, nb, ref_steps;
   uint64_t seed;
+  int32_t rule, degree;  // connectivity rule (kRule*) and exact out-degree of rule 2
+  float inv_rate;        // rule 1: 1 / -ln(1 - p)
   float w_exc, w_inh, de, di, a, v_rest, v_th, v_reset, e_exc, e_inh, r, i_ext;
   int32_t n_wg, range;
   int32_t push;  // several workgroups exchange targets (JIT, one post block), else spike ids
@@ -416,6 +418,7 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
   const int32_t nbt = b_hi - b_lo + 1;
   const uint64_t seed = N.seed;
   const uint32_t K = (uint32_t)N.K;
+  const ConnGen G{N.seed, (uint32_t)N.K, N.n, N.block, N.rule, N.inv_rate, N.degree};
   unsigned long long ev_local = 0;
 
   // accumulate the targets of the staged firing rows sh.ids[0, nact)
@@ -428,7 +431,7 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
         const uint32_t j = (uint32_t)sh.ids[ai];
         if (j >= (uint32_t)N.n) continue;
         uint32_t* cnt = ((int32_t)j < N.n_exc) ? sh.cE : sh.cI;
-        gen_block(N.seed, (uint32_t)N.K, N.n, B, j, b, lo, hi, [&](int32_t pos, uint32_t) {
+        gen_block(G, j, b, lo, hi, [&](int32_t pos, uint32_t) {
           atomicAdd(&cnt[pos - lo], 1u);
           ++ev_local;
         });
@@ -614,8 +617,21 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
   auto push_generate = [&](int total) {
     const int lane = lane_id();
     if constexpr (CONN == 1) {
-      if (B == 0) {
+      if (B == 0 && N.rule == kRuleFixedDegree) {
+        // exactly `degree` targets per spike: lane l computes targets
+        // l, l + 64, ... of the row's permutation
+        const uint32_t h = fd_half_bits(N.n);
+        const int32_t k = N.degree < N.n ? N.degree : N.n;
+        for (int si = wave; si < total; si += kNetWaves) {
+          const uint32_t j = (uint32_t)sh.own[si];
+          const uint32_t inh = (int32_t)j >= N.n_exc ? 0x1000u : 0u;
+          const Words4 key = fd_keys(seed, j);
+          for (int32_t i = lane; i < k; i += kWave) emit((int32_t)fd_target(key, h, N.n, (uint32_t)i), inh);
+        }
+      } else if (B == 0) {
         const uint32_t cap = (uint32_t)N.n;
+        const bool geo = N.rule == kRuleGeometric;
+        const float inv_rate = N.inv_rate;
         for (int si = wave; si < total; si += kNetWaves) {
           const uint32_t j = (uint32_t)sh.own[si];
           const uint32_t inh = (int32_t)j >= N.n_exc ? 0x1000u : 0u;
@@ -623,12 +639,14 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
           for (uint32_t c = 0;; ++c) {
             const uint32_t blk = c * kWave + (uint32_t)lane;
             const Words4 q = philox10(j, 0u, blk, kStreamConn, (uint32_t)seed, (uint32_t)(seed >> 32));
-            // draw 0 is the first position itself, later draws are gaps 1 + U[0, K);
-            // a gap beyond n ends the row, so gaps are clipped to n
-            const uint32_t g0 = min(below(q.x, K) + (blk != 0u ? 1u : 0u), cap);
-            const uint32_t g1 = min(1u + below(q.y, K), cap);
-            const uint32_t g2 = min(1u + below(q.z, K), cap);
-            const uint32_t g3 = min(1u + below(q.w, K), cap);
+            // draw 0 is the first position itself (gap - 1), later draws are
+            // gaps (1 + U[0, K), or geometric); a gap beyond n ends the row,
+            // so gaps are clipped to n
+            const uint32_t first = blk == 0u ? 1u : 0u;
+            const uint32_t g0 = min(geo ? geo_gap(q.x, inv_rate) - first : below(q.x, K) + 1u - first, cap);
+            const uint32_t g1 = min(geo ? geo_gap(q.y, inv_rate) : 1u + below(q.y, K), cap);
+            const uint32_t g2 = min(geo ? geo_gap(q.z, inv_rate) : 1u + below(q.z, K), cap);
+            const uint32_t g3 = min(geo ? geo_gap(q.w, inv_rate) : 1u + below(q.w, K), cap);
             const int s4 = (int)(g0 + g1 + g2 + g3);
             const int incl = wave_incl_scan(s4);
             int32_t p = base + incl - s4 + (int32_t)g0;
@@ -650,7 +668,7 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
           const uint32_t b = (uint32_t)(it - si * N.nb);
           const uint32_t j = (uint32_t)sh.own[si];
           const uint32_t inh = (int32_t)j >= N.n_exc ? 0x1000u : 0u;
-          gen_block(seed, K, N.n, B, j, b, 0, N.n, [&](int32_t pos, uint32_t) { emit(pos, inh); });
+          gen_block(G, j, b, 0, N.n, [&](int32_t pos, uint32_t) { emit(pos, inh); });
         }
       }
     } else {
@@ -1011,7 +1029,13 @@ struct Layout {
 
 static int64_t nnz_upper_bound(const bp_net_desc* d) {
   const double n = d->n;
-  const double per_row = n * 2.0 / ((double)d->max_gap + 1.0) + 1.0;
+  if (d->rule == kRuleFixedDegree) return (int64_t)d->n * (d->degree < d->n ? d->degree : d->n);
+  // expected targets per row: 2 n / (K + 1) for uniform gaps, n p with
+  // p = 1 - exp(-1 / inv_rate) for geometric gaps
+  const double dens = d->rule == kRuleGeometric
+                          ? (d->geo_inv_rate > 0.f ? -expm1(-1.0 / (double)d->geo_inv_rate) : 1.0)
+                          : 2.0 / ((double)d->max_gap + 1.0);
+  const double per_row = n * dens + 1.0;
   const double mean = n * per_row;
   return (int64_t)(mean + 8.0 * sqrt(n * (per_row + 1.0)) + 4096.0);
 }
@@ -1022,8 +1046,9 @@ static bp_status make_layout(const bp_net_desc* d, Layout* L) {
   BP_REQUIRE(d->n_exc >= 0 && d->n_exc <= d->n, "n_exc must be in [0, n]");
   BP_REQUIRE(d->model == BP_COBA || d->model == BP_CUBA, "unknown model %d", d->model);
   BP_REQUIRE(d->conn == BP_CONN_CSR || d->conn == BP_CONN_JIT, "unknown connectivity %d", d->conn);
-  BP_REQUIRE(d->max_gap >= 1, "max_gap must be >= 1");
   BP_REQUIRE(d->block >= 0, "block must be >= 0");
+  bp_status rs = check_rule(d->rule, d->max_gap, d->geo_inv_rate, d->degree, d->block);
+  if (rs) return rs;
   BP_REQUIRE(d->dt > 0.f && d->tau_m > 0.f && d->tau_e > 0.f && d->tau_i > 0.f && d->tau_ref >= 0.f,
              "time constants and dt must be positive");
   BP_REQUIRE(d->max_wgs >= 0, "max_wgs must be >= 0");
@@ -1182,6 +1207,9 @@ bp_status bp_create_net(const bp_net_desc* d, void* ws, size_t bytes, bp_stream 
   H.conn = d->conn;
   H.K = d->max_gap;
   H.block = d->block;
+  H.rule = d->rule;
+  H.degree = d->degree;
+  H.inv_rate = d->geo_inv_rate;
   H.nb = L.nb;
   H.ref_steps = (int32_t)floor((double)d->tau_ref / (double)d->dt + 0.5);
   H.seed = d->seed;
@@ -1238,6 +1266,9 @@ bp_status bp_create_net(const bp_net_desc* d, void* ws, size_t bytes, bp_stream 
     c.max_gap = d->max_gap;
     c.block = d->block;
     c.seed = d->seed;
+    c.rule = d->rule;
+    c.geo_inv_rate = d->geo_inv_rate;
+    c.degree = d->degree;
     int32_t* indptr = (int32_t*)(base + L.off_indptr);
     int32_t* indices = (int32_t*)(base + L.off_indices);
     if ((s = bp_csr_count(&c, indptr, stream))) return fail(s);
