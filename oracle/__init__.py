@@ -129,6 +129,10 @@ def _load(path):
                               C.c_int32, _i32p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]
     L.or_rule_weights.argtypes = [C.c_uint64, C.c_int32, C.c_double, C.c_double, C.c_int32, _i32p, _i32p, _i32p,
                                   _f64p]
+    L.or_proj_run_f64.argtypes = [_i32p, _i32p, C.c_void_p, C.c_double, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                  C.c_double, C.c_double, C.c_int32, C.c_int32, _u8p, _f64p, _f64p]
+    L.or_proj_run_f32.argtypes = [_i32p, _i32p, C.c_void_p, C.c_float, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                  C.c_float, C.c_float, C.c_int32, C.c_int32, _u8p, _f32p, _f64p]
     L.or_net_v0.argtypes = [C.POINTER(NetParams), _f32p]
     L.or_net_ref_steps.restype = C.c_int32
     L.or_net_ref_steps.argtypes = [C.POINTER(NetParams)]
@@ -482,6 +486,34 @@ def net_run(P, state, T, indptr=None, indices=None, iext_vec=None, want_raster=T
        _ptr(iv), _ptr(raster), _ptr(counts), _ptr(events))
     state.t += T
     return raster, counts, int(events[0])
+
+
+# ---------------------------------------------------------------- projections
+ALIGN_POST, ALIGN_PRE = 0, 1
+SYN_EXP, SYN_SAT = 0, 1
+
+
+def proj_run(indptr, indices, data, w, n_post, align, syn, decay, u, delay, raster, state=None, precision=64):
+    """T steps of a projection with a `delay`-step spike delay driven by the
+    presynaptic raster [T, n_pre] (Section 4.3, Appendix D).  Returns
+    (g [T, n_post] FP64, final state).  precision 32: the FP32 recursion of
+    the state in the library's order of operations."""
+    R = np.ascontiguousarray(raster, np.uint8)
+    T, n_pre = R.shape
+    ip = np.ascontiguousarray(indptr, np.int32)
+    ix = np.ascontiguousarray(indices, np.int32)
+    d = None if data is None else np.ascontiguousarray(data, np.float32)
+    g = np.empty((T, n_post), np.float64)
+    n_state = n_post if align == ALIGN_POST else n_pre
+    if precision == 64:
+        st = np.zeros(n_state, np.float64) if state is None else np.array(state, np.float64)
+        lib().or_proj_run_f64(ip, ix, _ptr(d), float(w), n_pre, n_post, align, syn, float(decay), float(u), delay, T,
+                              R.reshape(-1), st, g.reshape(-1))
+    else:
+        st = np.zeros(n_state, np.float32) if state is None else np.array(state, np.float32)
+        lib().or_proj_run_f32(ip, ix, _ptr(d), C.c_float(w), n_pre, n_post, align, syn, C.c_float(decay),
+                              C.c_float(u), delay, T, R.reshape(-1), st, g.reshape(-1))
+    return g, st
 
 
 # ---------------------------------------------------------------- SNN

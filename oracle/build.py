@@ -7,7 +7,7 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["oracle.c", "snn.c"]
+SOURCES = ["oracle.c", "snn.c", "proj.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 # the same sources with their OpenMP pragmas honoured: the network loops
 # spread over the host cores (the CPU baseline); results are identical
