@@ -207,9 +207,10 @@ int64_t or_row(uint64_t seed, int32_t K, int32_t n_post, int32_t B, int32_t j, i
  * pseudo-random permutation): target i of row j, i < k, is pi_j(i) with pi_j
  * a permutation of [0, n_post) built by cycle walking (Black and Rogaway,
  * "Ciphers with arbitrary finite domains", CT-RSA 2002) over a four-round
- * balanced Feistel network on [0, 4^h), 4^h >= n_post, whose round function
- * is the 32-bit finalizer of MurmurHash3 (Appleby) applied to the right half
- * xor a round key; the four round keys are the four words of Philox block
+ * alternating Feistel network on [0, 2^b), 2^b the smallest power of two
+ * >= n_post (halves of b - b/2 and b/2 bits), whose round function is the
+ * 32-bit finalizer of MurmurHash3 (Appleby) applied to the other half xor a
+ * round key; the four round keys are the four words of Philox block
  * (j, 0, 0, CONN).  Targets come in index order (not sorted); one post block
  * (B = 0) only.
  */
@@ -271,27 +272,31 @@ static uint32_t fmix32(uint32_t h) {
   return h;
 }
 
-/* Half width h of the Feistel domain: the smallest h >= 1 with 4^h >= n. */
-static uint32_t fd_half_bits(int32_t n) {
-  uint32_t h = 1;
-  while (h < 16 && ((uint64_t)1 << (2 * h)) < (uint64_t)n) ++h;
-  return h;
+/* Bits b of the Feistel domain [0, 2^b): the smallest b >= 2 with 2^b >= n. */
+static uint32_t fd_bits(int32_t n) {
+  uint32_t b = 2;
+  while (b < 31 && ((uint64_t)1 << b) < (uint64_t)n) ++b;
+  return b;
 }
 
-/* pi(i) for the row whose round keys are key[0..3], i < n. */
+/* pi(i) for the row whose round keys are key[0..3], i < n: x in [0, 2^b) is
+ * split into a high part L of b - b/2 bits and a low part R of b/2 bits;
+ * four alternating rounds L ^= F(R ^ key0), R ^= F(L ^ key1), L ^= F(R ^ key2),
+ * R ^= F(L ^ key3), F the finalizer cut to the part's width (each round is
+ * invertible, so the network permutes [0, 2^b)); values >= n are sent through
+ * the network again until they land below n (cycle walking). */
 uint32_t or_fd_target(const uint32_t key[4], int32_t n, uint32_t i) {
-  const uint32_t h = fd_half_bits(n);
-  const uint32_t mask = (1u << h) - 1u;
+  const uint32_t b = fd_bits(n);
+  const uint32_t hr = b / 2, hl = b - hr;
+  const uint32_t ml = (1u << hl) - 1u, mr = (1u << hr) - 1u;
   uint32_t x = i;
   do {
-    uint32_t L = x >> h, R = x & mask;
-    for (int r = 0; r < 4; ++r) {
-      const uint32_t F = fmix32(R ^ key[r]) & mask;
-      const uint32_t nl = R;
-      R = L ^ F;
-      L = nl;
-    }
-    x = (L << h) | R;
+    uint32_t L = x >> hr, R = x & mr;
+    L ^= fmix32(R ^ key[0]) & ml;
+    R ^= fmix32(L ^ key[1]) & mr;
+    L ^= fmix32(R ^ key[2]) & ml;
+    R ^= fmix32(L ^ key[3]) & mr;
+    x = (L << hr) | R;
   } while (x >= (uint32_t)n);
   return x;
 }

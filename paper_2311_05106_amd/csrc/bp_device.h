@@ -84,11 +84,12 @@ __device__ __forceinline__ float u_open1(uint32_t w) { return (float)(w >> 8) * 
 // floor(-ln(U) / -ln(1 - p)), the logarithm by the fixed FP32 operation
 // sequence of ln_f32 so that every device decides the same gaps).
 // 2: exactly `degree` distinct targets per row (one post block): target i is
-// pi_j(i) for a keyed permutation of the columns, a four-round balanced
-// Feistel network over [0, 4^h) whose round function is MurmurHash3's 32-bit
-// finalizer of the right half xor a round key, cycle-walked into
-// [0, n_post) (Black and Rogaway, CT-RSA 2002); the round keys are the four
-// words of Philox block (j, 0, 0, CONN).
+// pi_j(i) for a keyed permutation of the columns: four alternating Feistel
+// rounds over the high b - b/2 and low b/2 bits of [0, 2^b), 2^b the smallest
+// power of two >= n_post, whose round function is MurmurHash3's 32-bit
+// finalizer of the other part xor a round key, cycle-walked into [0, n_post)
+// (Black and Rogaway, CT-RSA 2002); the round keys are the four words of
+// Philox block (j, 0, 0, CONN).
 // ---------------------------------------------------------------------------
 constexpr int kRuleUniform = 0, kRuleGeometric = 1, kRuleFixedDegree = 2;
 
@@ -142,28 +143,27 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
   return h;
 }
 
-// Half width h of the Feistel domain: the smallest h >= 1 with 4^h >= n.
-__device__ __forceinline__ uint32_t fd_half_bits(int32_t n) {
-  const uint32_t bits = n > 1 ? 32u - (uint32_t)__clz(n - 1) : 0u;
-  const uint32_t h = (bits + 1u) >> 1;
-  return h < 1u ? 1u : (h > 16u ? 16u : h);
+// Bits b of the Feistel domain [0, 2^b): the smallest b >= 2 with 2^b >= n.
+__device__ __forceinline__ uint32_t fd_bits(int32_t n) {
+  const uint32_t b = n > 1 ? 32u - (uint32_t)__clz(n - 1) : 0u;
+  return b < 2u ? 2u : b;
 }
 
-// pi(i), i < n, for the round keys `key` and half width h.
-__device__ __forceinline__ uint32_t fd_target(const Words4& key, uint32_t h, int32_t n, uint32_t i) {
-  const uint32_t mask = (1u << h) - 1u;
+// pi(i), i < n, for the round keys `key` on [0, 2^b): a high part of
+// b - b/2 bits and a low part of b/2 bits, four alternating rounds (each
+// xors one part with the finalizer of the other part and a key, cut to the
+// part's width), cycle-walked until the value lands below n.
+__device__ __forceinline__ uint32_t fd_target(const Words4& key, uint32_t b, int32_t n, uint32_t i) {
+  const uint32_t hr = b >> 1, hl = b - hr;
+  const uint32_t ml = (1u << hl) - 1u, mr = (1u << hr) - 1u;
   uint32_t x = i;
   do {
-    uint32_t L = x >> h, R = x & mask;
-    uint32_t F = fmix32(R ^ key.x) & mask;
-    L ^= F;
-    F = fmix32(L ^ key.y) & mask;
-    R ^= F;
-    F = fmix32(R ^ key.z) & mask;
-    L ^= F;
-    F = fmix32(L ^ key.w) & mask;
-    R ^= F;
-    x = (L << h) | R;  // four rounds of (L, R) -> (R, L ^ F(R)), written in place
+    uint32_t L = x >> hr, R = x & mr;
+    L ^= fmix32(R ^ key.x) & ml;
+    R ^= fmix32(L ^ key.y) & mr;
+    L ^= fmix32(R ^ key.z) & ml;
+    R ^= fmix32(L ^ key.w) & mr;
+    x = (L << hr) | R;
   } while (x >= (uint32_t)n);
   return x;
 }
@@ -218,16 +218,48 @@ __device__ __forceinline__ void gen_walk(const ConnGen& g, uint32_t j, uint32_t 
   }
 }
 
+// Rule 0 alone with the parameters passed one by one (the network kernel's
+// lean variant, whose register allocation the general form above disturbs).
+template <class Emit>
+__device__ __forceinline__ void gen_block_uniform(uint64_t seed, uint32_t K, int32_t n_post, int32_t B, uint32_t j,
+                                                  uint32_t b, int64_t lo, int64_t hi, Emit&& emit) {
+  DrawSeq d(seed, kStreamConn, j, b);
+  int64_t start, end, pos;
+  uint32_t i;
+  if (B > 0) {
+    start = (int64_t)b * B;
+    end = start + B;
+    if (end > n_post) end = n_post;
+    const uint32_t ra = below(d(0), K);
+    const uint32_t rb = below(d(1), K + 1u);
+    pos = start + (int64_t)(ra < rb ? ra : rb);
+    i = 2;
+  } else {
+    start = 0;
+    end = n_post;
+    pos = (int64_t)below(d(0), K);
+    i = 1;
+  }
+  if (hi < end) end = hi;
+  uint32_t m = 0;
+  while (pos < end) {
+    if (pos >= lo) emit((int32_t)pos, m);
+    ++m;
+    pos += 1 + (int64_t)below(d(i), K);
+    ++i;
+  }
+}
+
 template <class Emit>
 __device__ __forceinline__ void gen_block(const ConnGen& g, uint32_t j, uint32_t b, int64_t lo, int64_t hi,
                                           Emit&& emit) {
   if (g.rule == kRuleFixedDegree) {
     if (b != 0u) return;
     const Words4 key = fd_keys(g.seed, j);
-    const uint32_t h = fd_half_bits(g.n_post);
+    const uint32_t fb = fd_bits(g.n_post);
     const int32_t k = g.degree < g.n_post ? g.degree : g.n_post;
     for (int32_t i = 0; i < k; ++i) {
-      const int32_t t = (int32_t)fd_target(key, h, g.n_post, (uint32_t)i);
+      const int32_t t = (int32_t)fd_target(key, fb, g.n_post, (uint32_t)i);
       if (t >= lo && t < hi) emit(t, (uint32_t)i);
     }
   } else if (g.rule == kRuleGeometric) {

@@ -41,6 +41,7 @@
 
 #include <mutex>
 #include <new>
+#include <type_traits>
 #include <unordered_set>
 
 #include "bp_device.h"
@@ -366,7 +367,10 @@ __device__ __forceinline__ int gather_and_process(const NetDev& N, int self, int
 // and pushes them to the inbox of the workgroup that owns them; otherwise
 // the spike ids themselves are pushed and every reader regenerates (or
 // streams) the part of each firing row inside its own range.
-template <int CONN, bool PUSH>
+// RULES: nets of any connectivity rule; without it only the paper's uniform
+// gaps are compiled in (the other rules' generators enlarge the kernel and
+// raise its register pressure, so rule-0 launches use the lean variant).
+template <int CONN, bool PUSH, bool RULES>
 __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, int w, uint32_t spin_limit,
                                          NetShared& sh) {
   const int tid = threadIdx.x, wave = tid / kWave;
@@ -418,7 +422,6 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
   const int32_t nbt = b_hi - b_lo + 1;
   const uint64_t seed = N.seed;
   const uint32_t K = (uint32_t)N.K;
-  const ConnGen G{N.seed, (uint32_t)N.K, N.n, N.block, N.rule, N.inv_rate, N.degree};
   unsigned long long ev_local = 0;
 
   // accumulate the targets of the staged firing rows sh.ids[0, nact)
@@ -431,10 +434,12 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
         const uint32_t j = (uint32_t)sh.ids[ai];
         if (j >= (uint32_t)N.n) continue;
         uint32_t* cnt = ((int32_t)j < N.n_exc) ? sh.cE : sh.cI;
-        gen_block(G, j, b, lo, hi, [&](int32_t pos, uint32_t) {
+        auto add = [&](int32_t pos, uint32_t) {
           atomicAdd(&cnt[pos - lo], 1u);
           ++ev_local;
-        });
+        };
+        if constexpr (RULES) gen_block(ConnGen{seed, K, N.n, B, N.rule, N.inv_rate, N.degree}, j, b, lo, hi, add);
+        else gen_block_uniform(seed, K, N.n, B, j, b, lo, hi, add);
       }
     } else {
       int total = 0;
@@ -617,58 +622,107 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
   auto push_generate = [&](int total) {
     const int lane = lane_id();
     if constexpr (CONN == 1) {
-      if (B == 0 && N.rule == kRuleFixedDegree) {
-        // exactly `degree` targets per spike: lane l computes targets
-        // l, l + 64, ... of the row's permutation
-        const uint32_t h = fd_half_bits(N.n);
-        const int32_t k = N.degree < N.n ? N.degree : N.n;
-        for (int si = wave; si < total; si += kNetWaves) {
-          const uint32_t j = (uint32_t)sh.own[si];
-          const uint32_t inh = (int32_t)j >= N.n_exc ? 0x1000u : 0u;
-          const Words4 key = fd_keys(seed, j);
-          for (int32_t i = lane; i < k; i += kWave) emit((int32_t)fd_target(key, h, N.n, (uint32_t)i), inh);
-        }
-      } else if (B == 0) {
-        const uint32_t cap = (uint32_t)N.n;
-        const bool geo = N.rule == kRuleGeometric;
-        const float inv_rate = N.inv_rate;
-        for (int si = wave; si < total; si += kNetWaves) {
-          const uint32_t j = (uint32_t)sh.own[si];
-          const uint32_t inh = (int32_t)j >= N.n_exc ? 0x1000u : 0u;
-          int32_t base = 0;
-          for (uint32_t c = 0;; ++c) {
-            const uint32_t blk = c * kWave + (uint32_t)lane;
-            const Words4 q = philox10(j, 0u, blk, kStreamConn, (uint32_t)seed, (uint32_t)(seed >> 32));
-            // draw 0 is the first position itself (gap - 1), later draws are
-            // gaps (1 + U[0, K), or geometric); a gap beyond n ends the row,
-            // so gaps are clipped to n
-            const uint32_t first = blk == 0u ? 1u : 0u;
-            const uint32_t g0 = min(geo ? geo_gap(q.x, inv_rate) - first : below(q.x, K) + 1u - first, cap);
-            const uint32_t g1 = min(geo ? geo_gap(q.y, inv_rate) : 1u + below(q.y, K), cap);
-            const uint32_t g2 = min(geo ? geo_gap(q.z, inv_rate) : 1u + below(q.z, K), cap);
-            const uint32_t g3 = min(geo ? geo_gap(q.w, inv_rate) : 1u + below(q.w, K), cap);
-            const int s4 = (int)(g0 + g1 + g2 + g3);
-            const int incl = wave_incl_scan(s4);
-            int32_t p = base + incl - s4 + (int32_t)g0;
-            emit(p, inh);
-            p += (int32_t)g1;
-            emit(p, inh);
-            p += (int32_t)g2;
-            emit(p, inh);
-            p += (int32_t)g3;
-            emit(p, inh);
-            base += __builtin_amdgcn_readlane(incl, kWave - 1);
-            if (base >= N.n) break;
+      if constexpr (!RULES) {
+        if (B == 0) {
+          const uint32_t cap = (uint32_t)N.n;
+          for (int si = wave; si < total; si += kNetWaves) {
+            const uint32_t j = (uint32_t)sh.own[si];
+            const uint32_t inh = (int32_t)j >= N.n_exc ? 0x1000u : 0u;
+            int32_t base = 0;
+            for (uint32_t c = 0;; ++c) {
+              const uint32_t blk = c * kWave + (uint32_t)lane;
+              const Words4 q = philox10(j, 0u, blk, kStreamConn, (uint32_t)seed, (uint32_t)(seed >> 32));
+              // draw 0 is the first position itself, later draws are gaps 1 + U[0, K);
+              // a gap beyond n ends the row, so gaps are clipped to n
+              const uint32_t g0 = min(below(q.x, K) + (blk != 0u ? 1u : 0u), cap);
+              const uint32_t g1 = min(1u + below(q.y, K), cap);
+              const uint32_t g2 = min(1u + below(q.z, K), cap);
+              const uint32_t g3 = min(1u + below(q.w, K), cap);
+              const int s4 = (int)(g0 + g1 + g2 + g3);
+              const int incl = wave_incl_scan(s4);
+              int32_t p = base + incl - s4 + (int32_t)g0;
+              emit(p, inh);
+              p += (int32_t)g1;
+              emit(p, inh);
+              p += (int32_t)g2;
+              emit(p, inh);
+              p += (int32_t)g3;
+              emit(p, inh);
+              base += __builtin_amdgcn_readlane(incl, kWave - 1);
+              if (base >= N.n) break;
+            }
+          }
+        } else {
+          const int items = total * N.nb;
+          for (int it = tid; it < items; it += kNetThreads) {
+            const int si = it / N.nb;
+            const uint32_t b = (uint32_t)(it - si * N.nb);
+            const uint32_t j = (uint32_t)sh.own[si];
+            const uint32_t inh = (int32_t)j >= N.n_exc ? 0x1000u : 0u;
+            auto put = [&](int32_t pos, uint32_t) { emit(pos, inh); };
+            gen_block_uniform(seed, K, N.n, B, j, b, 0, N.n, put);
           }
         }
       } else {
-        const int items = total * N.nb;
-        for (int it = tid; it < items; it += kNetThreads) {
-          const int si = it / N.nb;
-          const uint32_t b = (uint32_t)(it - si * N.nb);
-          const uint32_t j = (uint32_t)sh.own[si];
-          const uint32_t inh = (int32_t)j >= N.n_exc ? 0x1000u : 0u;
-          gen_block(G, j, b, 0, N.n, [&](int32_t pos, uint32_t) { emit(pos, inh); });
+        if (B == 0 && N.rule == kRuleFixedDegree) {
+          // exactly `degree` targets per spike: lane l computes targets
+          // l, l + 64, ... of the row's permutation
+          const uint32_t fb = fd_bits(N.n);
+          const int32_t k = N.degree < N.n ? N.degree : N.n;
+          for (int si = wave; si < total; si += kNetWaves) {
+            const uint32_t j = (uint32_t)sh.own[si];
+            const uint32_t inh = (int32_t)j >= N.n_exc ? 0x1000u : 0u;
+            const Words4 key = fd_keys(seed, j);
+            for (int32_t i = lane; i < k; i += kWave) emit((int32_t)fd_target(key, fb, N.n, (uint32_t)i), inh);
+          }
+        } else if (B == 0) {
+          // one wave per spike, gaps uniform or geometric (the law chosen
+          // outside the loop)
+          const uint32_t cap = (uint32_t)N.n;
+          const float inv_rate = N.inv_rate;
+          auto rows = [&](auto geo_tag) {
+            constexpr bool kGeo = decltype(geo_tag)::value;
+            auto gap = [&](uint32_t w) { return kGeo ? geo_gap(w, inv_rate) : 1u + below(w, K); };
+            for (int si = wave; si < total; si += kNetWaves) {
+              const uint32_t j = (uint32_t)sh.own[si];
+              const uint32_t inh = (int32_t)j >= N.n_exc ? 0x1000u : 0u;
+              int32_t base = 0;
+              for (uint32_t c = 0;; ++c) {
+                const uint32_t blk = c * kWave + (uint32_t)lane;
+                const Words4 q = philox10(j, 0u, blk, kStreamConn, (uint32_t)seed, (uint32_t)(seed >> 32));
+                // draw 0 is the first position itself (gap - 1), later draws are
+                // gaps; a gap beyond n ends the row, so gaps are clipped to n
+                const uint32_t g0 = min(gap(q.x) - (blk == 0u ? 1u : 0u), cap);
+                const uint32_t g1 = min(gap(q.y), cap);
+                const uint32_t g2 = min(gap(q.z), cap);
+                const uint32_t g3 = min(gap(q.w), cap);
+                const int s4 = (int)(g0 + g1 + g2 + g3);
+                const int incl = wave_incl_scan(s4);
+                int32_t p = base + incl - s4 + (int32_t)g0;
+                emit(p, inh);
+                p += (int32_t)g1;
+                emit(p, inh);
+                p += (int32_t)g2;
+                emit(p, inh);
+                p += (int32_t)g3;
+                emit(p, inh);
+                base += __builtin_amdgcn_readlane(incl, kWave - 1);
+                if (base >= N.n) break;
+              }
+            }
+          };
+          if (N.rule == kRuleGeometric) rows(std::true_type{});
+          else rows(std::false_type{});
+        } else {
+          const int items = total * N.nb;
+          for (int it = tid; it < items; it += kNetThreads) {
+            const int si = it / N.nb;
+            const uint32_t b = (uint32_t)(it - si * N.nb);
+            const uint32_t j = (uint32_t)sh.own[si];
+            const uint32_t inh = (int32_t)j >= N.n_exc ? 0x1000u : 0u;
+            auto put = [&](int32_t pos, uint32_t) { emit(pos, inh); };
+            gen_block(ConnGen{seed, K, N.n, B, N.rule, N.inv_rate, N.degree}, j, b, 0, N.n, put);
+          }
         }
       }
     } else {
@@ -877,6 +931,7 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
   }
 }
 
+template <bool RULES>
 __global__ void __launch_bounds__(kNetThreads) net_run_k(BatchArgs args) {
   __shared__ NetShared sh;
   int e = 0;
@@ -886,12 +941,24 @@ __global__ void __launch_bounds__(kNetThreads) net_run_k(BatchArgs args) {
   const NetDev N = *L.net;
   const int w = (int)blockIdx.x - L.wg_begin;
   if (N.conn == 1) {
-    if (N.push) net_body<1, true>(L, N, w, args.spin_limit, sh);
-    else net_body<1, false>(L, N, w, args.spin_limit, sh);
+    if (N.push) net_body<1, true, RULES>(L, N, w, args.spin_limit, sh);
+    else net_body<1, false, RULES>(L, N, w, args.spin_limit, sh);
   } else {
-    net_body<0, false>(L, N, w, args.spin_limit, sh);
+    // stored rows: the rule only decided how they were built
+    net_body<0, false, false>(L, N, w, args.spin_limit, sh);
   }
 }
+
+// Launch of the kernel variant for nets of every connectivity rule.  It is
+// instantiated in a translation unit of its own (net_rules.hip includes this
+// file with BP_NET_RULES_TU defined): compiled beside the lean variant, the
+// shared code was outlined differently and the lean kernel lost 2.5 % per
+// step.
+bp_status launch_net_rules(BatchArgs& args, int32_t wg, bool coop, hipStream_t st);
+
+#ifdef BP_NET_RULES_TU
+}  // namespace bp
+#else
 
 // Initial state: V0 from the hash (FP64 arithmetic, one rounding), zero
 // conductances and counters; every record slot invalid, except the headers of
@@ -1137,10 +1204,11 @@ static bp_status launch_batch(const bp_net* nets, int32_t n_nets, const int64_t*
   BatchArgs args{};
   args.spin_limit = kSpinLimit;
   int32_t wg = 0;
-  bool coop = false;
+  bool coop = false, rules = false;  // rules: some regenerated net draws by another rule than rule 0
   for (int32_t i = 0; i < n_nets; ++i) {
     bp_status s = check_net(nets[i]);
     if (s) return s;
+    if (nets[i]->desc.conn == BP_CONN_JIT && nets[i]->desc.rule != kRuleUniform) rules = true;
     BP_REQUIRE(n_steps[i] >= 0 && n_steps[i] <= INT32_MAX, "n_steps out of range");
     for (int32_t q = 0; q < i; ++q) BP_REQUIRE(nets[q] != nets[i], "a net appears twice in one batch");
     if (n_steps[i] == 0) continue;
@@ -1157,13 +1225,17 @@ static bp_status launch_batch(const bp_net* nets, int32_t n_nets, const int64_t*
     if (L.n_wg > 1) coop = true;
   }
   if (args.n_nets == 0) return BP_OK;
-  if (coop) {
+  if (rules) {
+    bp_status s = launch_net_rules(args, wg, coop, st);
+    if (s) return s;
+  } else if (coop) {
     void* kargs[] = {&args};
-    hipError_t e = hipLaunchCooperativeKernel((const void*)net_run_k, dim3(wg), dim3(kNetThreads), kargs, 0, st);
+    hipError_t e = hipLaunchCooperativeKernel((const void*)net_run_k<false>, dim3(wg), dim3(kNetThreads), kargs, 0,
+                                              st);
     if (e != hipSuccess)
       return set_error(BP_EDEVICE, "cooperative launch of %d workgroups failed: %s", wg, hipGetErrorString(e));
   } else {
-    net_run_k<<<wg, kNetThreads, 0, st>>>(args);
+    net_run_k<false><<<wg, kNetThreads, 0, st>>>(args);
     BP_LAUNCHED("net_run_k");
   }
   for (int32_t i = 0; i < n_nets; ++i) nets[i]->step += n_steps[i];
@@ -1385,3 +1457,5 @@ bp_status bp_destroy_net(bp_net net) {
 }
 
 }  // extern "C"
+
+#endif  // BP_NET_RULES_TU
