@@ -109,9 +109,11 @@ typedef struct {
  *     the law), every later draw is one more gap.  Gaps are capped at 2^30.
  *   BP_RULE_FIXED_DEGREE: every row has exactly min(degree, n_post) distinct
  *     targets: target i is pi_j(i), pi_j a keyed permutation of [0, n_post)
- *     (four-round Feistel network over [0, 4^h) with MurmurHash3's 32-bit
- *     finalizer as round function, cycle-walked into [0, n_post); round keys
- *     the four words of Philox block (j, 0, 0, BP_STREAM_CONN)).  Targets are
+ *     (four alternating Feistel rounds over the high b - b/2 and low b/2
+ *     bits of [0, 2^b), 2^b the smallest power of two >= n_post (b >= 2),
+ *     with MurmurHash3's 32-bit finalizer as round function, cycle-walked
+ *     into [0, n_post); round keys the four words of Philox block
+ *     (j, 0, 0, BP_STREAM_CONN)).  Targets are
  *     generated in index order; connection i of the JIT weight streams is
  *     target i.  One post block only (block == 0). */
 #define BP_RULE_UNIFORM 0
@@ -290,6 +292,17 @@ size_t bp_jit_matmat_ws_bytes(const bp_jit_conn* c, int32_t m);
 bp_status bp_jit_conn_matmat_dense(const bp_jit_conn* c, const float* X, int32_t m, float* Y, void* ws,
                                    size_t ws_bytes, bp_stream stream);
 
+/* Stored CSR on a dense float vector: y (device float[n_post], overwritten)
+ * = M^T v, y[k] = sum over rows j with v[j] != 0 of M[j, k] v[j] (M[j, k] =
+ * data or w), each term rounded to FP32 and summed in an unspecified order
+ * (the float-vector counterpart of bp_event_csr_matvec: the AlignPre
+ * projection's product of its presynaptic traces, Appendix D).  Unsorted rows
+ * need n_post <= 16384 (BP_EUNSUPPORTED otherwise).  ws:
+ * bp_csr_matvec_dense_ws_bytes(m) bytes. */
+size_t bp_csr_matvec_dense_ws_bytes(const bp_csr* m);
+bp_status bp_csr_matvec_dense(const bp_csr* m, const float* v, float* y, void* ws, size_t ws_bytes,
+                              bp_stream stream);
+
 /* Reverse mode: d_events[j] = sum over row j of w_jk dy[k] (every row);
  * d_w (device float[2], nullable) = derivatives with respect to (w0, w1)
  * summed over firing rows: homogeneous (sum dy, 0); normal (sum dy, sum z dy);
@@ -301,6 +314,65 @@ bp_status bp_jit_conn_backward(const bp_jit_conn* c, const uint8_t* events, cons
  * (args: const bp_jit_conn*; d_data unused). */
 bp_status bp_backward(int32_t op, const void* args, const uint8_t* events, const float* dy, float* d_events,
                       float* d_data, float* d_w, bp_stream stream);
+
+/* ------------------------------------------------------------------------ */
+/* Projections with multi-step delays (Section 4.3; Appendices D, E, F)      */
+/* ------------------------------------------------------------------------ */
+
+/* A spike delay line: device uint8 [depth][n], slot t mod depth holds the
+ * spikes of step t; the caller zeroes it before step 0 (steps before 0 then
+ * read as silent).  bp_delay_push copies step t's spikes (device uint8[n])
+ * into its slot (an asynchronous device copy). */
+bp_status bp_delay_push(uint8_t* ring, int32_t depth, int32_t n, int64_t t, const uint8_t* spikes,
+                        bp_stream stream);
+
+#define BP_ALIGN_POST 0 /* synaptic variable per postsynaptic neuron: g <- g d + M^T s */
+#define BP_ALIGN_PRE 1  /* trace per presynaptic neuron x, g = M^T x */
+#define BP_SYN_EXP 0    /* x <- x d + s */
+#define BP_SYN_SAT 1    /* x <- x d, then x <- x + u (1 - x) on a spike (AlignPre only) */
+
+/* A projection from a presynaptic group (n_pre neurons, the rows of the
+ * connectivity) to a postsynaptic group (n_post), reading the presynaptic
+ * spikes `delay` steps late from a delay line.  AlignPost keeps n_post
+ * synaptic variables (exact for the exponential synapse: every arriving
+ * spike adds its weight, whichever neuron sent it, Appendix E); AlignPre
+ * keeps one trace per presynaptic neuron, shared by all its synapses and by
+ * every projection that reads it with the same delay and dynamics (Appendix
+ * D), and is exact for any per-synapse dynamics.  For the exponential synapse
+ * both give the same g. */
+typedef struct {
+  int32_t align;            /* BP_ALIGN_POST or BP_ALIGN_PRE */
+  int32_t syn;              /* BP_SYN_EXP or BP_SYN_SAT */
+  int32_t conn;             /* BP_CONN_CSR (csr) or BP_CONN_JIT (jit) */
+  const bp_csr* csr;        /* stored connectivity: weight w or data */
+  const bp_jit_conn* jit;   /* regenerated connectivity and weights */
+  int32_t delay;            /* steps, 0 <= delay < depth of the delay line */
+  float decay;              /* exp(-dt / tau), computed in FP64 and rounded once */
+  float u;                  /* BP_SYN_SAT increment */
+} bp_proj;
+
+/* Device scratch of one step: n_post floats (AlignPost) plus the product's. */
+size_t bp_proj_ws_bytes(const bp_proj* p);
+
+/* Step t (>= 0) of the projection, reading ring slot (t - delay) mod depth
+ * (nothing before step 0):
+ *   AlignPost: state = g (device float[n_post]), g <- g d + M^T s, in FP32
+ *     as fl(fl(g d) + y) with y the event product (homogeneous: (float)count
+ *     * w, so g is bit-reproducible); `g` (nullable) receives a copy.
+ *   AlignPre: state = x (device float[n_pre]), x <- fl(x d) (+ 1, or
+ *     + fl(u fl(1 - fl(x d))) saturating) where the delayed spike is set; then
+ *     g (device float[n_post], overwritten) = M^T x by the float-vector
+ *     product (FP32 terms, unspecified order).
+ * Errors: BP_EINVAL for a bad descriptor, a delay >= depth, null buffers or
+ * a short workspace, before any launch. */
+bp_status bp_proj_step(const bp_proj* p, const uint8_t* ring, int32_t depth, int64_t t, float* state, float* g,
+                       void* ws, size_t ws_bytes, bp_stream stream);
+
+/* T steps from step t0 driven by a presynaptic raster (device uint8
+ * [T][n_pre]): for each step, bp_delay_push of its raster row, then
+ * bp_proj_step writing g_out[i] (device float [T][n_post]). */
+bp_status bp_proj_run(const bp_proj* p, const uint8_t* raster, int32_t T, uint8_t* ring, int32_t depth, int64_t t0,
+                      float* state, float* g_out, void* ws, size_t ws_bytes, bp_stream stream);
 
 /* ------------------------------------------------------------------------ */
 /* E/I LIF network (Appendices E, F, N)                                       */

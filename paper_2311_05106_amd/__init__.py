@@ -11,15 +11,17 @@ import math
 import torch
 
 from . import _abi
-from ._abi import (COBA, CONN_CSR, CONN_JIT, CUBA, RULE_FIXED_DEGREE, RULE_GEOMETRIC, RULE_UNIFORM, STREAM_CONN,
-                   STREAM_V0, STREAM_W, W_HOMO, W_NORMAL, W_UNIFORM, BpError, check, lib)
+from ._abi import (ALIGN_POST, ALIGN_PRE, COBA, CONN_CSR, CONN_JIT, CUBA, RULE_FIXED_DEGREE, RULE_GEOMETRIC,
+                   RULE_UNIFORM, STREAM_CONN, STREAM_V0, STREAM_W, SYN_EXP, SYN_SAT, W_HOMO, W_NORMAL, W_UNIFORM,
+                   BpError, check, lib)
 
 __all__ = [
     "lib", "BpError", "max_gap", "hash_words", "csr_build", "csr_tile_index", "compact", "event_csr_matvec",
     "event_csr_matvec_noalloc", "event_csr_matmat", "jit_conn_matmat",
     "jit_conn_matvec", "jit_conn_matvec_dense", "jit_conn_matmat_dense", "event_csr_backward", "jit_conn_backward", "Net", "run_batch", "JitConn",
     "COBA", "CUBA", "CONN_CSR", "CONN_JIT", "W_HOMO", "W_NORMAL", "W_UNIFORM", "RULE_UNIFORM", "RULE_GEOMETRIC",
-    "RULE_FIXED_DEGREE", "geo_inv_rate",
+    "RULE_FIXED_DEGREE", "geo_inv_rate", "csr_matvec_dense", "Projection", "ALIGN_POST", "ALIGN_PRE", "SYN_EXP",
+    "SYN_SAT",
 ]
 
 
@@ -197,6 +199,68 @@ def event_csr_matvec_noalloc(indptr, indices, data, w, n_post, events, out, tile
     y = _out(out, n_post, torch.float32, events.device)
     check(lib().bp_event_csr_matvec_noalloc(C.byref(m), _p(events), _p(y), _stream()))
     return y
+
+
+def csr_matvec_dense(indptr, indices, data, w, n_post, v, tile_ptr=None, tile_width=0, sorted_rows=True, out=None,
+                     ws=None):
+    """y = M^T v for a dense FP32 vector v and a stored CSR (rows with
+    v[j] == 0 skipped)."""
+    indptr, indices, data = _csr_args(indptr, indices, data, n_post)
+    v = _vec(v, indptr.numel() - 1, torch.float32, "v")
+    if tile_ptr is not None:
+        tile_ptr = _dev(tile_ptr, torch.int32, "tile_ptr")
+    m = _csr_struct(indptr, indices, data, w, n_post, tile_ptr, tile_width, sorted_rows)
+    y = _out(out, n_post, torch.float32, v.device)
+    wsb = int(lib().bp_csr_matvec_dense_ws_bytes(C.byref(m)))
+    if ws is None or ws.numel() < wsb:
+        ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=v.device)
+    check(lib().bp_csr_matvec_dense(C.byref(m), _p(v), _p(y), _p(ws), wsb, _stream()))
+    return y
+
+
+class Projection:
+    """A synaptic projection with a `delay`-step spike delay (Section 4.3,
+    Appendix D): align ALIGN_POST (state g per postsynaptic neuron) or
+    ALIGN_PRE (one trace per presynaptic neuron, g = M^T x); syn SYN_EXP or
+    SYN_SAT (AlignPre only).  Connectivity: a stored CSR (indptr, indices,
+    data or w) or a JitConn.  Holds the delay line, the state and the
+    scratch in device memory."""
+
+    def __init__(self, align, decay, delay=0, depth=None, syn=SYN_EXP, u=0.0, csr=None, jit=None, device="cuda"):
+        self._keep = []
+        if csr is not None:
+            indptr, indices, data, w, n_post = csr
+            indptr, indices, data = _csr_args(indptr, indices, data, n_post)
+            self._keep += [indptr, indices, data]
+            self._csr = _csr_struct(indptr, indices, data, w, n_post)
+            self.n_pre, self.n_post, conn = indptr.numel() - 1, n_post, CONN_CSR
+            cp, jp = C.pointer(self._csr), None
+        else:
+            self._jit = jit.c
+            self.n_pre, self.n_post, conn = jit.n_pre, jit.n_post, CONN_JIT
+            cp, jp = None, C.pointer(self._jit)
+        self.depth = int(depth if depth is not None else delay + 1)
+        self.p = _abi.Proj(align, syn, conn, cp, jp, int(delay), float(decay), float(u))
+        self.ring = torch.zeros(max(self.depth * self.n_pre, 1), dtype=torch.uint8, device=device)
+        self.state = torch.zeros(max(self.n_post if align == ALIGN_POST else self.n_pre, 1), dtype=torch.float32,
+                                 device=device)
+        wsb = int(lib().bp_proj_ws_bytes(C.byref(self.p)))
+        self.ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=device)
+        self.wsb = wsb
+        self.t = 0
+
+    def run(self, raster, g_out=None):
+        """Steps driven by a presynaptic raster [T, n_pre] (CUDA uint8);
+        returns g [T, n_post]."""
+        raster = _dev(raster, torch.uint8, "raster")
+        if raster.dim() != 2 or raster.shape[1] != self.n_pre:
+            raise ValueError(f"raster must be [T, {self.n_pre}]")
+        T = int(raster.shape[0])
+        g = g_out if g_out is not None else torch.empty((T, self.n_post), dtype=torch.float32, device=raster.device)
+        check(lib().bp_proj_run(C.byref(self.p), _p(raster), T, _p(self.ring), self.depth, self.t, _p(self.state),
+                                _p(g), _p(self.ws), self.wsb, _stream()))
+        self.t += T
+        return g
 
 
 def event_csr_ws(indptr, indices, data, w, n_post, tile_ptr=None, tile_width=0, sorted_rows=True):

@@ -12,6 +12,8 @@ STREAM_CONN, STREAM_W, STREAM_V0 = 1, 2, 3
 COBA, CUBA = 0, 1
 CONN_CSR, CONN_JIT = 0, 1
 RULE_UNIFORM, RULE_GEOMETRIC, RULE_FIXED_DEGREE = 0, 1, 2
+ALIGN_POST, ALIGN_PRE = 0, 1
+SYN_EXP, SYN_SAT = 0, 1
 
 
 class JitConn(C.Structure):
@@ -24,6 +26,11 @@ class Csr(C.Structure):
     _fields_ = [("indptr", C.c_void_p), ("indices", C.c_void_p), ("data", C.c_void_p), ("w", C.c_float),
                 ("n_pre", C.c_int32), ("n_post", C.c_int32), ("sorted", C.c_int32), ("tile_ptr", C.c_void_p),
                 ("tile_width", C.c_int32)]
+
+
+class Proj(C.Structure):
+    _fields_ = [("align", C.c_int32), ("syn", C.c_int32), ("conn", C.c_int32), ("csr", C.POINTER(Csr)),
+                ("jit", C.POINTER(JitConn)), ("delay", C.c_int32), ("decay", C.c_float), ("u", C.c_float)]
 
 
 class NetDesc(C.Structure):
@@ -73,6 +80,12 @@ SIGNATURES = {
     "bp_event_csr_matmat": (_i32, [C.POINTER(Csr), _vp, _i32, _i64, _vp, _i64, _vp, _sz, _vp]),
     "bp_jit_conn_matmat_ws_bytes": (_sz, [C.POINTER(JitConn), _i32]),
     "bp_jit_conn_matmat": (_i32, [C.POINTER(JitConn), _vp, _i32, _i64, _vp, _i64, _vp, _sz, _vp]),
+    "bp_csr_matvec_dense_ws_bytes": (_sz, [C.POINTER(Csr)]),
+    "bp_csr_matvec_dense": (_i32, [C.POINTER(Csr), _vp, _vp, _vp, _sz, _vp]),
+    "bp_delay_push": (_i32, [_vp, _i32, _i32, _i64, _vp, _vp]),
+    "bp_proj_ws_bytes": (_sz, [C.POINTER(Proj)]),
+    "bp_proj_step": (_i32, [C.POINTER(Proj), _vp, _i32, _i64, _vp, _vp, _vp, _sz, _vp]),
+    "bp_proj_run": (_i32, [C.POINTER(Proj), _vp, _i32, _vp, _i32, _i64, _vp, _vp, _vp, _sz, _vp]),
     "bp_jit_ws_bytes": (_sz, [C.POINTER(JitConn)]),
     "bp_jit_conn_matvec": (_i32, [C.POINTER(JitConn), _vp, _vp, _vp, _sz, _vp]),
     "bp_jit_dense_ws_bytes": (_sz, [C.POINTER(JitConn)]),

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbpmi.so")
-SOURCES = ["hash_csr.hip", "compact.hip", "matvec.hip", "net.hip", "snn.hip"]
+SOURCES = ["hash_csr.hip", "compact.hip", "matvec.hip", "net.hip", "snn.hip", "proj.hip", "net_rules.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

@@ -44,11 +44,13 @@ enum MvMode {
   kCsrHomo = 0, kCsrData = 1, kJitHomo = 2, kJitWeighted = 3, kJitVec = 4, kJitMat = 5,
   // batched spike products: the same four operators on `batch` spike
   // vectors at once, up to kMatCols per workgroup (blockIdx.y = group)
-  kCsrHomoB = 6, kCsrDataB = 7, kJitHomoB = 8, kJitWeightedB = 9
+  kCsrHomoB = 6, kCsrDataB = 7, kJitHomoB = 8, kJitWeightedB = 9,
+  // stored CSR on a dense float vector: y = M^T v over the rows with v[j] != 0
+  kCsrVec = 16
 };
 constexpr int kMatCols = 8;  // kJitMat / batched: columns per workgroup
-constexpr bool is_batch(int m) { return m >= kCsrHomoB; }
-constexpr int base_mode(int m) { return m >= kCsrHomoB ? m - kCsrHomoB : m; }
+constexpr bool is_batch(int m) { return m >= kCsrHomoB && m <= kJitWeightedB; }
+constexpr int base_mode(int m) { return is_batch(m) ? m - kCsrHomoB : m; }
 constexpr bool counts_mode(int m) { return base_mode(m) == kCsrHomo || base_mode(m) == kJitHomo; }
 
 struct MvArgs {
@@ -261,7 +263,8 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
     reinterpret_cast<uint4*>(acc)[i] = make_uint4(0u, 0u, 0u, 0u);
   if (threadIdx.x < 3) sh.cnt[threadIdx.x] = 0;
   __syncthreads();
-  const uintptr_t src = MODE == kJitVec ? reinterpret_cast<uintptr_t>(a.vec) : reinterpret_cast<uintptr_t>(a.events);
+  constexpr bool kFV = MODE == kJitVec || MODE == kCsrVec;  // rows listed where v[j] != 0
+  const uintptr_t src = kFV ? reinterpret_cast<uintptr_t>(a.vec) : reinterpret_cast<uintptr_t>(a.events);
   const bool vec = ((src | (uintptr_t)r_begin | (kB ? (uintptr_t)a.ev_stride : 0)) & 15) == 0;
   const uint8_t* evg = kB ? a.events + (size_t)c0 * a.ev_stride : a.events;  // the group's first vector
 
@@ -274,7 +277,7 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
     if (r < r_end) {
       if constexpr (MODE == kJitMat) {
         bits = r + kRowsPerLane <= r_end ? 0xFFFFu : (1u << (r_end - r)) - 1u;
-      } else if constexpr (MODE == kJitVec) {
+      } else if constexpr (kFV) {
         bits = nonzero_floats16(a.vec, r, r_end, vec);
       } else if constexpr (kB) {
 #pragma unroll
@@ -303,13 +306,14 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
     if (total <= kIdCap - kSweep && r0 + kSweep < r_end) continue;
     if (total > kIdCap) total = kIdCap;  // unreachable: a sweep adds at most kSweep rows
 
-    if constexpr (BM == kCsrHomo || BM == kCsrData) {
+    if constexpr (BM == kCsrHomo || BM == kCsrData || BM == kCsrVec) {
       // quarter-wave g streams the segments of rows g, g + G, ...; lane l
       // reads entries l, l + 16, ... of a segment.  Rows go in batches of R
       // per group: the loads of all R segments (kSegLoads per lane, 160
       // entries each) are issued together, then the bounds of the next batch,
       // then the LDS adds; the rare entries beyond 160 follow row by row.
       constexpr int R = BM == kCsrHomo ? 4 : 2;
+      constexpr bool kLoadVal = BM == kCsrData || BM == kCsrVec;  // per-entry values (kCsrVec: data or w)
       constexpr int U = kSegLoads;
       constexpr int kPass = kGroup * U;
       const int G = kMvThreads / kGroup;
@@ -322,6 +326,7 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
         const int32_t id = sh.ids[i];
         const int32_t j = kB ? (int32_t)((uint32_t)id >> 8) : id;
         if constexpr (kB) mk = (uint32_t)id & 0xFFu;
+        if constexpr (MODE == kCsrVec) mk = __float_as_uint(a.vec[j]);  // the row's factor v[j]
         if (a.tile_ptr) {
           const int32_t* tp = a.tile_ptr + (size_t)j * (a.n_tiles + 1) + t;
           st = tp[0];
@@ -338,6 +343,7 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
       auto add = [&](int c, float v, uint32_t mk) {
         if constexpr (MODE == kCsrHomo) atomicAdd(&acc[c - lo], 1u);
         else if constexpr (MODE == kCsrData) lds_add_f32(&acc[c - lo], v);
+        else if constexpr (MODE == kCsrVec) lds_add_f32(&acc[c - lo], v * __uint_as_float(mk));
         else if constexpr (MODE == kCsrHomoB) batch_count(reinterpret_cast<uint32_t*>(acc), c - lo, width, mk);
         else batch_sum(reinterpret_cast<float*>(acc), c - lo, width, mk, v);
       };
@@ -355,6 +361,7 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
             const int e = l + kGroup * u;
             col[r][u] = e < ln[r] ? a.indices[st[r] + e] : -1;
             if constexpr (BM == kCsrData) val[r][u] = e < ln[r] ? a.data[st[r] + e] : 0.f;
+            if constexpr (BM == kCsrVec) val[r][u] = a.data ? (e < ln[r] ? a.data[st[r] + e] : 0.f) : a.w;
           }
         }
         int nst[R], nln[R];
@@ -365,7 +372,7 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
         for (int r = 0; r < R; ++r) {
 #pragma unroll
           for (int u = 0; u < U; ++u)
-            if (col[r][u] >= 0) add(col[r][u], BM == kCsrData ? val[r][u] : 0.f, mk[r]);
+            if (col[r][u] >= 0) add(col[r][u], kLoadVal ? val[r][u] : 0.f, mk[r]);
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -377,10 +384,11 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
               const int e = base + l + kGroup * u;
               c2[u] = e < ln[r] ? a.indices[st[r] + e] : -1;
               if constexpr (BM == kCsrData) v2[u] = e < ln[r] ? a.data[st[r] + e] : 0.f;
+              if constexpr (BM == kCsrVec) v2[u] = a.data ? (e < ln[r] ? a.data[st[r] + e] : 0.f) : a.w;
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
-              if (c2[u] >= 0) add(c2[u], BM == kCsrData ? v2[u] : 0.f, mk[r]);
+              if (c2[u] >= 0) add(c2[u], kLoadVal ? v2[u] : 0.f, mk[r]);
           }
         }
 #pragma unroll
@@ -406,7 +414,29 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
       // needs the tile to begin there (a block wider than the LDS tile is cut
       // into several tiles, the later ones starting inside the block)
       // (uniform gaps only: it reads the gap law off the draws directly)
-      if (a.jit.rule == kRuleUniform && B > 0 && nbt == 1 && lo == (int64_t)b_lo * B && items * 4 <= kMvThreads) {
+      if (a.jit.rule == kRuleFixedDegree) {
+        // exactly k targets per row, each computed on its own from the row's
+        // permutation: one wave per listed row, lane l takes targets l,
+        // l + 64, ... (every tile evaluates all k and keeps its own)
+        const int32_t k = a.jit.degree < n_post ? a.jit.degree : n_post;
+        const uint32_t fb = fd_bits(n_post);
+        const int wv = (int)threadIdx.x / kWave, ln = lane_id();
+        for (int ai = wv; ai < total; ai += kMvThreads / kWave) {
+          const uint32_t id = (uint32_t)sh.ids[ai];
+          const uint32_t j = kB ? id >> 8 : id, mk = kB ? id & 0xFFu : 0u;
+          RowScale<MODE> sc;
+          sc.load(a, j, c0, mg);
+          const Words4 key = fd_keys(seed, j);
+          for (int32_t i = ln; i < k; i += kWave) {
+            const int32_t t = (int32_t)fd_target(key, fb, n_post, (uint32_t)i);
+            if (t >= lo && t < hi) {
+              DrawSeq wd(seed, kStreamW, j, 0u);
+              jit_put<MODE>(acc, t - lo, width, mk, sc, wd, wkind, w0, w1, (uint32_t)i, mg);
+            }
+          }
+        }
+      } else if (a.jit.rule == kRuleUniform && B > 0 && nbt == 1 && lo == (int64_t)b_lo * B &&
+                 items * 4 <= kMvThreads) {
         // Few rows in the pass: four lanes per row.  In pass P lane q draws
         // generator block 4P + q (draws 16P + 4q .. 16P + 4q + 3); a prefix
         // of the lanes' gap sums over the quad places the targets, so a row
@@ -721,6 +751,7 @@ __global__ void jit_backward_k(bp_jit_conn c, const uint8_t* __restrict__ ev, co
 struct MvPlan {
   int32_t tile, n_tiles, chunks, chunk_rows;
   bool atomic_path;
+  bool unsupported;
   size_t ws;
 };
 
@@ -743,7 +774,7 @@ static void set_chunks(MvPlan& p, int32_t n_pre, bool homo, int32_t n_post, bool
   p.ws = p.chunks > 1 ? (size_t)p.chunks * n_post * (homo ? 2 : 4) : 0;
 }
 
-static MvPlan plan_csr(const bp_csr* m) {
+static MvPlan plan_csr(const bp_csr* m, bool vec_input = false) {
   MvPlan p{};
   if (m->n_post <= kTileMax) {
     p.tile = m->n_post > 0 ? m->n_post : 1;
@@ -758,13 +789,17 @@ static MvPlan plan_csr(const bp_csr* m) {
     p.tile = (int32_t)(((int64_t)m->n_post + nt - 1) / nt);
     p.n_tiles = (int32_t)(((int64_t)m->n_post + p.tile - 1) / p.tile);
   } else {
+    if (vec_input) {  // float-vector products of unsorted rows: one tile only
+      p.unsupported = true;
+      return p;
+    }
     p.atomic_path = true;
     p.ws = (size_t)(m->n_post > 0 ? m->n_post : 1) * sizeof(uint32_t);
     return p;
   }
-  set_chunks(p, m->n_pre, m->data == nullptr, m->n_post);
+  set_chunks(p, m->n_pre, !vec_input && m->data == nullptr, m->n_post);
   // 16-bit partial counts need at most one entry per row and column
-  if (!m->data && !m->sorted && p.chunks > 1) {
+  if (!vec_input && !m->data && !m->sorted && p.chunks > 1) {
     p.atomic_path = true;
     p.ws = (size_t)(m->n_post > 0 ? m->n_post : 1) * sizeof(uint32_t);
   }
@@ -1037,6 +1072,35 @@ static bp_status event_csr_run(const bp_csr* m, const MvPlan& p, const uint8_t* 
 }  // namespace bp
 
 extern "C" {
+
+size_t bp_csr_matvec_dense_ws_bytes(const bp_csr* m) {
+  if (!m) return 0;
+  return plan_csr(m, true).ws;
+}
+
+bp_status bp_csr_matvec_dense(const bp_csr* m, const float* v, float* y, void* ws, size_t ws_bytes,
+                              bp_stream stream) {
+  bp_status s = check_csr(m);
+  if (s) return s;
+  if (m->n_post == 0) return BP_OK;
+  BP_REQUIRE(y != nullptr, "null y");
+  BP_REQUIRE(m->n_pre == 0 || v != nullptr, "null v");
+  const MvPlan p = plan_csr(m, true);
+  if (p.unsupported)
+    return set_error(BP_EUNSUPPORTED, "float-vector products of unsorted rows need n_post <= %d", kTileMax);
+  BP_REQUIRE(ws_bytes >= p.ws && (p.ws == 0 || ws != nullptr), "workspace too small (%zu < %zu)", ws_bytes, p.ws);
+  hipStream_t st = as_stream(stream);
+  MvArgs a{};
+  a.indptr = m->indptr; a.indices = m->indices; a.data = m->data; a.vec = v;
+  a.tile_ptr = p.n_tiles > 1 && m->tile_ptr && p.tile == m->tile_width ? m->tile_ptr : nullptr;
+  a.search = p.n_tiles > 1 && a.tile_ptr == nullptr;
+  a.out = p.chunks > 1 ? ws : (void*)y; a.w = m->w;
+  a.n_pre = m->n_pre; a.n_post = m->n_post; a.tile = p.tile; a.n_tiles = p.n_tiles;
+  a.chunks = p.chunks; a.chunk_rows = p.chunk_rows;
+  s = launch_scatter<kCsrVec>(a, p, st);
+  if (s) return s;
+  return finish_partials(p, false, ws, m->n_post, m->w, y, st);
+}
 
 size_t bp_event_csr_matmat_ws_bytes(const bp_csr* m, int32_t batch) {
   if (!m || batch <= 0) return 0;

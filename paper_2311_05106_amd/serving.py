@@ -178,9 +178,17 @@ def serve_plain(requests, max_wgs=0, block=1024, torch=None):
     return dict(records=done, rejected=[], launches=len(done), wall=clock.now())
 
 
-def summarize(result):
-    lat = sorted(r["latency"] for r in result["records"])
-    ev = sum(r["events"] for r in result["records"])
+def summarize(result, skip=0):
+    """p50/p99 latency and throughput of the requests with id >= skip (the
+    first `skip` of the stream warm the server up); throughput is their
+    synaptic events over the time from the first one's arrival to the last
+    one's completion."""
+    recs = [r for r in result["records"] if r["id"] >= skip]
+    lat = sorted(r["latency"] for r in recs)
+    ev = sum(r["events"] for r in recs)
+    if skip and recs:
+        wall = max(r["finished"] for r in recs) - min(r["arrival"] for r in recs)
+        result = dict(result, wall=wall)
 
     def pct(q):
         if not lat:
