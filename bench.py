@@ -78,13 +78,13 @@ def counters_traffic(kernel_file, key, per_launch_units, block=None):
 LAUNCH_STEPS = 1000  # simulation steps per bench step: one persistent-kernel launch (0.1 s simulated)
 
 
-def bench_network(bp, torch, steps, warmup, block=None):
+def bench_network(bp, torch, steps, warmup, block=None, desc=None):
     """max(W, 1) warm-up launches of LAUNCH_STEPS steps (the initial transient
     is over after the first), then K timed launches of the same net, one per
     bench step; the state stays on the device throughout.  Every buffer is
     allocated before the first event; each launch is bracketed by HIP events
     on the stream it runs on."""
-    d = c2_desc(bp, block=block)
+    d = desc if desc is not None else c2_desc(bp, block=block)
     net = bp.Net(d)
     warm = max(warmup, 1)
     for _ in range(warm):
@@ -280,6 +280,137 @@ def bench_ops(bp, torch, calls=10000, fracs=(0.001, 0.01, 0.1)):
     return out
 
 
+def _graph_time_us(torch, fn, items, calls):
+    """Mean us per call of fn over `items`, replayed from a HIP graph of one
+    pass over the items (eager warm-up first)."""
+    for it in items:
+        fn(it)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            for it in items:
+                fn(it)
+    torch.cuda.synchronize()
+    reps = max(1, calls // len(items))
+    g.replay()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        g.replay()
+    b.record()
+    torch.cuda.synchronize()
+    us = a.elapsed_time(b) * 1e3 / (reps * len(items))
+    del g
+    return us
+
+
+def bench_ops_batch(bp, torch, calls=1280, fracs=(0.001, 0.01, 0.1), m=8):
+    """Batched spike products on the operator sweep's matrix (1e5 x 1e5,
+    p = 0.01): m spike vectors per call (E [m, 1e5]), 8 distinct batches
+    cycled from the same 64 vectors per firing fraction as the single-vector
+    sweep.  Stored CSR with a tile index of 4096 columns (counts: 8 vectors per
+    group) or 2048 (sums); JIT with the sweep's blocks of 3125."""
+    import synthetic as S
+    n, K = 100_000, bp.max_gap(0.01)
+    dev = "cuda"
+    ip, ix = bp.csr_build(bp.JitConn(n, n, K=K, seed=0))
+    data = torch.from_numpy(S.hetero_data(ix.numel(), 1)).to(dev)
+    rowlen = (ip[1:] - ip[:-1]).to(torch.int64)
+    tp4, tp2 = bp.csr_tile_index(ip, ix, n, 4096), bp.csr_tile_index(ip, ix, n, 2048)
+    out = []
+    for frac in fracs:
+        ev = torch.from_numpy(S.events(n, frac, 5, count=64)).to(dev)
+        Es = [ev[i * m:(i + 1) * m] for i in range(64 // m)]
+        nnz_a = float((ev.to(torch.int64) * rowlen[None, :]).sum(1).double().mean().item())
+        jc = bp.JitConn(n, n, K=K, block=JIT_OP_BLOCK, seed=0, w0=0.5)
+        jn = bp.JitConn(n, n, K=K, block=JIT_OP_BLOCK, seed=0, wkind=bp.W_NORMAL, w0=0.5, w1=0.1)
+        Y = torch.empty((m, n), dtype=torch.float32, device=dev)
+        cases = [
+            ("event_csr_homo", lambda E: bp.event_csr_matmat(ip, ix, None, 0.5, n, E, tp4, 4096, out=Y, ws=ws),
+             bp.event_csr_matmat_ws(ip, ix, None, 0.5, n, m, tp4, 4096)),
+            ("event_csr_hetero", lambda E: bp.event_csr_matmat(ip, ix, data, 0.0, n, E, tp2, 2048, out=Y, ws=ws),
+             bp.event_csr_matmat_ws(ip, ix, data, 0.0, n, m, tp2, 2048)),
+            ("jit_homo", lambda E: bp.jit_conn_matmat(jc, E, out=Y, ws=ws), bp.jit_conn_matmat_ws(jc, m)),
+            ("jit_normal", lambda E: bp.jit_conn_matmat(jn, E, out=Y, ws=ws), bp.jit_conn_matmat_ws(jn, m)),
+        ]
+        for name, fn, wsb in cases:
+            ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+            us = _graph_time_us(torch, fn, Es, calls // m)
+            out.append(dict(op=f"{name}_batch{m}", firing=frac, vectors=m, us_per_call=us, us_per_vector=us / m,
+                            synaptic_events_per_s=m * nnz_a / (us * 1e-6)))
+    return out
+
+
+def bench_rules(bp, torch, calls=1280, fracs=(0.01, 0.1)):
+    """The JIT spike product on 1e5 x 1e5 under each connectivity rule:
+    uniform gaps on [1, K] (the paper's sampler, blocks of 3125), geometric
+    gaps (exact Bernoulli(0.01), same blocks) and exactly 1000 targets per row
+    (one block per row), homogeneous weights; Appendix C compares the first
+    two samplers' cost."""
+    import synthetic as S
+    n, K = 100_000, bp.max_gap(0.01)
+    dev = "cuda"
+    conns = [("uniform_gaps", bp.JitConn(n, n, K=K, block=JIT_OP_BLOCK, seed=0, w0=0.5)),
+             ("geometric_gaps", bp.JitConn(n, n, p=0.01, block=JIT_OP_BLOCK, seed=0, w0=0.5,
+                                           rule=bp.RULE_GEOMETRIC)),
+             ("fixed_degree_1000", bp.JitConn(n, n, block=0, seed=0, w0=0.5, rule=bp.RULE_FIXED_DEGREE,
+                                              degree=1000))]
+    y = torch.empty(n, dtype=torch.float32, device=dev)
+    out = []
+    for frac in fracs:
+        ev = torch.from_numpy(S.events(n, frac, 5, count=64)).to(dev)
+        for name, c in conns:
+            ip, _ = bp.csr_build(c)
+            rowlen = (ip[1:] - ip[:-1]).to(torch.int64)
+            nnz_a = float((ev.to(torch.int64) * rowlen[None, :]).sum(1).double().mean().item())
+            ws = torch.empty(max(bp.jit_ws(c), 1), dtype=torch.uint8, device=dev)
+            us = _graph_time_us(torch, lambda e: bp.jit_conn_matvec(c, e, out=y, ws=ws), list(ev), calls)
+            out.append(dict(op=f"jit_homo_{name}", firing=frac, block=int(c.block), us_per_call=us,
+                            synapses_per_s=nnz_a / (us * 1e-6)))
+    return out
+
+
+def bench_backward(bp, torch, calls=64):
+    """Reverse mode of the operators on the sweep's matrix (1e5 x 1e5,
+    p = 0.01, 10 % firing): the event-CSR VJP (d_events over every row, d_data
+    over the firing rows' entries, d_w) and the JIT VJP (d_events, d_w)."""
+    import synthetic as S
+    n, K = 100_000, bp.max_gap(0.01)
+    dev = "cuda"
+    ip, ix = bp.csr_build(bp.JitConn(n, n, K=K, seed=0))
+    nnz = int(ix.numel())
+    data = torch.from_numpy(S.hetero_data(nnz, 1)).to(dev)
+    e = torch.from_numpy(S.events(n, 0.1, 5)).to(dev)
+    dy = torch.from_numpy(S.dense_vector(n, 3)).to(dev)
+    out = []
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for name, fn, alg in [
+        ("event_csr_vjp_hetero", lambda: bp.event_csr_backward(ip, ix, data, 0.0, n, e, dy),
+         # indptr, indices, data, gathered dy and d_data per entry; d_events
+         8.0 * (n + 1) + 16.0 * nnz + 4.0 * n),
+        ("jit_vjp_homo", lambda: bp.jit_conn_backward(bp.JitConn(n, n, K=K, block=JIT_OP_BLOCK, seed=0, w0=0.5),
+                                                      e, dy), None),
+        ("jit_vjp_normal", lambda: bp.jit_conn_backward(
+            bp.JitConn(n, n, K=K, block=JIT_OP_BLOCK, seed=0, wkind=bp.W_NORMAL, w0=0.5, w1=0.1), e, dy), None),
+    ]:
+        fn()
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(calls):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        us = a.elapsed_time(b) * 1e3 / calls
+        row = dict(op=name, us_per_call=us, synapses=nnz, synapses_per_s=nnz / (us * 1e-6))
+        if alg is not None:
+            row.update(alg_bytes=alg, alg_GBps=alg / (us * 1e-6) / 1e9, hbm_frac=alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS)
+        out.append(row)
+    return out
+
+
 def bench_dense(bp, torch, calls=640):
     """JIT product on dense float vectors (Section 5.2's operator y = J^T v):
     n_pre = n_post = 1e5, p = 0.01, blocks of DENSE_OP_BLOCK columns, v ~ N(0, 1)
@@ -401,21 +532,24 @@ def bench_snn(bp, torch, reps=5):
                 hidden_spikes_per_s=spikes / (ms * 1e-3))
 
 
-def bench_serving(bp, torch, n_requests=100, rate_hz=20.0, budget_gib=1.0, quantum=500, max_wgs=64):
+def bench_serving(bp, torch, n_requests=600, n_warm=50, rate_hz=100.0, budget_gib=4.0, quantum=500, max_wgs=64):
     """Serving workload: Poisson arrivals at rate_hz, N ~ log-uniform[1e3,
     2e5], p = 80/N, duration ~ U(100, 2000) ms at dt = 0.1 ms, COBA or CUBA
     with probability 1/2, per-request seed; continuous batching under an HBM
-    budget against the plain one-net-at-a-time path on the same GPU."""
+    budget against the plain one-net-at-a-time path on the same GPU.  The
+    stream has n_warm + n_requests requests; statistics cover the last
+    n_requests.  The arrival rate is above what the plain path serves (about
+    20 requests per second), so it saturates and its queue grows."""
     import synthetic as S
     from paper_2311_05106_amd import serving as sv
-    reqs = S.request_stream(n_requests, rate_hz, 0)
-    warm = S.request_stream(4, rate_hz, 1)
-    sv.serve_batched(warm, hbm_budget=int(budget_gib * 2**30), quantum=quantum, max_wgs=max_wgs)
-    a = sv.summarize(sv.serve_batched(reqs, hbm_budget=int(budget_gib * 2**30), quantum=quantum, max_wgs=max_wgs))
-    b = sv.summarize(sv.serve_plain(reqs))
-    return dict(workload=f"{n_requests} requests, Poisson {rate_hz:g} req/s, N ~ logU[1e3, 2e5], p=80/N, "
-                         f"duration U(100, 2000) ms, COBA/CUBA", hbm_budget_gib=budget_gib, quantum_steps=quantum,
-                max_wgs_per_net=max_wgs, batched=a, plain=b)
+    reqs = S.request_stream(n_warm + n_requests, rate_hz, 0)
+    budget = int(budget_gib * 2**30)
+    a = sv.summarize(sv.serve_batched(reqs, hbm_budget=budget, quantum=quantum, max_wgs=max_wgs), skip=n_warm)
+    b = sv.summarize(sv.serve_plain(reqs), skip=n_warm)
+    return dict(workload=f"{n_warm} warm-up + {n_requests} requests, Poisson {rate_hz:g} req/s, N ~ logU[1e3, 2e5], "
+                         f"p=80/N, duration U(100, 2000) ms, COBA/CUBA", hbm_budget_gib=budget_gib,
+                quantum_steps=quantum, max_wgs_per_net=max_wgs, batched=a, plain=b,
+                throughput_ratio=a["synaptic_events_per_s"] / b["synaptic_events_per_s"])
 
 
 def bench_copy(bp, torch, mib=1024, reps=2):
@@ -451,7 +585,8 @@ def main():
     ap.add_argument("--calls", type=int, default=10000, help="products per point of the operator sweep")
     ap.add_argument("--ops-frac", type=float, default=None,
                     help="run the operator sweep at this firing fraction only (for profiling)")
-    ap.add_argument("--section", choices=["c0", "ops", "dense", "snn", "serving", "copy"],
+    ap.add_argument("--section", choices=["c0", "ops", "ops_batch", "rules", "backward", "dense", "snn", "serving",
+                                          "copy"],
                     help="run only this secondary workload and print its JSON (for profiling)")
     args = ap.parse_args()
     globals()["C2_BLOCK"] = args.block
@@ -470,8 +605,8 @@ def main():
             res = bench_ops(bp, torch, calls=args.calls,
                             **({} if args.ops_frac is None else {"fracs": (args.ops_frac,)}))
         else:
-            res = dict(c0=bench_c0, dense=bench_dense, snn=bench_snn, serving=bench_serving,
-                       copy=bench_copy)[args.section](bp, torch)
+            res = dict(c0=bench_c0, dense=bench_dense, snn=bench_snn, serving=bench_serving, copy=bench_copy,
+                       ops_batch=bench_ops_batch, rules=bench_rules, backward=bench_backward)[args.section](bp, torch)
         print(json.dumps({args.section: res}), flush=True)
         return
 
@@ -528,8 +663,21 @@ def main():
             workgroups=w["n_wg"], us_per_sim_step=w["wall"] * 1e6 / (4 * LAUNCH_STEPS),
             launch_ms=sum(w["launch_ms"]) / 4, synaptic_events_per_s=w["events"] / w["wall"],
             sim_s_per_wall_s=4 * LAUNCH_STEPS * w["dt_ms"] * 1e-3 / w["wall"])
+        f = bench_network(bp, torch, 4, 1, desc=bp.net_desc(400_000, n_exc=320_000, K=1, conn=bp.CONN_JIT, block=0,
+                                                            seed=0, rule=bp.RULE_FIXED_DEGREE, degree=80))
+        line["c2_fixed_degree"] = dict(
+            workload="the 400k net with exactly 80 targets per neuron (3.2e7 synapses, the fixed out-degree of "
+                     "the configuration read literally), regenerated every step and pushed by the writers; 1 warm-up "
+                     f"+ 4 timed launches of {LAUNCH_STEPS} steps",
+            workgroups=f["n_wg"], us_per_sim_step=f["wall"] * 1e6 / (4 * LAUNCH_STEPS),
+            launch_ms=sum(f["launch_ms"]) / 4, synaptic_events_per_s=f["events"] / f["wall"],
+            sim_s_per_wall_s=4 * LAUNCH_STEPS * f["dt_ms"] * 1e-3 / f["wall"],
+            mean_rate_hz=f["spikes"] / (4 * LAUNCH_STEPS) / f["n"] / (f["dt_ms"] * 1e-3))
         line["c0"] = bench_c0(bp, torch)
         line["operator_sweep"] = bench_ops(bp, torch, calls=args.calls)
+        line["operator_sweep_batch8"] = bench_ops_batch(bp, torch)
+        line["connectivity_rules"] = bench_rules(bp, torch)
+        line["reverse_mode"] = bench_backward(bp, torch)
         line["jit_dense_vector"] = bench_dense(bp, torch)
         line["snn_training"] = bench_snn(bp, torch)
         line["serving"] = bench_serving(bp, torch)
