@@ -411,6 +411,41 @@ def bench_backward(bp, torch, calls=64):
     return out
 
 
+def bench_proj(bp, torch, T=200):
+    """Projections with a 10-step spike delay (Section 4.3, Appendix D):
+    AlignPost (event product, then g <- g d + y) against AlignPre (trace
+    update, then the float-vector product of the traces), on the 4000-neuron
+    net's stored matrix (p = 0.02) and on a regenerated 1e5 x 1e5 matrix
+    (p = 0.01, blocks of 3125), driven by T steps of 2 % firing; us per step
+    (one delay push and one projection step), the T steps issued back to back."""
+    import math
+    import synthetic as S
+    out = []
+    d = float(math.exp(-0.1 / 5.0))
+    for name, n, kw in [
+        ("csr_4000_p0.02", 4000, None),
+        ("jit_1e5_p0.01", 100_000, dict(jit=bp.JitConn(100_000, 100_000, K=bp.max_gap(0.01), block=JIT_OP_BLOCK,
+                                                     seed=0, w0=0.6))),
+    ]:
+        if kw is None:
+            ip, ix = bp.csr_build(bp.JitConn(n, n, K=bp.max_gap(0.02), seed=0))
+            kw = dict(csr=(ip, ix, None, 0.6, n))
+        R = torch.from_numpy(S.events(n, 0.02, 9, count=T)).to("cuda")
+        for align in (bp.ALIGN_POST, bp.ALIGN_PRE):
+            pr = bp.Projection(align, d, delay=10, depth=11, **kw)
+            g = torch.empty((T, n), dtype=torch.float32, device="cuda")
+            pr.run(R, g_out=g)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            pr.run(R, g_out=g)
+            b.record()
+            torch.cuda.synchronize()
+            out.append(dict(projection=name, align="post" if align == bp.ALIGN_POST else "pre", delay=10,
+                            us_per_step=a.elapsed_time(b) * 1e3 / T))
+    return out
+
+
 def bench_dense(bp, torch, calls=640):
     """JIT product on dense float vectors (Section 5.2's operator y = J^T v):
     n_pre = n_post = 1e5, p = 0.01, blocks of DENSE_OP_BLOCK columns, v ~ N(0, 1)
@@ -585,8 +620,8 @@ def main():
     ap.add_argument("--calls", type=int, default=10000, help="products per point of the operator sweep")
     ap.add_argument("--ops-frac", type=float, default=None,
                     help="run the operator sweep at this firing fraction only (for profiling)")
-    ap.add_argument("--section", choices=["c0", "ops", "ops_batch", "rules", "backward", "dense", "snn", "serving",
-                                          "copy"],
+    ap.add_argument("--section", choices=["c0", "ops", "ops_batch", "rules", "backward", "proj", "dense", "snn",
+                                          "serving", "copy"],
                     help="run only this secondary workload and print its JSON (for profiling)")
     args = ap.parse_args()
     globals()["C2_BLOCK"] = args.block
@@ -606,7 +641,8 @@ def main():
                             **({} if args.ops_frac is None else {"fracs": (args.ops_frac,)}))
         else:
             res = dict(c0=bench_c0, dense=bench_dense, snn=bench_snn, serving=bench_serving, copy=bench_copy,
-                       ops_batch=bench_ops_batch, rules=bench_rules, backward=bench_backward)[args.section](bp, torch)
+                       ops_batch=bench_ops_batch, rules=bench_rules, backward=bench_backward,
+                       proj=bench_proj)[args.section](bp, torch)
         print(json.dumps({args.section: res}), flush=True)
         return
 
@@ -678,6 +714,7 @@ def main():
         line["operator_sweep_batch8"] = bench_ops_batch(bp, torch)
         line["connectivity_rules"] = bench_rules(bp, torch)
         line["reverse_mode"] = bench_backward(bp, torch)
+        line["projections"] = bench_proj(bp, torch)
         line["jit_dense_vector"] = bench_dense(bp, torch)
         line["snn_training"] = bench_snn(bp, torch)
         line["serving"] = bench_serving(bp, torch)

@@ -146,6 +146,9 @@ def _load(path):
     L.or_snn_grad.argtypes = [C.POINTER(SnnParams), _u8p, _i32p, _f64p, _i32p, _i32p, _f64p, _f64p, _f64p,
                               C.c_void_p, C.c_void_p, C.POINTER(C.c_double), _f64p, C.c_void_p, C.c_void_p,
                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.or_snn_grad_abs.restype = C.c_int
+    L.or_snn_grad_abs.argtypes = [C.POINTER(SnnParams), _u8p, _i32p, _f64p, _i32p, _i32p, _f64p, _f64p, _f64p, _u8p,
+                                  _f64p, _f64p, _f64p, _f64p]
     L.or_snn_spike_fns.argtypes = [C.POINTER(SnnParams), _f64p, C.c_int64, C.c_void_p, C.c_void_p]
     return L
 
@@ -531,6 +534,25 @@ def snn_spike_fns(P, v):
     ds = np.empty_like(vv)
     lib().or_snn_spike_fns(C.byref(P), vv, vv.size, _ptr(s), _ptr(ds))
     return s, ds
+
+
+def snn_grad_abs(P, x, labels, W_in, indptr, indices, w_rec, W_out, b_out, z_force):
+    """Per-entry sum of |terms| reaching each gradient entry through the
+    reverse pass (spikes z_force [T, B, N]): the scale of the parity
+    tolerance of an FP32 reverse pass."""
+    Cc, N, O = P.C, P.N, P.O
+    nnz = int(indptr[-1])
+    a = dict(dW_in=np.empty((Cc, N), np.float64), dw_rec=np.empty(max(nnz, 1), np.float64),
+             dW_out=np.empty((N, O), np.float64), db_out=np.empty(O, np.float64))
+    rc = lib().or_snn_grad_abs(C.byref(P), np.ascontiguousarray(x, np.uint8), np.ascontiguousarray(labels, np.int32),
+                               np.ascontiguousarray(W_in, np.float64), np.ascontiguousarray(indptr, np.int32),
+                               np.ascontiguousarray(indices, np.int32), np.ascontiguousarray(w_rec, np.float64),
+                               np.ascontiguousarray(W_out, np.float64), np.ascontiguousarray(b_out, np.float64),
+                               np.ascontiguousarray(z_force, np.uint8), a["dW_in"], a["dw_rec"], a["dW_out"],
+                               a["db_out"])
+    assert rc == 0
+    a["dw_rec"] = a["dw_rec"][:nnz]
+    return a
 
 
 def snn_grad(P, x, labels, W_in, indptr, indices, w_rec, W_out, b_out, z_force=None, want_z=False,

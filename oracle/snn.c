@@ -236,3 +236,122 @@ int or_snn_grad(const or_snn* P, const uint8_t* x, const int32_t* labels, const 
   free(dlog); free(zsum);
   return 0;
 }
+
+/*
+ * Magnitude companion of or_snn_grad's reverse pass (a running error bound):
+ * the same recursion with every sum replaced by the sum of the absolute
+ * values of its terms, so that each output entry is the sum of |terms| that
+ * reach that gradient entry through every path of the reverse pass.  An
+ * implementation that carries the reverse pass in FP32 with the same spikes
+ * differs from the FP64 gradient by a small multiple of its unit roundoff
+ * times this sum per entry (the reverse recursion is contracting, alpha and
+ * beta below one), which is what the per-entry parity tolerance is stated
+ * against.  Spikes are taken from z_force (required); the outputs are
+ * [C, N], [nnz], [N, O], [O] like the gradients.
+ */
+int or_snn_grad_abs(const or_snn* P, const uint8_t* x, const int32_t* labels, const double* W_in,
+                    const int32_t* indptr, const int32_t* indices, const double* w_rec, const double* W_out,
+                    const double* b_out, const uint8_t* z_force, double* aW_in, double* aw_rec, double* aW_out,
+                    double* ab_out) {
+  const int32_t B = P->B, C = P->C, N = P->N, O = P->O, T = P->T;
+  const size_t TBN = (size_t)T * B * N;
+  const int32_t nnz = indptr[N];
+  double* I = (double*)calloc(TBN, sizeof(double));
+  double* V = (double*)calloc(TBN, sizeof(double));
+  double* Z = (double*)calloc(TBN, sizeof(double));
+  double* dIn = (double*)calloc((size_t)B * N, sizeof(double));
+  double* dVn = (double*)calloc((size_t)B * N, sizeof(double));
+  double* dI = (double*)calloc((size_t)B * N, sizeof(double));
+  double* dV = (double*)calloc((size_t)B * N, sizeof(double));
+  double* dlog = (double*)calloc((size_t)B * O, sizeof(double));
+  double* zsum = (double*)calloc((size_t)B * N, sizeof(double));
+  if (!I || !V || !Z || !dIn || !dVn || !dI || !dV || !dlog || !zsum || !z_force) return -1;
+  /* forward with the given spikes (the reset factor is 1 - z_{t-1}) */
+  for (int32_t t = 0; t < T; ++t)
+    for (int32_t b = 0; b < B; ++b) {
+      double* It = I + ((size_t)t * B + b) * N;
+      double* Vt = V + ((size_t)t * B + b) * N;
+      double* Zt = Z + ((size_t)t * B + b) * N;
+      const double* Ip = t ? I + ((size_t)(t - 1) * B + b) * N : NULL;
+      const double* Vp = t ? V + ((size_t)(t - 1) * B + b) * N : NULL;
+      const double* Zp = t ? Z + ((size_t)(t - 1) * B + b) * N : NULL;
+      const uint8_t* xt = x + ((size_t)t * B + b) * C;
+      for (int32_t k = 0; k < N; ++k) It[k] = Ip ? P->alpha * Ip[k] : 0.0;
+      for (int32_t c = 0; c < C; ++c)
+        if (xt[c])
+          for (int32_t k = 0; k < N; ++k) It[k] += W_in[(size_t)c * N + k];
+      if (Zp)
+        for (int32_t j = 0; j < N; ++j)
+          if (Zp[j] != 0.0)
+            for (int32_t idx = indptr[j]; idx < indptr[j + 1]; ++idx) It[indices[idx]] += w_rec[idx];
+      for (int32_t k = 0; k < N; ++k) {
+        const double vprev = Vp ? Vp[k] * (1.0 - Zp[k]) : 0.0;
+        Vt[k] = P->beta * vprev + (1.0 - P->beta) * It[k];
+        Zt[k] = z_force[((size_t)t * B + b) * N + k] ? 1.0 : 0.0;
+        zsum[(size_t)b * N + k] += Zt[k];
+      }
+    }
+  for (int32_t b = 0; b < B; ++b) {
+    double lg[1024];
+    double mx = -1e300;
+    for (int32_t o = 0; o < O; ++o) {
+      double acc = b_out[o];
+      for (int32_t k = 0; k < N; ++k) acc += zsum[(size_t)b * N + k] / T * W_out[(size_t)k * O + o];
+      lg[o] = acc;
+      if (acc > mx) mx = acc;
+    }
+    double se = 0.0;
+    for (int32_t o = 0; o < O; ++o) se += exp(lg[o] - mx);
+    for (int32_t o = 0; o < O; ++o)
+      dlog[(size_t)b * O + o] = fabs((exp(lg[o] - mx) / se - (o == labels[b] ? 1.0 : 0.0)) / B);
+  }
+  memset(aW_in, 0, sizeof(double) * (size_t)C * N);
+  memset(aw_rec, 0, sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+  for (int32_t k = 0; k < N; ++k)
+    for (int32_t o = 0; o < O; ++o) {
+      double acc = 0.0;
+      for (int32_t b = 0; b < B; ++b) acc += zsum[(size_t)b * N + k] / T * dlog[(size_t)b * O + o];
+      aW_out[(size_t)k * O + o] = acc;
+    }
+  for (int32_t o = 0; o < O; ++o) {
+    double acc = 0.0;
+    for (int32_t b = 0; b < B; ++b) acc += dlog[(size_t)b * O + o];
+    ab_out[o] = acc;
+  }
+  for (int32_t t = T - 1; t >= 0; --t) {
+    for (int32_t b = 0; b < B; ++b) {
+      const double* Vt = V + ((size_t)t * B + b) * N;
+      const double* Zt = Z + ((size_t)t * B + b) * N;
+      double* dInb = dIn + (size_t)b * N;
+      double* dVnb = dVn + (size_t)b * N;
+      double* dIt = dI + (size_t)b * N;
+      double* dVt = dV + (size_t)b * N;
+      for (int32_t j = 0; j < N; ++j) {
+        double acc = 0.0;
+        for (int32_t o = 0; o < O; ++o) acc += fabs(W_out[(size_t)j * O + o]) * dlog[(size_t)b * O + o];
+        acc /= T;
+        if (t + 1 < T) {
+          for (int32_t idx = indptr[j]; idx < indptr[j + 1]; ++idx) acc += fabs(w_rec[idx]) * dInb[indices[idx]];
+          if (!P->detach_reset) acc += dVnb[j] * P->beta * fabs(Vt[j]);
+        }
+        const double g = acc * fabs(surrogate(P, Vt[j])) + (t + 1 < T ? dVnb[j] * P->beta * (1.0 - Zt[j]) : 0.0);
+        dVt[j] = g;
+        dIt[j] = g * (1.0 - P->beta) + (t + 1 < T ? dInb[j] * P->alpha : 0.0);
+      }
+      const uint8_t* xt = x + ((size_t)t * B + b) * C;
+      for (int32_t c = 0; c < C; ++c)
+        if (xt[c])
+          for (int32_t k = 0; k < N; ++k) aW_in[(size_t)c * N + k] += dIt[k];
+      if (t > 0) {
+        const double* Zp = Z + ((size_t)(t - 1) * B + b) * N;
+        for (int32_t j = 0; j < N; ++j)
+          if (Zp[j] != 0.0)
+            for (int32_t idx = indptr[j]; idx < indptr[j + 1]; ++idx) aw_rec[idx] += dIt[indices[idx]];
+      }
+    }
+    memcpy(dIn, dI, sizeof(double) * (size_t)B * N);
+    memcpy(dVn, dV, sizeof(double) * (size_t)B * N);
+  }
+  free(I); free(V); free(Z); free(dIn); free(dVn); free(dI); free(dV); free(dlog); free(zsum);
+  return 0;
+}

@@ -708,35 +708,55 @@ __global__ void csr_backward_k(bp_csr m, const uint8_t* __restrict__ ev, const f
   }
 }
 
-// One thread per row (all blocks of the row in order).
+// LPR lanes per row (a power of two up to 64, groups aligned in the wave):
+// lane q of the group walks the row's blocks q, q + LPR, ... (for exactly
+// fixed out-degree, the targets q, q + LPR, ... of the row's permutation);
+// the group's partial sums are then combined by shuffles in a fixed order,
+// so d_events does not depend on scheduling.
+template <int LPR>
 __global__ void jit_backward_k(bp_jit_conn c, const uint8_t* __restrict__ ev, const float* __restrict__ dy,
                                float* __restrict__ d_ev, float* __restrict__ d_w) {
-  const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  float g0 = 0.f, g1 = 0.f;
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t j = (int32_t)(gt / LPR);
+  const int q = (int)(gt % LPR);
+  float acc = 0.f, g0 = 0.f, g1 = 0.f;
   if (j < c.n_pre) {
-    const int32_t nb = c.block > 0 ? (int32_t)(((int64_t)c.n_post + c.block - 1) / c.block) : 1;
     const bool on = ev[j] != 0;
-    float acc = 0.f;
     const uint64_t seed = c.seed;
-    const ConnGen G = conn_gen(c);
-    const int32_t n_post = c.n_post, B = c.block, wkind = c.wkind;
+    const int32_t n_post = c.n_post, wkind = c.wkind;
     const float w0 = c.w0, w1 = c.w1;
-    for (int32_t b = 0; b < nb; ++b) {
-      DrawSeq wd(seed, kStreamW, (uint32_t)j, (uint32_t)b);
-      gen_block(G, (uint32_t)j, (uint32_t)b, 0, n_post, [&](int32_t pos, uint32_t m) {
-        float unit;
-        const float wjk = jit_weight(wd, wkind, w0, w1, m, &unit);
-        const float g = dy[pos];
-        acc += wjk * g;
-        if (on) {
-          // d w / d w0 and d w / d w1: (1, z) normal, (1 - u, u) uniform, (1, 0) homogeneous
-          g0 += (wkind == kWUniform ? 1.f - unit : 1.f) * g;
-          g1 += (wkind == kWHomo ? 0.f : unit) * g;
-        }
-      });
+    auto term = [&](DrawSeq& wd, int32_t pos, uint32_t m) {
+      float unit;
+      const float wjk = jit_weight(wd, wkind, w0, w1, m, &unit);
+      const float g = dy[pos];
+      acc += wjk * g;
+      if (on) {
+        // d w / d w0 and d w / d w1: (1, z) normal, (1 - u, u) uniform, (1, 0) homogeneous
+        g0 += (wkind == kWUniform ? 1.f - unit : 1.f) * g;
+        g1 += (wkind == kWHomo ? 0.f : unit) * g;
+      }
+    };
+    if (c.rule == kRuleFixedDegree) {
+      const Words4 key = fd_keys(seed, (uint32_t)j);
+      const uint32_t fb = fd_bits(n_post);
+      const int32_t k = c.degree < n_post ? c.degree : n_post;
+      for (int32_t i = q; i < k; i += LPR) {
+        DrawSeq wd(seed, kStreamW, (uint32_t)j, 0u);
+        term(wd, (int32_t)fd_target(key, fb, n_post, (uint32_t)i), (uint32_t)i);
+      }
+    } else {
+      const ConnGen G = conn_gen(c);
+      const int32_t nb = c.block > 0 ? (int32_t)(((int64_t)n_post + c.block - 1) / c.block) : 1;
+      for (int32_t b = q; b < nb; b += LPR) {
+        DrawSeq wd(seed, kStreamW, (uint32_t)j, (uint32_t)b);
+        gen_block(G, (uint32_t)j, (uint32_t)b, 0, n_post,
+                  [&](int32_t pos, uint32_t m) { term(wd, pos, m); });
+      }
     }
-    if (d_ev) d_ev[j] = acc;
   }
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+  if (j < c.n_pre && q == 0 && d_ev) d_ev[j] = acc;
   if (d_w) {
     g0 = wave_sum_f(g0);
     g1 = wave_sum_f(g1);
@@ -1289,7 +1309,24 @@ bp_status bp_jit_conn_backward(const bp_jit_conn* c, const uint8_t* events, cons
   }
   if (c->n_pre == 0) return BP_OK;
   BP_REQUIRE(events && dy, "null events or dy");
-  jit_backward_k<<<(c->n_pre + 255) / 256, 256, 0, st>>>(*c, events, dy, d_events, d_w);
+  // lanes per row: one per post block (rounded up to a power of two), 64 for
+  // exactly fixed out-degree (one per target), 1 for a single block
+  const int32_t nb = c->block > 0 ? (int32_t)(((int64_t)c->n_post + c->block - 1) / c->block) : 1;
+  int lpr = 1;
+  if (c->rule == kRuleFixedDegree) lpr = 64;
+  else
+    while (lpr < nb && lpr < 64) lpr *= 2;
+  const int64_t threads = (int64_t)c->n_pre * lpr;
+  const unsigned grid = (unsigned)((threads + 255) / 256);
+  switch (lpr) {
+    case 1: jit_backward_k<1><<<grid, 256, 0, st>>>(*c, events, dy, d_events, d_w); break;
+    case 2: jit_backward_k<2><<<grid, 256, 0, st>>>(*c, events, dy, d_events, d_w); break;
+    case 4: jit_backward_k<4><<<grid, 256, 0, st>>>(*c, events, dy, d_events, d_w); break;
+    case 8: jit_backward_k<8><<<grid, 256, 0, st>>>(*c, events, dy, d_events, d_w); break;
+    case 16: jit_backward_k<16><<<grid, 256, 0, st>>>(*c, events, dy, d_events, d_w); break;
+    case 32: jit_backward_k<32><<<grid, 256, 0, st>>>(*c, events, dy, d_events, d_w); break;
+    default: jit_backward_k<64><<<grid, 256, 0, st>>>(*c, events, dy, d_events, d_w); break;
+  }
   BP_LAUNCHED("jit_backward_k");
   return BP_OK;
 }

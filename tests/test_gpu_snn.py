@@ -2,7 +2,8 @@
 BPTT against the FP64 oracle.  The oracle is teacher-forced with the GPU's
 spikes; every GPU spike decision must agree with the FP64 membrane potential
 except within 1e-4 of threshold.  Loss and logits: 1e-5 relative; gradients:
-relative L2 error below 1e-4.  Checkpoint interval does not change the
+every entry within 1e-4 of the sum of |terms| that reach it through the
+reverse pass, and relative L2 error below 1e-4.  Checkpoint interval does not change the
 gradient bits."""
 import math
 
@@ -59,6 +60,24 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a.astype(np.float64) - b) / max(np.linalg.norm(b), 1e-30))
 
 
+def check_grads(case, B, Cc, N, Ocls, T, g, r, **cfg):
+    """Every gradient entry within 1e-4 of the sum of |terms| reaching it
+    through the reverse pass (the oracle's magnitude companion, on the GPU's
+    spikes), exact zeros where no term reaches; and relative L2 below 1e-4."""
+    P = O.snn_params(B, Cc, N, Ocls, T, alpha=cfg["alpha"], beta=cfg["beta"], theta=cfg.get("theta", 1.0),
+                     slope=cfg.get("slope", 4.0), surrogate=cfg.get("surrogate", 0),
+                     detach_reset=cfg.get("detach_reset", 1))
+    f64 = lambda a: np.asarray(a, np.float64)
+    a = O.snn_grad_abs(P, case["x"], case["labels"], f64(case["W_in"]), case["ip"], case["ix"], f64(case["w_rec"]),
+                       f64(case["W_out"]), f64(case["b_out"]), g["raster"])
+    for k in ("dW_in", "dw_rec", "dW_out", "db_out"):
+        err = np.abs(g[k].astype(np.float64) - r[k])
+        bad = np.flatnonzero(err > 1e-4 * a[k] + 1e-12)
+        assert bad.size == 0, (k, bad[:5], err.reshape(-1)[bad[:5]], a[k].reshape(-1)[bad[:5]])
+        assert np.all(g[k][a[k] == 0] == 0), k
+        assert rel_l2(g[k], r[k]) < 1e-4, (k, rel_l2(g[k], r[k]))
+
+
 CFG = dict(alpha=math.exp(-1 / 5), beta=math.exp(-1 / 20), theta=1.0, slope=4.0)
 
 
@@ -76,8 +95,7 @@ def test_snn_small_against_oracle(mods, surrogate, detach):
     assert not np.any(z & (m < -1e-4)) and not np.any(~z & (m > 1e-4)), "spike decision disagrees with FP64"
     assert g["loss"] == pytest.approx(r["loss"], rel=1e-5)
     np.testing.assert_allclose(g["logits"], r["logits"], rtol=1e-5, atol=1e-6)
-    for k in ("dW_in", "dw_rec", "dW_out", "db_out"):
-        assert rel_l2(g[k], r[k]) < 1e-4, (k, rel_l2(g[k], r[k]))
+    check_grads(case, B, Cc, N, Ocls, T, g, r, **cfg)
 
 
 def test_checkpoint_interval_does_not_change_bits(mods):
@@ -106,8 +124,7 @@ def test_snn_full_config_against_oracle(mods):
     m = r["vmargin"]
     assert not np.any(z & (m < -1e-4)) and not np.any(~z & (m > 1e-4))
     assert g["loss"] == pytest.approx(r["loss"], rel=1e-5)
-    for k in ("dW_in", "dw_rec", "dW_out", "db_out"):
-        assert rel_l2(g[k], r[k]) < 1e-4, (k, rel_l2(g[k], r[k]))
+    check_grads(case, B, Cc, N, Ocls, T, g, r, **CFG)
 
 
 def test_snn_autograd_function(mods):

@@ -203,3 +203,32 @@ def test_readout_gradient_closed_form():
     np.testing.assert_allclose(g["db_out"], (sm - oh).mean(0), rtol=1e-12, atol=1e-15)
     lse = np.log(np.exp(lg).sum(1))
     assert g["loss"] == pytest.approx(float((lse - lg[np.arange(2), d["labels"]]).mean()), rel=1e-12)
+
+
+@pytest.mark.parametrize("detach,kind", [(1, "sigmoid"), (0, "sigmoid"), (1, "relu")])
+def test_gradient_magnitude_companion(detach, kind):
+    # the per-entry tolerance scale of the GPU's reverse pass: the same
+    # recursion on absolute values bounds every gradient entry (triangle
+    # inequality) and vanishes exactly where no term reaches an entry; with
+    # one sample the readout gradients have a single term per entry, so
+    # there it equals |gradient|
+    T = 25
+    P = O.snn_params(2, 6, 12, 3, T, alpha=math.exp(-1 / 5), beta=math.exp(-1 / 20), theta=1.0,
+                     detach_reset=detach, **SURR[kind])
+    d = tiny(T=T)
+    g = loss_of(P, d, want_z=True)
+    a = O.snn_grad_abs(P, d["x"], d["labels"], d["W_in"], d["indptr"], d["indices"], d["w_rec"], d["W_out"],
+                       d["b_out"], g["z"])
+    for k in ("dW_in", "dw_rec", "dW_out", "db_out"):
+        assert np.all(a[k] >= np.abs(g[k]) * (1 - 1e-12) - 1e-300), k
+        assert np.all(np.isfinite(a[k]))
+        assert np.all(g[k][a[k] == 0] == 0), k
+    assert (a["dW_in"] > np.abs(g["dW_in"]) * 1.0001).any()  # cancellation happens in the recursion
+    P1 = O.snn_params(1, 6, 12, 3, T, alpha=math.exp(-1 / 5), beta=math.exp(-1 / 20), theta=1.0,
+                      detach_reset=detach, **SURR[kind])
+    d1 = dict(d, x=d["x"][:, :1], labels=d["labels"][:1])
+    g1 = loss_of(P1, d1, want_z=True)
+    a1 = O.snn_grad_abs(P1, d1["x"], d1["labels"], d1["W_in"], d1["indptr"], d1["indices"], d1["w_rec"],
+                        d1["W_out"], d1["b_out"], g1["z"])
+    np.testing.assert_allclose(a1["db_out"], np.abs(g1["db_out"]), rtol=1e-12)
+    np.testing.assert_allclose(a1["dW_out"], np.abs(g1["dW_out"]), rtol=1e-12)
