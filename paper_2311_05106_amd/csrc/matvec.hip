@@ -628,6 +628,98 @@ __global__ void mv_reduce_f32_k(const float* __restrict__ part, int32_t chunks, 
   }
 }
 
+// The same sums with 16-byte loads, for 8-column-aligned partial rows
+// (n_post a multiple of 8, 16-byte-aligned part and y).  A lane holds 8
+// consecutive columns and every fourth chunk: lanes l, l + 16, l + 32, l + 48
+// of a wave take chunks q, q + 4, ... (q = l / 16) of the same 8 columns, so
+// one load instruction fetches four 256-byte runs and a lane has all its
+// chunk loads in flight at once (8 for 32 chunks).  The four lanes' sums are
+// combined by two lane exchanges, ((q0 + q1) + (q2 + q3)): a fixed order,
+// so repeated calls give the same bits.  Workgroup b takes 512 columns of
+// the 8-aligned range that starts at or before tile b mod n_tiles (the
+// scatter's tile-to-workgroup order, so partials are read on the XCD that
+// wrote them).
+constexpr int kRedThreads = 256;
+constexpr int kRedCols = kRedThreads / 4 * 8;  // columns per workgroup
+constexpr int kRedLoads = 8;                   // chunk loads in flight per lane
+// used from 16 chunks up: with fewer (two or fewer loads per lane) the
+// two-column kernels above measured faster
+constexpr int kRedMinChunks = 16;
+
+__host__ __device__ inline int32_t reduce_slices(int32_t tile) { return (tile + 7 + kRedCols - 1) / kRedCols; }
+
+template <bool COUNTS>
+__global__ void __launch_bounds__(kRedThreads) mv_reduce_wide_k(const void* __restrict__ part, int32_t chunks,
+                                                                  int32_t n_post, float w, float* __restrict__ y,
+                                                                  int32_t tile, int32_t n_tiles) {
+  const int32_t t = (int32_t)blockIdx.x % n_tiles, sl = (int32_t)blockIdx.x / n_tiles;
+  const int32_t start = (int32_t)(((int64_t)t * tile) & ~7ll);
+  const int32_t end = t == n_tiles - 1 ? n_post : (int32_t)(((int64_t)(t + 1) * tile) & ~7ll);
+  const int l = lane_id(), q = l >> 4;
+  const int32_t col = start + sl * kRedCols + ((int32_t)threadIdx.x / kWave * 16 + (l & 15)) * 8;
+  const bool act = col < end;  // every lane takes part in the exchanges
+  if constexpr (COUNTS) {
+    uint32_t s[8] = {};
+    if (act) {
+      const uint16_t* p = reinterpret_cast<const uint16_t*>(part) + col;
+      for (int c0 = q; c0 < chunks; c0 += 4 * kRedLoads) {
+        // kRedLoads loads issued back to back (chunks past the end re-read
+        // the last one and are dropped), then summed
+        uint4 v[kRedLoads];
+#pragma unroll
+        for (int i = 0; i < kRedLoads; ++i)
+          v[i] = *reinterpret_cast<const uint4*>(p + (size_t)min(c0 + 4 * i, chunks - 1) * n_post);
+#pragma unroll
+        for (int i = 0; i < kRedLoads; ++i) {
+          if (c0 + 4 * i >= chunks) v[i] = make_uint4(0u, 0u, 0u, 0u);
+          s[0] += v[i].x & 0xFFFFu; s[1] += v[i].x >> 16; s[2] += v[i].y & 0xFFFFu; s[3] += v[i].y >> 16;
+          s[4] += v[i].z & 0xFFFFu; s[5] += v[i].z >> 16; s[6] += v[i].w & 0xFFFFu; s[7] += v[i].w >> 16;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      s[i] += (uint32_t)__shfl_xor((int)s[i], 16, kWave);
+      s[i] += (uint32_t)__shfl_xor((int)s[i], 32, kWave);
+    }
+    if (act && q == 0) {
+      float4* o = reinterpret_cast<float4*>(y + col);
+      o[0] = make_float4((float)s[0] * w, (float)s[1] * w, (float)s[2] * w, (float)s[3] * w);
+      o[1] = make_float4((float)s[4] * w, (float)s[5] * w, (float)s[6] * w, (float)s[7] * w);
+    }
+  } else {
+    float s[8] = {};
+    if (act) {
+      const float* p = reinterpret_cast<const float*>(part) + col;
+      for (int c0 = q; c0 < chunks; c0 += 4 * kRedLoads) {
+        float4 a[kRedLoads], b[kRedLoads];
+#pragma unroll
+        for (int i = 0; i < kRedLoads; ++i) {
+          const float* r = p + (size_t)min(c0 + 4 * i, chunks - 1) * n_post;
+          a[i] = *reinterpret_cast<const float4*>(r);
+          b[i] = *reinterpret_cast<const float4*>(r + 4);
+        }
+#pragma unroll
+        for (int i = 0; i < kRedLoads; ++i) {
+          if (c0 + 4 * i >= chunks) a[i] = b[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+          s[0] += a[i].x; s[1] += a[i].y; s[2] += a[i].z; s[3] += a[i].w;
+          s[4] += b[i].x; s[5] += b[i].y; s[6] += b[i].z; s[7] += b[i].w;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      s[i] += __shfl_xor(s[i], 16, kWave);
+      s[i] += __shfl_xor(s[i], 32, kWave);
+    }
+    if (act && q == 0) {
+      float4* o = reinterpret_cast<float4*>(y + col);
+      o[0] = make_float4(s[0], s[1], s[2], s[3]);
+      o[1] = make_float4(s[4], s[5], s[6], s[7]);
+    }
+  }
+}
+
 // Batched products: Y[b][k] = (w *) sum_c part[c][b][k] in chunk order, part
 // [chunks][batch][n_post] (16-bit counts or FP32 sums); blockIdx.y = b, two
 // consecutive columns per thread.
@@ -946,6 +1038,14 @@ static bp_status launch_scatter(const MvArgs& a, const MvPlan& p, hipStream_t st
 static bp_status finish_partials(const MvPlan& p, bool homo, void* ws, int32_t n_post, float w, float* y,
                                  hipStream_t st) {
   if (p.chunks <= 1 || n_post == 0) return BP_OK;
+  if (p.chunks >= kRedMinChunks && (n_post & 7) == 0 &&
+      ((reinterpret_cast<uintptr_t>(ws) | reinterpret_cast<uintptr_t>(y)) & 15) == 0) {
+    const int g = p.n_tiles * reduce_slices(p.tile);
+    if (homo) mv_reduce_wide_k<true><<<g, kRedThreads, 0, st>>>(ws, p.chunks, n_post, w, y, p.tile, p.n_tiles);
+    else mv_reduce_wide_k<false><<<g, kRedThreads, 0, st>>>(ws, p.chunks, n_post, w, y, p.tile, p.n_tiles);
+    BP_LAUNCHED("mv_reduce_wide_k");
+    return BP_OK;
+  }
   const int g = p.n_tiles * ((p.tile + 511) / 512);
   if (homo) mv_reduce_counts_k<<<g, 256, 0, st>>>((const uint16_t*)ws, p.chunks, n_post, w, y, p.tile, p.n_tiles);
   else mv_reduce_f32_k<<<g, 256, 0, st>>>((const float*)ws, p.chunks, n_post, y, p.tile, p.n_tiles);
