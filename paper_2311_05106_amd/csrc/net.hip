@@ -512,6 +512,7 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
   // the previous step over all sources, -1 if a wait gave up.
   auto push_gather = [&](int par, uint32_t tag) -> int {
     const uint32_t t4 = tag & 15u;
+    int sp = 0;  // spikes of the polled source (lanes h == 0)
     // add the entries of one target-line word to the counters
     auto apply = [&](uint64_t v, int nmax) {
       const int n = min(line_n(v), nmax);
@@ -548,7 +549,7 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
         apply(wb, 4);
         if (h == 0) {
           const int tc = tline_tc(wa);
-          atomicAdd(&sh.acnt, tline_spikes(wa));
+          sp = tline_spikes(wa);
           if (tc == 31) {
             sh.fb_src[atomicAdd(&sh.fb_cnt, 1)] = src;
           } else if (tc > 14) {  // words beyond the polled ones
@@ -575,6 +576,12 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
           }
         }
       }
+    }
+    // the step's spike count is reported by workgroup 0 only: one LDS atomic
+    // per wave after a DPP sum (no same-address atomics across the lanes)
+    if (w == 0 && L.counts) {
+      const int tot = wave_incl_scan(sp);
+      if (lane_id() == kWave - 1 && tot != 0) atomicAdd(&sh.acnt, tot);
     }
     __syncthreads();
     if (sh.abort_flag) return -1;
