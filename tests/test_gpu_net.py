@@ -179,6 +179,26 @@ def test_run_batch_equals_solo_runs(bp):
         assert net.info().step == steps[i]
 
 
+def test_run_batch_of_target_exchange_nets(bp):
+    # a batch whose nets all push their spikes as targets (regenerated rows of
+    # one post block on several workgroups): COBA and CUBA nets side by side
+    # in one launch, each against the oracle
+    cases = [(20000, 80 / 20000, 0, 8), (30000, 80 / 30000, 1, 12), (12000, 0.02, 0, 6)]
+    steps = [260, 150, 200]
+    nets, refs = [], []
+    for i, (n, p, model, mw) in enumerate(cases):
+        P, net, _, _ = make(bp, n, p, O.CONN_JIT, 0, seed=40 + i, model=model, max_wgs=mw)
+        assert net.info().n_wg > 1
+        _, c_ref, ev = O.net_run(P, O.NetState(P), steps[i], None, None)
+        nets.append(net)
+        refs.append((c_ref, ev))
+    counts = [torch.empty(s, dtype=torch.int32, device="cuda") for s in steps]
+    bp.run_batch(nets, steps, counts)
+    for i, net in enumerate(nets):
+        np.testing.assert_array_equal(counts[i].cpu().numpy(), refs[i][0])
+        assert int(net.events().item()) == refs[i][1]
+
+
 @pytest.mark.parametrize("block", [2560, 0])
 def test_large_jit_net_first_steps(bp, block):
     # 400k neurons (320k E / 80k I), p = 80/N, post blocks of 2560 (spike ids
