@@ -815,35 +815,42 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
         ci[i] = sh.cI[k];
       }
     }
+    // (the model and the optional inputs and outputs are fixed for the whole
+    // launch: the common case, COBA without external current or raster, is
+    // compiled with them as constants)
+    auto update = [&](auto coba, auto has_iext, auto has_raster) {
 #pragma unroll
-    for (int i = 0; i < kNPT; ++i) {
-      const int k = i * kNetThreads + tid;
-      if (k < R) {
-        const float xe = (float)ce[i] * sh.kc[kcWe];
-        const float xi = (float)ci[i] * sh.kc[kcWi];
-        ge[i] = ge[i] * sh.kc[kcDe] + xe;
-        gi[i] = gi[i] * sh.kc[kcDi] + xi;
-        bool spk = false;
-        if (ref[i] > 0) {
-          ref[i] -= 1;
-        } else {
-          float ix = sh.kc[kcIext];
-          if (iext) ix = ix + as_global(iext)[lo + k];
-          float I;
-          if (N.model == 0) I = ge[i] * (sh.kc[kcEe] - V[i]) + gi[i] * (sh.kc[kcEi] - V[i]) + ix;
-          else I = ge[i] + gi[i] + ix;
-          float v = V[i] + sh.kc[kcA] * ((sh.kc[kcVrest] - V[i]) + sh.kc[kcR] * I);
-          if (v > sh.kc[kcVth]) {
-            spk = true;
-            v = sh.kc[kcVreset];
-            ref[i] = N.ref_steps;
+      for (int i = 0; i < kNPT; ++i) {
+        const int k = i * kNetThreads + tid;
+        if (k < R) {
+          const float xe = (float)ce[i] * sh.kc[kcWe];
+          const float xi = (float)ci[i] * sh.kc[kcWi];
+          ge[i] = ge[i] * sh.kc[kcDe] + xe;
+          gi[i] = gi[i] * sh.kc[kcDi] + xi;
+          bool spk = false;
+          if (ref[i] > 0) {
+            ref[i] -= 1;
+          } else {
+            float ix = sh.kc[kcIext];
+            if (has_iext) ix = ix + as_global(iext)[lo + k];
+            float I;
+            if (coba) I = ge[i] * (sh.kc[kcEe] - V[i]) + gi[i] * (sh.kc[kcEi] - V[i]) + ix;
+            else I = ge[i] + gi[i] + ix;
+            float v = V[i] + sh.kc[kcA] * ((sh.kc[kcVrest] - V[i]) + sh.kc[kcR] * I);
+            if (v > sh.kc[kcVth]) {
+              spk = true;
+              v = sh.kc[kcVreset];
+              ref[i] = N.ref_steps;
+            }
+            V[i] = v;
           }
-          V[i] = v;
+          if (spk) sbits |= 1u << i;
+          if (has_raster) as_global(L.raster)[(size_t)s * N.n + lo + k] = spk ? 1 : 0;
         }
-        if (spk) sbits |= 1u << i;
-        if (L.raster) as_global(L.raster)[(size_t)s * N.n + lo + k] = spk ? 1 : 0;
       }
-    }
+    };
+    if (N.model == 0 && !iext && !L.raster) update(std::true_type{}, std::false_type{}, std::false_type{});
+    else update(N.model == 0, iext != nullptr, L.raster != nullptr);
     // compaction of the own spikes: one LDS atomic per wave and neuron slot
     // reserves the wave's positions (the list order carries no meaning: every
     // reader accumulates integer counts)
