@@ -39,6 +39,8 @@ constexpr int kIdCap = kSweep + 4096;              // firing rows listed before 
 constexpr int kTileMax = 16384;                    // LDS tile columns (64 KB)
 constexpr int kGroup = 16;                         // lanes streaming one CSR segment
 constexpr int kSegLoads = 10;                      // loads per lane and segment pass (160 entries)
+constexpr int kMinChunkRows = 256;                 // row chunks of small operators
+constexpr int64_t kSmallPartialBytes = 4 << 20;    // partials those may use
 
 enum MvMode {
   kCsrHomo = 0, kCsrData = 1, kJitHomo = 2, kJitWeighted = 3, kJitVec = 4, kJitMat = 5,
@@ -872,10 +874,24 @@ struct MvPlan {
 // chunks as keep tiles x chunks within the compute units, each at least a
 // quarter sweep of rows.  Chunk starts are multiples of 16 (aligned spike
 // loads); 16-bit partial counts cap homogeneous chunks at 65520 rows.
-static void set_chunks(MvPlan& p, int32_t n_pre, bool homo, int32_t n_post, bool packed = false) {
+static void set_chunks(MvPlan& p, int32_t n_pre, bool homo, int32_t n_post, bool packed = false,
+                       bool small_chunks = false) {
   const int32_t cus = device_cu_count();
-  int32_t want = max(1, cus / p.n_tiles);
-  want = max(1, min(want, (n_pre + kSweep / 4 - 1) / (kSweep / 4)));
+  const int32_t cap = max(1, cus / p.n_tiles);
+  int32_t want = max(1, min(cap, (n_pre + kSweep / 4 - 1) / (kSweep / 4)));
+  // products on dense float vectors (every row listed) over few rows (a few
+  // thousand): chunks of kMinChunkRows, so that more than a handful of
+  // workgroups share the rows (one workgroup streaming 4000 listed rows
+  // takes 30 batches of dependent loads one after another), while the
+  // partials stay within kSmallPartialBytes; spike products over few rows
+  // list few rows and keep one chunk (no second launch)
+  if (want < 4 && small_chunks) {
+    const int64_t by_bytes = kSmallPartialBytes / ((int64_t)max(n_post, 1) * 4);
+    int64_t w2 = (n_pre + kMinChunkRows - 1) / kMinChunkRows;
+    if (w2 > cap) w2 = cap;
+    if (w2 > by_bytes) w2 = by_bytes;
+    if (w2 > want) want = (int32_t)w2;
+  }
   // 16-bit partial counts (and the batched products' packed 16-bit LDS
   // counts, even with one chunk) hold at most 65520 rows' worth per column
   if (homo && (want > 1 || packed)) want = max(want, (n_pre + 65519) / 65520);
@@ -909,7 +925,7 @@ static MvPlan plan_csr(const bp_csr* m, bool vec_input = false) {
     p.ws = (size_t)(m->n_post > 0 ? m->n_post : 1) * sizeof(uint32_t);
     return p;
   }
-  set_chunks(p, m->n_pre, !vec_input && m->data == nullptr, m->n_post);
+  set_chunks(p, m->n_pre, !vec_input && m->data == nullptr, m->n_post, false, vec_input);
   // 16-bit partial counts need at most one entry per row and column
   if (!vec_input && !m->data && !m->sorted && p.chunks > 1) {
     p.atomic_path = true;
@@ -919,7 +935,8 @@ static MvPlan plan_csr(const bp_csr* m, bool vec_input = false) {
 }
 
 // counts: homogeneous weights summed as integer counts (event input only).
-static MvPlan plan_jit(const bp_jit_conn* c, bool counts) {
+// vec: the product on dense float vectors (every row listed).
+static MvPlan plan_jit(const bp_jit_conn* c, bool counts, bool vec = false) {
   MvPlan p{};
   if (c->block > 0 && c->block <= kTileMax && c->n_post > c->block) {
     p.tile = c->block;  // one block per tile: every generated target lands in the tile
@@ -930,7 +947,7 @@ static MvPlan plan_jit(const bp_jit_conn* c, bool counts) {
   }
   p.n_tiles = (int32_t)(((int64_t)c->n_post + p.tile - 1) / p.tile);
   if (p.n_tiles < 1) p.n_tiles = 1;
-  set_chunks(p, c->n_pre, counts, c->n_post);
+  set_chunks(p, c->n_pre, counts, c->n_post, false, vec);
   return p;
 }
 
@@ -938,12 +955,12 @@ static MvPlan plan_jit(const bp_jit_conn* c, bool counts) {
 // workgroup while the LDS tile holds them (tile * mg <= kTileMax), column
 // groups on blockIdx.y, row chunks sized for tiles x groups workgroups.
 static MvPlan plan_jit_mat(const bp_jit_conn* c, int32_t m, int32_t* mg, int32_t* groups) {
-  MvPlan p = plan_jit(c, false);
+  MvPlan p = plan_jit(c, false, true);
   *mg = max(1, min(min(kMatCols, kTileMax / p.tile), m));
   *groups = (m + *mg - 1) / *mg;
   const int32_t nt = p.n_tiles;
   p.n_tiles = nt * *groups;
-  set_chunks(p, c->n_pre, false, c->n_post);
+  set_chunks(p, c->n_pre, false, c->n_post, false, true);
   p.n_tiles = nt;
   p.ws = p.chunks > 1 ? (size_t)p.chunks * c->n_post * m * sizeof(float) : 0;
   return p;
@@ -1326,7 +1343,7 @@ bp_status bp_jit_conn_matvec(const bp_jit_conn* c, const uint8_t* events, float*
 
 size_t bp_jit_dense_ws_bytes(const bp_jit_conn* c) {
   if (!c) return 0;
-  return plan_jit(c, false).ws;
+  return plan_jit(c, false, true).ws;
 }
 
 bp_status bp_jit_conn_matvec_dense(const bp_jit_conn* c, const float* v, float* y, void* ws, size_t ws_bytes,
@@ -1337,7 +1354,7 @@ bp_status bp_jit_conn_matvec_dense(const bp_jit_conn* c, const float* v, float* 
   BP_REQUIRE(y != nullptr, "null y");
   BP_REQUIRE(c->n_pre == 0 || v != nullptr, "null v");
   hipStream_t st = as_stream(stream);
-  const MvPlan p = plan_jit(c, false);
+  const MvPlan p = plan_jit(c, false, true);
   BP_REQUIRE(ws_bytes >= p.ws && (p.ws == 0 || ws != nullptr), "workspace too small (%zu < %zu)", ws_bytes, p.ws);
   MvArgs a{};
   a.jit = *c; a.vec = v; a.out = p.chunks > 1 ? ws : (void*)y; a.w = c->w0;
