@@ -113,6 +113,7 @@ __device__ __forceinline__ void group_bounds(const int32_t* __restrict__ idx, in
 struct MvShared {
   int ids[kIdCap];
   int cnt[3];  // per-sweep append counters, rotated so one barrier per sweep suffices
+  int grab;    // next listed row of the balanced JIT walks
 };
 
 // Bit q set iff byte q of v is nonzero.
@@ -494,6 +495,70 @@ __global__ void __launch_bounds__(kMvThreads) mv_scatter_k(MvArgs a) {
           prev = shfl64(pos, qb + 3);  // the pass's last position
           live = live && prev < end;
           if (__ballot(live) == 0) break;
+        }
+      } else if (a.jit.rule == kRuleUniform && B > 0 && nbt == 1 && lo == (int64_t)b_lo * B) {
+        // Balanced walks: a lane runs its (row, block) walk one generator
+        // call (four draws) at a time and, when the walk leaves the block,
+        // takes the next listed row (a wave claims rows for all its idle
+        // lanes with one LDS atomic), so lanes stay busy until the list is
+        // used up instead of each waiting for the longest walk of its wave.
+        // Targets and their indices are those of the sequential walk.
+        if (threadIdx.x == 0) sh.grab = 0;
+        __syncthreads();
+        const uint32_t b = (uint32_t)b_lo;
+        const int64_t start = (int64_t)b * B;
+        const int64_t end = hi;  // the tile is the block, clipped at n_post
+        const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+        bool act = false, more = true;
+        uint32_t j = 0, mk = 0, call = 0, m = 0;
+        int64_t pos = 0;
+        RowScale<MODE> sc;
+        DrawSeq wd(seed, kStreamW, 0u, b);
+        while (true) {
+          if (more) {
+            const uint64_t need = __ballot(!act);
+            if (need) {
+              const int nn = (int)__popcll(need);
+              const int leader = __ffsll((long long)need) - 1;
+              int base = 0;
+              if (lane_id() == leader) base = atomicAdd(&sh.grab, nn);
+              base = __builtin_amdgcn_readlane(base, leader);
+              if (!act) {
+                const int it = base + mask_rank(need);
+                if (it < items) {
+                  const uint32_t id = (uint32_t)sh.ids[it];
+                  j = kB ? id >> 8 : id;
+                  mk = kB ? id & 0xFFu : 0u;
+                  sc.load(a, j, c0, mg);
+                  wd = DrawSeq(seed, kStreamW, j, b);
+                  call = 0;
+                  m = 0;
+                  act = true;
+                }
+              }
+              if (base + nn >= items) more = false;
+            }
+          }
+          if (__ballot(act) == 0) break;
+          if (act) {
+            const Words4 w = philox10(j, b, call, kStreamConn, k0, k1);
+            const uint32_t d[4] = {w.x, w.y, w.z, w.w};
+            const int u0 = call == 0 ? 2 : 0;
+            if (call == 0) {  // draws 0 and 1 give the first target, not gaps
+              const uint32_t ra = below(d[0], K), rb = below(d[1], K + 1u);
+              pos = start + (int64_t)(ra < rb ? ra : rb);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              if (u >= u0 && pos < end) {
+                jit_put<MODE>(acc, (int)(pos - lo), width, mk, sc, wd, wkind, w0, w1, m, mg);
+                ++m;
+                pos += 1 + (int64_t)below(d[u], K);
+              }
+            }
+            ++call;
+            if (pos >= end) act = false;
+          }
         }
       } else
       for (int it = threadIdx.x; it < items; it += kMvThreads) {
