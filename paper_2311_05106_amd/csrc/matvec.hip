@@ -20,11 +20,12 @@
 //   group at once (40 loads in flight per lane for counts, the next rows'
 //   bounds fetched ahead), so a wave reads four segments per instruction,
 //   coalesced.
-//   JIT rows are regenerated per (row, block) by one lane each, or by four
-//   lanes (one generator call each, positions by a quad prefix sum) when a
-//   pass lists at most 256 rows; the tile is one block, so no lane generates
-//   targets outside its tile, and with enough blocks to cover the chip no
-//   row chunks (and no partials) are used.
+//   JIT rows are regenerated per (row, block) by one lane each (a lane whose
+//   walk leaves the block takes the next listed row, so the lanes of a wave
+//   do not wait for its longest walk), or by four lanes (one generator call
+//   each, positions by a quad prefix sum) when a pass lists at most 256
+//   rows; the tile is one block, so no lane generates targets outside its
+//   tile.
 #include <mutex>
 
 #include "bp_device.h"
