@@ -885,10 +885,9 @@ __global__ void jit_backward_k(bp_jit_conn c, const uint8_t* __restrict__ ev, co
     const uint64_t seed = c.seed;
     const int32_t n_post = c.n_post, wkind = c.wkind;
     const float w0 = c.w0, w1 = c.w1;
-    auto term = [&](DrawSeq& wd, int32_t pos, uint32_t m) {
+    auto term_g = [&](DrawSeq& wd, float g, uint32_t m) {
       float unit;
       const float wjk = jit_weight(wd, wkind, w0, w1, m, &unit);
-      const float g = dy[pos];
       acc += wjk * g;
       if (on) {
         // d w / d w0 and d w / d w1: (1, z) normal, (1 - u, u) uniform, (1, 0) homogeneous
@@ -896,7 +895,58 @@ __global__ void jit_backward_k(bp_jit_conn c, const uint8_t* __restrict__ ev, co
         g1 += (wkind == kWHomo ? 0.f : unit) * g;
       }
     };
-    if (c.rule == kRuleFixedDegree) {
+    auto term = [&](DrawSeq& wd, int32_t pos, uint32_t m) { term_g(wd, dy[pos], m); };
+    if (c.rule == kRuleUniform || c.rule == kRuleGeometric) {
+      // gap walks: one generator call (four draws) at a time, the dy loads
+      // of its up to four targets issued together before any is used (one
+      // load at a time left each lane waiting a cache round trip per
+      // target); targets, their order and indices are the walk's
+      const bool geo = c.rule == kRuleGeometric;
+      const float inv_rate = c.geo_inv_rate;
+      const uint32_t K = (uint32_t)c.max_gap;
+      const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+      const int32_t nb = c.block > 0 ? (int32_t)(((int64_t)n_post + c.block - 1) / c.block) : 1;
+      for (int32_t b = q; b < nb; b += LPR) {
+        DrawSeq wd(seed, kStreamW, (uint32_t)j, (uint32_t)b);
+        const int64_t start = c.block > 0 ? (int64_t)b * c.block : 0;
+        const int64_t end = c.block > 0 && start + c.block < n_post ? start + c.block : n_post;
+        int64_t pos = 0;
+        uint32_t m = 0;
+        for (uint32_t call = 0;; ++call) {
+          const Words4 w = philox10((uint32_t)j, (uint32_t)b, call, kStreamConn, k0, k1);
+          const uint32_t d[4] = {w.x, w.y, w.z, w.w};
+          int u0 = 0;
+          if (call == 0) {  // the first target: draw 0 (geometric), draws 0 and 1 in a block, draw 0 in a whole row
+            if (geo) {
+              pos = start + (int64_t)geo_gap(d[0], inv_rate) - 1;
+              u0 = 1;
+            } else if (c.block > 0) {
+              const uint32_t ra = below(d[0], K), rb = below(d[1], K + 1u);
+              pos = start + (int64_t)(ra < rb ? ra : rb);
+              u0 = 2;
+            } else {
+              pos = (int64_t)below(d[0], K);
+              u0 = 1;
+            }
+          }
+          int32_t tp[4];
+          bool tv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            tv[u] = u >= u0 && pos < end;
+            tp[u] = tv[u] ? (int32_t)pos : 0;
+            if (tv[u]) pos += geo ? (int64_t)geo_gap(d[u], inv_rate) : 1 + (int64_t)below(d[u], K);
+          }
+          float gy[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) gy[u] = tv[u] ? dy[tp[u]] : 0.f;
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (tv[u]) term_g(wd, gy[u], m++);
+          if (pos >= end) break;
+        }
+      }
+    } else if (c.rule == kRuleFixedDegree) {
       const Words4 key = fd_keys(seed, (uint32_t)j);
       const uint32_t fb = fd_bits(n_post);
       const int32_t k = c.degree < n_post ? c.degree : n_post;
