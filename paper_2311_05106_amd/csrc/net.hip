@@ -441,6 +441,29 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
         if constexpr (RULES) gen_block(ConnGen{seed, K, N.n, B, N.rule, N.inv_rate, N.degree}, j, b, lo, hi, add);
         else gen_block_uniform(seed, K, N.n, B, j, b, lo, hi, add);
       }
+    } else if (N.n_wg == 1) {
+      // one workgroup (every column is its own): wave w streams rows w,
+      // w + 16, ... of the listed neurons, its lanes over the entries, two
+      // loads per lane in flight; no scan of the row lengths
+      for (int r = wave; r < nact; r += kNetWaves) {
+        const int32_t j = sh.ids[r];
+        if ((uint32_t)j >= (uint32_t)N.n) continue;
+        const int32_t st = as_global(N.indptr)[j], en = as_global(N.indptr)[j + 1];
+        uint32_t* cnt = j < N.n_exc ? sh.cE : sh.cI;
+        for (int32_t e0 = st; e0 < en; e0 += 2 * kWave) {
+          const int32_t ea = e0 + lane_id(), eb = ea + kWave;
+          const int32_t ca = ea < en ? as_global(N.indices)[ea] : -1;
+          const int32_t cb = eb < en ? as_global(N.indices)[eb] : -1;
+          if (ca >= lo && ca < hi) {
+            atomicAdd(&cnt[ca - lo], 1u);
+            ++ev_local;
+          }
+          if (cb >= lo && cb < hi) {
+            atomicAdd(&cnt[cb - lo], 1u);
+            ++ev_local;
+          }
+        }
+      }
     } else {
       int total = 0;
       for (int base = 0; base < nact; base += kNetThreads) {
@@ -448,10 +471,7 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
         int st = 0, len = 0;
         if (i < nact && (uint32_t)sh.ids[i] < (uint32_t)N.n) {
           const int32_t j = sh.ids[i];
-          if (N.n_wg == 1) {
-            st = as_global(N.indptr)[j];
-            len = as_global(N.indptr)[j + 1] - st;
-          } else if (N.blkptr) {
+          if (N.blkptr) {
             const auto* bp = as_global(N.blkptr) + (size_t)j * (N.nb + 1);
             st = bp[b_lo];
             len = bp[b_hi + 1] - st;
