@@ -169,22 +169,25 @@ def full_csr():
     return O.csr_build(0, K, n, n, 0)
 
 
-@pytest.mark.parametrize("frac", [0.001, 0.01, 0.1])
-def test_event_csr_full_operator_size(bp, full_csr, frac):
+@pytest.mark.parametrize("frac,tw", [(0.001, 8192), (0.01, 8192), (0.1, 8192), (0.01, 12500), (0.1, 12500)])
+def test_event_csr_full_operator_size(bp, full_csr, frac, tw):
     # n_pre = n_post = 1e5, p = 0.01, the operator sweep's shape; whole output
-    # checked against the oracle's CSR and integer counts.
+    # checked against the oracle's CSR and integer counts.  Tiles of 12500
+    # columns (the sweep's) do not start on multiples of 8: the row-chunk sum
+    # over 8-column groups then takes ranges that start up to 7 columns before
+    # each tile.
     n = 100_000
     ip, ix = full_csr
     e = S.events(n, frac, 7)
     cnt = O.event_csr_counts(ip, ix, n, e)
     ipt, ixt = _to(ip), _to(ix)
-    tp = bp.csr_tile_index(ipt, ixt, n, 8192)
-    y = bp.event_csr_matvec(ipt, ixt, None, 0.5, n, _to(e), tile_ptr=tp, tile_width=8192)
+    tp = bp.csr_tile_index(ipt, ixt, n, tw)
+    y = bp.event_csr_matvec(ipt, ixt, None, 0.5, n, _to(e), tile_ptr=tp, tile_width=tw)
     np.testing.assert_array_equal(y.cpu().numpy(), cnt.astype(np.float32) * np.float32(0.5))
     data = S.hetero_data(ix.size, 1)
     ref = O.event_csr_matvec(ip, ix, data, 0.0, n, e)
     scale = O.event_csr_matvec(ip, ix, np.abs(data), 0.0, n, e)
-    yh = bp.event_csr_matvec(ipt, ixt, _to(data), 0.0, n, _to(e), tile_ptr=tp, tile_width=8192)
+    yh = bp.event_csr_matvec(ipt, ixt, _to(data), 0.0, n, _to(e), tile_ptr=tp, tile_width=tw)
     _tol_check(yh.cpu().numpy(), ref, scale, name="hetero-full")
 
 
