@@ -468,6 +468,11 @@ __device__ __forceinline__ void st_coh128(__amdgpu_buffer_rsrc_t r, uint32_t off
 }
 // Wait until every vector memory operation this wave issued has completed
 // (s_waitcnt vmcnt(0); stores are counted by vmcnt on gfx9-family targets).
-__device__ __forceinline__ void vm_drain() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+// The compiler barriers keep the memory operations on their own side.
+__device__ __forceinline__ void vm_drain() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 
 }  // namespace bp

@@ -30,9 +30,9 @@
 // instead: the writer generates the whole row of each of its spikes (a wave
 // per spike draws 256 gaps at once, one Philox call per lane, and places
 // them by a wave prefix sum), sorts the targets by owning workgroup, and
-// pushes up to 30 per line (13-bit entries); a line with more says so and
-// the reader regenerates that writer's targets from its record.  Readers add
-// the targets to their counters directly.
+// pushes up to 30 per line (13-bit entries, 14 in the polled 32 bytes); a
+// line with more says so and the reader regenerates that writer's targets
+// from its record.  Readers add the targets to their counters directly.
 // Several nets run in one launch (continuous batching): the grid is the
 // concatenation of their workgroup ranges and each net exchanges records only
 // among its own workgroups.
@@ -56,7 +56,8 @@ constexpr int kRangeMax = kNetThreads * kNPT;  // neurons per workgroup
 constexpr int kIdBatch = 4096;                 // firing rows staged per pass
 constexpr int kMaxWgPerNet = 512;  // one gathering thread per source
 constexpr int kTgtLine = 30;  // targets a line of the target exchange carries
-constexpr int kInbox = 8;     // its words: 2 targets in word 0, 4 in each further word
+constexpr int kInbox = 4;     // its polled words: 2 targets in word 0, 4 in each further word
+constexpr int kExtra = 8;     // its further words: 2 targets each (targets 14..29)
 constexpr int kLine = 4;      // words per inbox line of the spike-id exchange (32 bytes)
 constexpr int kLineIds = 15;  // ids such a line carries: 3 in word 0, 4 in each of words 1..3
 constexpr int kMaxBatch = 48;
@@ -71,7 +72,7 @@ struct NetDev {
   float w_exc, w_inh, de, di, a, v_rest, v_th, v_reset, e_exc, e_inh, r, i_ext;
   int32_t n_wg, range;
   int32_t push;  // several workgroups exchange targets (JIT, one post block), else spike ids
-  int32_t ibw;   // words per inbox line: kInbox (targets) or kLine (spike ids)
+  int32_t ibw;   // words per inbox line: kInbox + kExtra (targets) or kLine (spike ids)
   float* V;
   float* ge;
   float* gi;
@@ -80,7 +81,8 @@ struct NetDev {
   const int32_t* indices;
   const int32_t* blkptr;  // [n][nb + 1] block index of the stored rows, or null
   uint64_t* rec;          // [2][n_wg][range + 1] spike records by step parity
-  uint64_t* inbox;        // [ibw / 4 planes][2][n_wg dst][n_wg src][4] words of the lines pushed to each reader
+  uint64_t* inbox;        // [2][n_wg dst][n_wg src][4] polled words of the lines pushed to each reader,
+                          // then (target exchange) [2][n_wg dst][n_wg src][kExtra] further words
   unsigned long long* events;  // [n_wg] synaptic events delivered
   uint32_t* error;
 };
@@ -103,9 +105,12 @@ struct BatchArgs {
   NetLaunch e[kMaxBatch];
 };
 
+// input counters of the own neurons: excitatory at [k], inhibitory at
+// [kRangeMax + k], so a target-line entry (12-bit local id, bit 12 set for an
+// inhibitory source) is its own counter index
+static_assert(kRangeMax == 0x1000, "target-line entries index the counters directly");
 struct NetShared {
-  uint32_t cE[kRangeMax];
-  uint32_t cI[kRangeMax];
+  uint32_t cnt[2 * kRangeMax];
   int ids[kIdBatch];
   int own[kRangeMax];  // own spikes of this step (order of the wave appends)
   int pref[kIdBatch + 1];
@@ -135,12 +140,12 @@ __device__ __forceinline__ uint64_t* record(const NetDev& N, int par, int w) {
   return N.rec + ((size_t)par * N.n_wg + w) * (size_t)(N.range + 1);
 }
 
-// Word q of inbox line (par, dst, src).  Lines are stored in planes of 4
-// words (words 0..3 of every line, then words 4..7), so the polled first 32
-// bytes of the lines a reader scans are contiguous.
+// Word q of inbox line (par, dst, src): the 4 polled words of every line
+// first (the lines a reader scans are contiguous), then the further words.
+static_assert(kInbox == 4 && kLine == 4, "the polled part of a line is 4 words in both exchanges");
 __device__ __forceinline__ uint64_t* iword(const NetDev& N, int par, int dst, int src, int q) {
-  const size_t plane = (size_t)2 * N.n_wg * N.n_wg * 4;
-  return N.inbox + (size_t)(q >> 2) * plane + ((((size_t)par * N.n_wg + dst) * N.n_wg + src) * 4 + (q & 3));
+  const size_t line = ((size_t)par * N.n_wg + dst) * N.n_wg + src;
+  return q < 4 ? N.inbox + line * 4 + q : N.inbox + (size_t)2 * N.n_wg * N.n_wg * 4 + line * kExtra + (q - 4);
 }
 
 // Spike-id inbox line, 4 words of 64 bits, each written and read with its own
@@ -178,23 +183,36 @@ __device__ __forceinline__ uint64_t line_word(uint32_t tag, int q, int total, Id
 __device__ __forceinline__ uint32_t line_off(const NetDev& N, int par, int dst, int src, int h) {
   return (uint32_t)(((((size_t)par * N.n_wg + dst) * N.n_wg + src) * kLine + 2 * h) * 8);
 }
+// Byte offset of further words 2 pq and 2 pq + 1 of target line (par, dst, src).
+__device__ __forceinline__ uint32_t xline_off(const NetDev& N, int par, int dst, int src, int pq) {
+  const size_t line = ((size_t)par * N.n_wg + dst) * N.n_wg + src;
+  return (uint32_t)(((size_t)2 * N.n_wg * N.n_wg * 4 + line * kExtra + 2 * pq) * 8);
+}
 __device__ __forceinline__ uint32_t inbox_bytes(const NetDev& N) {
   return (uint32_t)(2 * (size_t)N.n_wg * N.n_wg * N.ibw * 8);
 }
 
-// Target inbox line (target exchange), 8 words of which the first 4 are
-// always written and polled (two 16-byte halves), the next ones only when
-// the targets need them; every word carries the tag as above:
+// Target inbox line (target exchange): 4 polled words, all written every step
+// (two 16-byte halves), each carrying the 4-bit tag as above:
 //   bits 63..60  tag, bits 59..57  entries in this word
 //   word 0: bits 56..52 targets in the line (0..30; 31: more, the reader
 //           regenerates them from the source's spike record), bits 51..39
 //           the source's spike count, bits 25..0 entries 0..1;
-//   words q >= 1: bits 51..0 entries 4q - 2 .. 4q + 1
+//   words 1..3: bits 51..0 entries 4q - 2 .. 4q + 1 (targets up to 13);
+// then up to kExtra further words, written only when the line needs them:
+//   bits 63..32  the whole step tag, bits 27..26 entries in this word,
+//   bits 25..0   entries 14 + 2 (q - 4) and the next.
+// A further word can still hold a line of many steps earlier (it is not
+// rewritten every step), so a 4-bit tag could match it before the new word
+// lands; the whole tag cannot.
 // An entry is 13 bits: local target id | 0x1000 if the source is inhibitory.
 __device__ __forceinline__ int tline_tc(uint64_t v) { return (int)((v >> 52) & 31u); }
 __device__ __forceinline__ int tline_spikes(uint64_t v) { return (int)((v >> 39) & 0x1FFFu); }
 __device__ __forceinline__ int tline_first(int q) { return q == 0 ? 0 : 4 * q - 2; }
-__device__ __forceinline__ int tline_words(int c) { return c <= 2 ? 1 : 1 + (c - 2 + 3) / 4; }
+constexpr int kPolledTargets = 14;
+// further words a line of ce targets needs
+__device__ __forceinline__ int tline_extra(int ce) { return ce > kPolledTargets ? (ce - kPolledTargets + 1) / 2 : 0; }
+constexpr uint64_t kNoTag = 0xFFFFFFFFull << 32;  // a further word no step can take
 // Word q for c targets of which the line carries `ce` (c, or 0 if c > 30);
 // ent(i) is called for i < 30 only.
 template <class Ent>
@@ -209,6 +227,16 @@ __device__ __forceinline__ uint64_t tline_word(uint32_t tag, int q, int c, int c
 #pragma unroll
   for (int i = 0; i < 4; ++i) v |= (uint64_t)(x[i] & (i < n ? 0x1FFFu : 0u)) << (13 * i);
   return v;
+}
+
+// Further word q (0-based) of a line of ce targets: entries 14 + 2q, 15 + 2q.
+template <class Ent>
+__device__ __forceinline__ uint64_t tline_xword(uint32_t tag, int q, int ce, Ent&& ent) {
+  const int first = kPolledTargets + 2 * q;
+  const int n = max(0, min(ce - first, 2));
+  const uint32_t x0 = ent(min(first, kTgtLine - 1)) & (n > 0 ? 0x1FFFu : 0u);
+  const uint32_t x1 = ent(min(first + 1, kTgtLine - 1)) & (n > 1 ? 0x1FFFu : 0u);
+  return ((uint64_t)tag << 32) | ((uint64_t)n << 26) | ((uint64_t)x1 << 13) | x0;
 }
 
 // Load slot q of a record until it carries `tag` (bounded).
@@ -393,8 +421,8 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
     }
   }
   for (int k = tid; k < R; k += kNetThreads) {
-    sh.cE[k] = 0u;
-    sh.cI[k] = 0u;
+    sh.cnt[k] = 0u;
+    sh.cnt[kRangeMax + k] = 0u;
   }
   if (tid == 0) {
     sh.abort_flag = 0;
@@ -433,7 +461,7 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
         const uint32_t b = (uint32_t)(b_lo + it % nbt);
         const uint32_t j = (uint32_t)sh.ids[ai];
         if (j >= (uint32_t)N.n) continue;
-        uint32_t* cnt = ((int32_t)j < N.n_exc) ? sh.cE : sh.cI;
+        uint32_t* cnt = sh.cnt + ((int32_t)j < N.n_exc ? 0 : kRangeMax);
         auto add = [&](int32_t pos, uint32_t) {
           atomicAdd(&cnt[pos - lo], 1u);
           ++ev_local;
@@ -449,7 +477,7 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
         const int32_t j = sh.ids[r];
         if ((uint32_t)j >= (uint32_t)N.n) continue;
         const int32_t st = as_global(N.indptr)[j], en = as_global(N.indptr)[j + 1];
-        uint32_t* cnt = j < N.n_exc ? sh.cE : sh.cI;
+        uint32_t* cnt = sh.cnt + (j < N.n_exc ? 0 : kRangeMax);
         for (int32_t e0 = st; e0 < en; e0 += 2 * kWave) {
           const int32_t ea = e0 + lane_id(), eb = ea + kWave;
           const int32_t ca = ea < en ? as_global(N.indices)[ea] : -1;
@@ -514,7 +542,7 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
             while (r + 1 < nact && sh.pref[r + 1] <= ee) ++r;
             const int32_t col = as_global(N.indices)[sh.start[r] + (ee - sh.pref[r])];
             if (col >= lo && col < hi) {
-              atomicAdd(&((sh.ids[r] < N.n_exc) ? sh.cE : sh.cI)[col - lo], 1u);
+              atomicAdd(&sh.cnt[(sh.ids[r] < N.n_exc ? 0 : kRangeMax) + col - lo], 1u);
               ++ev_local;
             }
           }
@@ -533,18 +561,22 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
   auto push_gather = [&](int par, uint32_t tag) -> int {
     const uint32_t t4 = tag & 15u;
     int sp = 0;  // spikes of the polled source (lanes h == 0)
-    // add the entries of one target-line word to the counters
+    // add the entries of one target-line word to the counters (the writer
+    // puts only targets inside the reader's range into its line; an entry
+    // is at most 0x1FFF, inside the counters whatever it holds)
     auto apply = [&](uint64_t v, int nmax) {
       const int n = min(line_n(v), nmax);
+      ev_local += (uint32_t)n;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const uint32_t e = (uint32_t)(v >> (13 * i)) & 0x1FFFu;
-        const int32_t k = (int32_t)(e & 0xFFFu);
-        if (i < n && k < R) {
-          atomicAdd((e & 0x1000u) ? &sh.cI[k] : &sh.cE[k], 1u);
-          ++ev_local;
-        }
-      }
+      for (int i = 0; i < 4; ++i)
+        if (i < n) atomicAdd(&sh.cnt[(uint32_t)(v >> (13 * i)) & 0x1FFFu], 1u);
+    };
+    // add the entries of a further word
+    auto apply_x = [&](uint64_t x) {
+      const int n = (int)((x >> 26) & 3u);
+      ev_local += (uint32_t)n;
+      if (n > 0) atomicAdd(&sh.cnt[(uint32_t)x & 0x1FFFu], 1u);
+      if (n > 1) atomicAdd(&sh.cnt[(uint32_t)(x >> 13) & 0x1FFFu], 1u);
     };
     if (tid < 2 * N.n_wg) {
       // two lanes per source: the two 16-byte halves of the polled words 0..3
@@ -572,22 +604,28 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
           sp = tline_spikes(wa);
           if (tc == 31) {
             sh.fb_src[atomicAdd(&sh.fb_cnt, 1)] = src;
-          } else if (tc > 14) {  // words beyond the polled ones
-            const uint64_t* r = iword(N, par, w, src, 4);  // words 4.. (second plane)
-            const int nw = tline_words(tc);
-            uint64_t u[kInbox - 4];
+          } else if (tc > kPolledTargets) {  // the further words, each with the whole tag, in 16-byte pairs
+            const int nx = tline_extra(tc), np = (nx + 1) / 2;
+            uint64_t u[kExtra];
 #pragma unroll
-            for (int q = 0; q < kInbox - 4; ++q) u[q] = 4 + q < nw ? ld_coh64(&r[q]) : 0;
+            for (int pq = 0; pq < kExtra / 2; ++pq) {
+              u[2 * pq] = u[2 * pq + 1] = 0;
+              if (pq < np) ld_coh128(rs, xline_off(N, par, w, src, pq), &u[2 * pq], &u[2 * pq + 1]);
+            }
 #pragma unroll
-            for (int q = 0; q < kInbox - 4; ++q) {
-              if (4 + q < nw) {
-                uint64_t x = u[q];
-                for (uint32_t sp = 0; tag4(x) != t4 && sp <= spin_limit; ++sp) {
+            for (int pq = 0; pq < kExtra / 2; ++pq) {
+              if (pq < np) {
+                uint64_t a = u[2 * pq], b = u[2 * pq + 1];
+                const bool two = 2 * pq + 1 < nx;
+                for (uint32_t spin = 0; (tag_of(a) != tag || (two && tag_of(b) != tag)) && spin <= spin_limit; ++spin) {
                   __builtin_amdgcn_s_sleep(1);
-                  x = ld_coh64(&r[q]);
+                  __asm__ volatile("" ::: "memory");  // reload every pass
+                  ld_coh128(rs, xline_off(N, par, w, src, pq), &a, &b);
                 }
-                if (tag4(x) == t4) apply(x, 4);
-                else {
+                if (tag_of(a) == tag && (!two || tag_of(b) == tag)) {
+                  apply_x(a);
+                  if (two) apply_x(b);
+                } else {
                   atomicOr(N.error, 1u);
                   sh.abort_flag = 1;
                 }
@@ -640,11 +678,13 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
   const float inv_range = 1.0f / (float)N.range;
   auto emit = [&](int32_t pos, uint32_t inh) {
     if ((uint32_t)pos >= (uint32_t)N.n) return;
+    // the FP32 quotient is off by at most one workgroup; corrected by selects
     int d = (int)((float)pos * inv_range);
-    if (d * N.range > pos) --d;
-    else if ((d + 1) * N.range <= pos) ++d;
+    int loc = pos - d * N.range;
+    d = loc < 0 ? d - 1 : (loc >= N.range ? d + 1 : d);
+    loc = loc < 0 ? loc + N.range : (loc >= N.range ? loc - N.range : loc);
     const int slot = atomicAdd(&sh.dcnt[d], 1);
-    if (slot < kTgtLine) sh.lst[d][slot] = (uint16_t)((uint32_t)(pos - d * N.range) | inh);
+    if (slot < kTgtLine) sh.lst[d][slot] = (uint16_t)((uint32_t)loc | inh);
   };
   auto push_generate = [&](int total) {
     const int lane = lane_id();
@@ -762,8 +802,9 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
     }
   };
 
-  // Writer: the header of every destination's inbox line (the signal its
-  // reader polls), then the target slots (each slot carries the tag too).
+  // Writer: the two polled halves of every destination's inbox line (the
+  // signal its reader polls; every word carries the tag), then the further
+  // words of a line with more than 14 targets.
   auto push_publish = [&](int par, uint32_t tag, int total) {
     const __amdgpu_buffer_rsrc_t rs = coh_rsrc(N.inbox, inbox_bytes(N));
     for (int x = tid; x < 2 * N.n_wg; x += kNetThreads) {
@@ -775,9 +816,10 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
       const uint64_t wb = tline_word(tag, 2 * h + 1, c, ce, total, ent);
       st_coh128(rs, line_off(N, par, d, w, h), wa, wb);
       if (h == 0) {
-        uint64_t* ib = iword(N, par, d, w, 4);
-        const int nw = tline_words(ce);
-        for (int q = 4; q < nw; ++q) st_coh64(ib + (q - 4), tline_word(tag, q, c, ce, total, ent));
+        const int nx = tline_extra(ce);
+        for (int pq = 0; 2 * pq < nx; ++pq)
+          st_coh128(rs, xline_off(N, par, d, w, pq), tline_xword(tag, 2 * pq, ce, ent),
+                    tline_xword(tag, 2 * pq + 1, ce, ent));
       }
     }
   };
@@ -795,8 +837,8 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
       for (int i = 0; i < kNPT; ++i) {
         const int k = i * kNetThreads + tid;
         if (k < R) {
-          sh.cE[k] = 0u;
-          sh.cI[k] = 0u;
+          sh.cnt[k] = 0u;
+          sh.cnt[kRangeMax + k] = 0u;
         }
       }
     }
@@ -828,11 +870,11 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
       // guard (a guarded access is a branch and a wait of its own); values
       // for k >= R are never used
       if constexpr (PUSH) {  // read and clear in one LDS exchange (the next gather adds at once)
-        ce[i] = atomicExch(&sh.cE[k], 0u);
-        ci[i] = atomicExch(&sh.cI[k], 0u);
+        ce[i] = atomicExch(&sh.cnt[k], 0u);
+        ci[i] = atomicExch(&sh.cnt[kRangeMax + k], 0u);
       } else {  // cleared at the start of the next step
-        ce[i] = sh.cE[k];
-        ci[i] = sh.cI[k];
+        ce[i] = sh.cnt[k];
+        ci[i] = sh.cnt[kRangeMax + k];
       }
     }
     // (the model and the optional inputs and outputs are fixed for the whole
@@ -1016,9 +1058,12 @@ __global__ void net_init_k(const NetDev* __restrict__ Np, float v0_lo, float v0_
   }
   if (N.n_wg > 1) {
     const int64_t ib = 2 * (int64_t)N.n_wg * N.n_wg * N.ibw;
-    if (i < ib) {  // planes of [2 parities][dst][src][4 words]
+    const int64_t polled = 2 * (int64_t)N.n_wg * N.n_wg * 4;
+    if (i < polled) {  // [2 parities][dst][src][4 words]
       const bool par1 = ((i / ((int64_t)N.n_wg * N.n_wg * 4)) & 1) == 1;
       N.inbox[i] = par1 ? 0ull : (15ull << 60);  // empty set of step -1; parity 0 as of step -2
+    } else if (i < ib) {
+      N.inbox[i] = kNoTag;
     }
   }
   if (i < N.n_wg) N.events[i] = 0ull;
@@ -1065,7 +1110,7 @@ __global__ void __launch_bounds__(kNetThreads) net_set_state_k(const NetDev* __r
     for (int q = threadIdx.x; q <= N.range; q += kNetThreads) r[q] = 0xFFFFFFFFull << 32;
     if (N.n_wg > 1)  // every line as of two steps before
       for (int x = threadIdx.x; x < N.n_wg * N.ibw; x += kNetThreads)
-        *iword(N, p, x / N.ibw, w, x % N.ibw) = (uint64_t)((step - 1u) & 15u) << 60;
+        *iword(N, p, x / N.ibw, w, x % N.ibw) = x % N.ibw < 4 ? (uint64_t)((step - 1u) & 15u) << 60 : kNoTag;
   }
   if (threadIdx.x == 0) base_s = 0;
   vm_drain();  // the invalidations land before the record is rewritten below
@@ -1190,7 +1235,7 @@ static bp_status make_layout(const bp_net_desc* d, Layout* L) {
   L->off_ref = take((size_t)n * 4);
   L->off_rec = take((size_t)2 * n_wg * (range + 1) * 8);
   L->push = n_wg > 1 && d->conn == BP_CONN_JIT && d->block == 0;
-  L->ibw = L->push ? kInbox : kLine;
+  L->ibw = L->push ? kInbox + kExtra : kLine;
   L->off_inbox = n_wg > 1 ? take((size_t)2 * n_wg * n_wg * L->ibw * 8) : 0;
   L->off_events = take((size_t)n_wg * 8);
   L->off_error = take(4);
