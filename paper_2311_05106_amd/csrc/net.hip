@@ -686,6 +686,25 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
     const int slot = atomicAdd(&sh.dcnt[d], 1);
     if (slot < kTgtLine) sh.lst[d][slot] = (uint16_t)((uint32_t)loc | inh);
   };
+  // The same for a lane's four consecutive targets of a gap walk: the four
+  // destination counters are incremented back to back (one LDS round trip
+  // instead of four), then the entries stored.
+  auto emit4 = [&](int32_t p0, int32_t p1, int32_t p2, int32_t p3, uint32_t inh) {
+    const int32_t pp[4] = {p0, p1, p2, p3};
+    int dd[4], ll[4], ss[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int d = (int)((float)pp[u] * inv_range);
+      int loc = pp[u] - d * N.range;
+      dd[u] = loc < 0 ? d - 1 : (loc >= N.range ? d + 1 : d);
+      ll[u] = loc < 0 ? loc + N.range : (loc >= N.range ? loc - N.range : loc);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) ss[u] = (uint32_t)pp[u] < (uint32_t)N.n ? atomicAdd(&sh.dcnt[dd[u]], 1) : kTgtLine;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (ss[u] < kTgtLine) sh.lst[dd[u]][ss[u]] = (uint16_t)((uint32_t)ll[u] | inh);
+  };
   auto push_generate = [&](int total) {
     const int lane = lane_id();
     if constexpr (CONN == 1) {
@@ -707,14 +726,8 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
               const uint32_t g3 = min(1u + below(q.w, K), cap);
               const int s4 = (int)(g0 + g1 + g2 + g3);
               const int incl = wave_incl_scan(s4);
-              int32_t p = base + incl - s4 + (int32_t)g0;
-              emit(p, inh);
-              p += (int32_t)g1;
-              emit(p, inh);
-              p += (int32_t)g2;
-              emit(p, inh);
-              p += (int32_t)g3;
-              emit(p, inh);
+              const int32_t p = base + incl - s4 + (int32_t)g0;
+              emit4(p, p + (int32_t)g1, p + (int32_t)(g1 + g2), p + (int32_t)(g1 + g2 + g3), inh);
               base += __builtin_amdgcn_readlane(incl, kWave - 1);
               if (base >= N.n) break;
             }
@@ -765,14 +778,8 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
                 const uint32_t g3 = min(gap(q.w), cap);
                 const int s4 = (int)(g0 + g1 + g2 + g3);
                 const int incl = wave_incl_scan(s4);
-                int32_t p = base + incl - s4 + (int32_t)g0;
-                emit(p, inh);
-                p += (int32_t)g1;
-                emit(p, inh);
-                p += (int32_t)g2;
-                emit(p, inh);
-                p += (int32_t)g3;
-                emit(p, inh);
+                const int32_t p = base + incl - s4 + (int32_t)g0;
+                emit4(p, p + (int32_t)g1, p + (int32_t)(g1 + g2), p + (int32_t)(g1 + g2 + g3), inh);
                 base += __builtin_amdgcn_readlane(incl, kWave - 1);
                 if (base >= N.n) break;
               }
