@@ -127,10 +127,11 @@ struct NetShared {
   int fb_cnt, fb_c, acnt;
   // neuron and synapse constants of the update, read from LDS there (as
   // scalars they would crowd the scalar registers of the whole step loop)
-  float kc[12];
+  alignas(16) float kc[12];
 };
 
-enum { kcWe, kcWi, kcDe, kcDi, kcIext, kcEe, kcEi, kcA, kcVrest, kcR, kcVth, kcVreset };
+enum { kcWe, kcWi, kcDe, kcDi, kcIext, kcEe, kcEi, kcA, kcVrest, kcR, kcVth, kcVreset, kcCount };
+static_assert(kcCount == 12, "the update reads the constants as three float4");
 
 __device__ __forceinline__ uint64_t pack(uint32_t tag, uint32_t v) { return ((uint64_t)tag << 32) | v; }
 __device__ __forceinline__ uint32_t tag_of(uint64_t s) { return (uint32_t)(s >> 32); }
@@ -888,27 +889,35 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
     // launch: the common case, COBA without external current or raster, is
     // compiled with them as constants)
     auto update = [&](auto coba, auto has_iext, auto has_raster) {
+      // the constants read once per step, before the slots (read inside the
+      // slots' conditional blocks they were reloaded in every slot, five LDS
+      // round trips in sequence each)
+      const float4 c0 = reinterpret_cast<const float4*>(sh.kc)[0];
+      const float4 c1 = reinterpret_cast<const float4*>(sh.kc)[1];
+      const float4 c2 = reinterpret_cast<const float4*>(sh.kc)[2];
+      const float kWe = c0.x, kWi = c0.y, kDe = c0.z, kDi = c0.w, kIext = c1.x, kEe = c1.y, kEi = c1.z,
+                  kA = c1.w, kVrest = c2.x, kR = c2.y, kVth = c2.z, kVreset = c2.w;
 #pragma unroll
       for (int i = 0; i < kNPT; ++i) {
         const int k = i * kNetThreads + tid;
         if (k < R) {
-          const float xe = (float)ce[i] * sh.kc[kcWe];
-          const float xi = (float)ci[i] * sh.kc[kcWi];
-          ge[i] = ge[i] * sh.kc[kcDe] + xe;
-          gi[i] = gi[i] * sh.kc[kcDi] + xi;
+          const float xe = (float)ce[i] * kWe;
+          const float xi = (float)ci[i] * kWi;
+          ge[i] = ge[i] * kDe + xe;
+          gi[i] = gi[i] * kDi + xi;
           bool spk = false;
           if (ref[i] > 0) {
             ref[i] -= 1;
           } else {
-            float ix = sh.kc[kcIext];
+            float ix = kIext;
             if (has_iext) ix = ix + as_global(iext)[lo + k];
             float I;
-            if (coba) I = ge[i] * (sh.kc[kcEe] - V[i]) + gi[i] * (sh.kc[kcEi] - V[i]) + ix;
+            if (coba) I = ge[i] * (kEe - V[i]) + gi[i] * (kEi - V[i]) + ix;
             else I = ge[i] + gi[i] + ix;
-            float v = V[i] + sh.kc[kcA] * ((sh.kc[kcVrest] - V[i]) + sh.kc[kcR] * I);
-            if (v > sh.kc[kcVth]) {
+            float v = V[i] + kA * ((kVrest - V[i]) + kR * I);
+            if (v > kVth) {
               spk = true;
-              v = sh.kc[kcVreset];
+              v = kVreset;
               ref[i] = N.ref_steps;
             }
             V[i] = v;
