@@ -214,20 +214,24 @@ constexpr int kPolledTargets = 14;
 // further words a line of ce targets needs
 __device__ __forceinline__ int tline_extra(int ce) { return ce > kPolledTargets ? (ce - kPolledTargets + 1) / 2 : 0; }
 constexpr uint64_t kNoTag = 0xFFFFFFFFull << 32;  // a further word no step can take
-// Word q for c targets of which the line carries `ce` (c, or 0 if c > 30);
-// ent(i) is called for i < 30 only.
-template <class Ent>
-__device__ __forceinline__ uint64_t tline_word(uint32_t tag, int q, int c, int ce, int spikes, Ent&& ent) {
+// Word q for c targets of which the line carries `ce` (c, or 0 if c > 30),
+// from the entries x[i] = entry first(q) + i (unused ones may hold anything).
+__device__ __forceinline__ uint64_t tline_pack(uint32_t tag, int q, int c, int ce, int spikes, const uint32_t (&x)[4]) {
   const int first = tline_first(q);
   const int n = max(0, min(ce - first, q == 0 ? 2 : 4));
   uint64_t v = ((uint64_t)(tag & 15u) << 60) | ((uint64_t)n << 57);
   if (q == 0) v |= ((uint64_t)(c > kTgtLine ? 31 : c) << 52) | ((uint64_t)min(spikes, 0x1FFF) << 39);
-  uint32_t x[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) x[i] = ent(min(first + i, kTgtLine - 1));
 #pragma unroll
   for (int i = 0; i < 4; ++i) v |= (uint64_t)(x[i] & (i < n ? 0x1FFFu : 0u)) << (13 * i);
   return v;
+}
+// The same with the entries read through ent(i), called for i < 30 only.
+template <class Ent>
+__device__ __forceinline__ uint64_t tline_word(uint32_t tag, int q, int c, int ce, int spikes, Ent&& ent) {
+  uint32_t x[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) x[i] = ent(min(tline_first(q) + i, kTgtLine - 1));
+  return tline_pack(tag, q, c, ce, spikes, x);
 }
 
 // Further word q (0-based) of a line of ce targets: entries 14 + 2q, 15 + 2q.
@@ -817,11 +821,19 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
     const __amdgpu_buffer_rsrc_t rs = coh_rsrc(N.inbox, inbox_bytes(N));
     for (int x = tid; x < 2 * N.n_wg; x += kNetThreads) {
       const int d = x >> 1, h = x & 1;
+      // the half's entries read before the line's count (both LDS reads in
+      // flight together; entries past the count are masked)
+      uint32_t xa[4], xb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        xa[i] = sh.lst[d][tline_first(2 * h) + i];
+        xb[i] = sh.lst[d][tline_first(2 * h + 1) + i];
+      }
       const int c = sh.dcnt[d];
       const int ce = c > kTgtLine ? 0 : c;
       auto ent = [&](int i) { return (uint32_t)sh.lst[d][i]; };
-      const uint64_t wa = tline_word(tag, 2 * h, c, ce, total, ent);
-      const uint64_t wb = tline_word(tag, 2 * h + 1, c, ce, total, ent);
+      const uint64_t wa = tline_pack(tag, 2 * h, c, ce, total, xa);
+      const uint64_t wb = tline_pack(tag, 2 * h + 1, c, ce, total, xb);
       st_coh128(rs, line_off(N, par, d, w, h), wa, wb);
       if (h == 0) {
         const int nx = tline_extra(ce);
