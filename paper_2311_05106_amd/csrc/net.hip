@@ -429,6 +429,13 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
     sh.cnt[k] = 0u;
     sh.cnt[kRangeMax + k] = 0u;
   }
+  // one workgroup with stored rows (n <= kRangeMax): the row pointers staged
+  // in LDS for the whole launch (sh.pref serves only the several-workgroup
+  // row scan otherwise), so a firing row's bounds cost an LDS read, not a
+  // cache round trip, every step
+  static_assert(kIdBatch + 1 >= kRangeMax + 1, "row pointers of a one-workgroup net fit sh.pref");
+  if (CONN == 0 && N.n_wg == 1)
+    for (int k = tid; k <= N.n; k += kNetThreads) sh.pref[k] = as_global(N.indptr)[k];
   if (tid == 0) {
     sh.abort_flag = 0;
     sh.ocnt[0] = sh.ocnt[1] = 0;
@@ -481,7 +488,7 @@ __device__ __forceinline__ void net_body(const NetLaunch& L, const NetDev& N, in
       for (int r = wave; r < nact; r += kNetWaves) {
         const int32_t j = sh.ids[r];
         if ((uint32_t)j >= (uint32_t)N.n) continue;
-        const int32_t st = as_global(N.indptr)[j], en = as_global(N.indptr)[j + 1];
+        const int32_t st = sh.pref[j], en = sh.pref[j + 1];
         uint32_t* cnt = sh.cnt + (j < N.n_exc ? 0 : kRangeMax);
         for (int32_t e0 = st; e0 < en; e0 += 2 * kWave) {
           const int32_t ea = e0 + lane_id(), eb = ea + kWave;
